@@ -1,0 +1,48 @@
+// pw_internal.h -- layout of the per-triangulation "program" that the scheme
+// kernels walk, shared by the host builder (tri.cpp) and the kernels.
+//
+// The reflected diamond A<> (Sec. 2) is numbered row by row (y ascending,
+// then x ascending).  Every diamond edge is listed once, at its later
+// endpoint, so the kernels can process vertices in order and only ever look
+// back.  All of it is read with wave-uniform loads (scalar cache).
+//
+//   words [0, nV)                   vertex records
+//       bits  0..6   p   : lattice point (|x|,|y|) index k in A (mask bit)
+//       bit   7      g   : reflection parity [x<0]|x| + [y<0]|y| mod 2,
+//                          so sign(v) = bit p of the mask XOR g (eq. (signs))
+//       bits  8..15  n   : number of earlier neighbours
+//       bits 16..31  off : offset of the first earlier neighbour in the list
+//   words [nV, nV+nE)               earlier-neighbour ids (one per word)
+//   words [nV+nE, nV+nE+nP)         antipodal pairs a | b << 16, a < b
+#pragma once
+#include <cstdint>
+
+namespace pw {
+
+constexpr int kDMax = 12;
+constexpr int kVMax = 2 * kDMax * kDMax + 2 * kDMax + 1;  // 313
+constexpr int kEMax = 6 * kDMax * kDMax + 2 * kDMax;      // 888
+
+constexpr int n_points(int d) { return (d + 1) * (d + 2) / 2; }
+constexpr int n_vertices(int d) { return 2 * d * d + 2 * d + 1; }
+constexpr int n_diamond_edges(int d) { return 6 * d * d + 2 * d; }
+constexpr int harnack(int d) { return (d - 1) * (d - 2) / 2 + 1; }
+constexpr int mask_bytes(int d) { return n_points(d) <= 32 ? 4 : (n_points(d) <= 64 ? 8 : 16); }
+
+// device-side error flags (sticky, per triangulation handle)
+constexpr uint32_t kErrRegions = 1u;   // more regions than Harnack's bound
+constexpr uint32_t kErrRoot = 2u;      // no unique root
+constexpr uint32_t kErrTree = 4u;      // adjacency graph is not a tree
+constexpr uint32_t kErrSelfLoop = 8u;  // self-loop for even d
+
+struct HostProgram {
+  int d = 0, nA = 0, nV = 0, nE = 0, nP = 0;
+  std::uint32_t words[kVMax + kEMax + 2 * kDMax];
+  int n_words = 0;
+};
+
+// Validates the edge list and fills `prog`.  Returns 0 or a negative
+// pw_status, with a message in `err`.
+int build_program(int d, const int16_t* edges_ij, int n_edges, HostProgram* prog, char* err, int errlen);
+
+}  // namespace pw

@@ -1,0 +1,209 @@
+"""Python binding of libpatchwork.so (ctypes; argument marshalling only).
+
+Every computation runs in the library's HIP kernels.  PyTorch provides the
+device buffers and the current stream; this module only passes pointers and
+sizes through the C-ABI declared in ``include/patchwork.h``.  There is no
+fallback: if the library is missing or a call fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpatchwork.so")
+
+PW_OK = 0
+PW_ERR_ARG = -1
+PW_ERR_TRI = -2
+PW_ERR_HIP = -3
+PW_ERR_RANGE = -4
+PW_ERR_HIST_FULL = -5
+PW_ERR_INTERNAL = -6
+
+J_BIT = 1 << 127
+
+_lib = None
+
+
+class PatchworkError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"patchwork error {status}: {msg}")
+        self.status = status
+
+
+def lib():
+    """Load libpatchwork.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    L.pw_last_error.restype = ctypes.c_char_p
+    L.pw_version.restype = i32
+    L.pw_mask_bytes.argtypes = [i32]
+    L.pw_mask_bytes.restype = i32
+    L.pw_tri_create.argtypes = [i32, ctypes.POINTER(ctypes.c_int16), i32, ctypes.POINTER(vp)]
+    L.pw_tri_destroy.argtypes = [vp]
+    L.pw_tri_info.argtypes = [vp, i32p, i32p, i32p, i32p, i32p]
+    L.pw_tri_errors.argtypes = [vp, u32p]
+    L.patchwork_scheme_batch.argtypes = [vp, vp, i64, vp, vp]
+    L.pw_hist_create.argtypes = [i32, ctypes.POINTER(vp)]
+    L.pw_hist_reset.argtypes = [vp, vp]
+    L.pw_hist_read.argtypes = [vp, u64p, u64p, u64p, i32, i32p]
+    L.pw_hist_destroy.argtypes = [vp]
+    L.patchwork_scheme_histogram.argtypes = [vp, vp, i64, u64, vp, vp]
+    L.patchwork_scheme_enumerate_range.argtypes = [vp, u64, u64, u64p, vp, vp]
+    for name in ("pw_tri_create", "pw_tri_destroy", "pw_tri_info", "pw_tri_errors", "patchwork_scheme_batch",
+                 "pw_hist_create", "pw_hist_reset", "pw_hist_read", "pw_hist_destroy",
+                 "patchwork_scheme_histogram", "patchwork_scheme_enumerate_range"):
+        getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def check(status):
+    if status != PW_OK:
+        raise PatchworkError(status, lib().pw_last_error().decode())
+
+
+def mask_bytes(d: int) -> int:
+    n = lib().pw_mask_bytes(d)
+    if n < 0:
+        raise PatchworkError(n, "degree out of range")
+    return n
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def mask_tensor(masks2: np.ndarray, d: int, device="cuda"):
+    """Host (n,2) uint64 masks -> a device tensor in the library's mask
+    layout for degree d (int32 / int64 / int64 pairs)."""
+    import torch
+
+    nb = mask_bytes(d)
+    m = np.ascontiguousarray(masks2, dtype=np.uint64).reshape(-1, 2)
+    if nb == 4:
+        host = m[:, 0].astype(np.uint32).view(np.int32)
+    elif nb == 8:
+        host = m[:, 0].view(np.int64)
+    else:
+        host = m.view(np.int64).reshape(-1)
+    return torch.from_numpy(np.ascontiguousarray(host)).to(device)
+
+
+def codes_to_ints(codes) -> list:
+    """(n,2) int64 tensor/array of (lo, hi) words -> Python ints."""
+    a = codes.cpu().numpy() if hasattr(codes, "cpu") else np.asarray(codes)
+    a = a.view(np.uint64).reshape(-1, 2)
+    return [int(lo) | (int(hi) << 64) for lo, hi in a]
+
+
+class Triangulation:
+    """A validated triangulation handle (pw_tri_create)."""
+
+    def __init__(self, d: int, edges):
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.int16).reshape(-1, 4))
+        h = ctypes.c_void_p()
+        check(lib().pw_tri_create(int(d), e.ctypes.data_as(ctypes.POINTER(ctypes.c_int16)), len(e),
+                                  ctypes.byref(h)))
+        self.handle = h
+        self.d = int(d)
+
+    def close(self):
+        if self.handle:
+            lib().pw_tri_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        v = [ctypes.c_int32() for _ in range(5)]
+        check(lib().pw_tri_info(self.handle, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("d", "n_points", "n_vertices", "n_diamond_edges", "n_antipodal_pairs"),
+                        (x.value for x in v)))
+
+    def errors(self) -> int:
+        f = ctypes.c_uint32()
+        check(lib().pw_tri_errors(self.handle, ctypes.byref(f)))
+        return f.value
+
+    def batch(self, masks, codes=None, stream=None):
+        """Scheme codes of device masks -> (n,2) int64 device tensor."""
+        import torch
+
+        n = masks.numel() * masks.element_size() // mask_bytes(self.d)
+        if codes is None:
+            codes = torch.empty((n, 2), dtype=torch.int64, device=masks.device)
+        check(lib().patchwork_scheme_batch(self.handle, _ptr(masks), n, _ptr(codes), _stream(stream)))
+        return codes
+
+    def histogram(self, masks, hist: "Histogram", index_base: int = 0, stream=None):
+        n = masks.numel() * masks.element_size() // mask_bytes(self.d)
+        check(lib().patchwork_scheme_histogram(self.handle, _ptr(masks), n, int(index_base), hist.handle,
+                                               _stream(stream)))
+
+    def enumerate_range(self, first: int, count: int, hist: "Histogram", fixed_zero_bits: int = 1, stream=None):
+        fz = (ctypes.c_uint64 * 2)(fixed_zero_bits & 0xFFFFFFFFFFFFFFFF, fixed_zero_bits >> 64)
+        check(lib().patchwork_scheme_enumerate_range(self.handle, int(first), int(count), fz, hist.handle,
+                                                     _stream(stream)))
+
+
+class Histogram:
+    """Device histogram code -> (count, witness) (pw_hist_create)."""
+
+    def __init__(self, capacity: int = 4096):
+        h = ctypes.c_void_p()
+        check(lib().pw_hist_create(int(capacity), ctypes.byref(h)))
+        self.handle = h
+        self.capacity = int(capacity)
+
+    def close(self):
+        if self.handle:
+            lib().pw_hist_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reset(self, stream=None):
+        check(lib().pw_hist_reset(self.handle, _stream(stream)))
+
+    def read(self):
+        """{code: (count, witness)} sorted by code (synchronises)."""
+        cap = self.capacity
+        codes = np.zeros((cap, 2), dtype=np.uint64)
+        counts = np.zeros(cap, dtype=np.uint64)
+        wit = np.zeros(cap, dtype=np.uint64)
+        n = ctypes.c_int32()
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        check(lib().pw_hist_read(self.handle, codes.ctypes.data_as(u64p), counts.ctypes.data_as(u64p),
+                                 wit.ctypes.data_as(u64p), cap, ctypes.byref(n)))
+        out = {}
+        for k in range(n.value):
+            out[int(codes[k, 0]) | (int(codes[k, 1]) << 64)] = (int(counts[k]), int(wit[k]))
+        return out
