@@ -448,12 +448,18 @@ __device__ __forceinline__ uint32_t hash_code(uint64_t lo, uint64_t hi) {
   return (uint32_t)(z ^ (z >> 32));
 }
 
-// Insert (lo,hi) += k, witness min.  Lock-free; a slot still being filled
-// by another lane is skipped, which can leave duplicate keys that
-// pw_hist_read merges.
+// Insert (lo,hi) += k, witness min.  A slot goes 0 -> 1 (claimed by one
+// lane's CAS) -> 2 (key, count and witness written, released).  A lane that
+// meets a slot in state 1 re-reads it until the claiming lane has
+// published it (a handful of stores, so the wait is short); after
+// kClaimWait reads it moves on instead, which can only leave a duplicate
+// key that pw_hist_read merges.
+constexpr int kClaimWait = 1 << 16;
+
 __device__ void global_insert(const HistDev& h, uint64_t lo, uint64_t hi, uint64_t k, uint64_t w) {
   uint32_t s = hash_code(lo, hi) & h.cap_mask;
-  for (uint32_t probe = 0; probe <= h.cap_mask; ++probe, s = (s + 1) & h.cap_mask) {
+  int waited = 0;
+  for (uint32_t probe = 0; probe <= h.cap_mask;) {
     uint32_t st = __hip_atomic_load(&h.state[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
     if (st == 0) {
       uint32_t expected = 0;
@@ -468,11 +474,15 @@ __device__ void global_insert(const HistDev& h, uint64_t lo, uint64_t hi, uint64
       }
       st = expected;
     }
+    if (st == 1 && ++waited < kClaimWait) continue;  // same slot again
     if (st == 2 && h.key[2 * s] == lo && h.key[2 * s + 1] == hi) {
       atomicAdd(reinterpret_cast<unsigned long long*>(&h.cnt[s]), (unsigned long long)k);
       atomicMin(reinterpret_cast<unsigned long long*>(&h.wit[s]), (unsigned long long)w);
       return;
     }
+    waited = 0;
+    ++probe;
+    s = (s + 1) & h.cap_mask;
   }
   atomicOr(h.overflow, 1u);
 }
@@ -680,11 +690,15 @@ int cu_count() {
   return n;
 }
 
+// Enough blocks to fill every CU once (the LDS footprint bounds how many
+// blocks a CU holds); each wave then loops over many batches.
 template <int D>
 int blocks_for(int64_t units_per_block, int64_t n) {
-  int64_t need = (n + units_per_block - 1) / units_per_block;
-  int64_t cap = (int64_t)cu_count() * 16;
-  return (int)std::max<int64_t>(1, std::min(need, cap));
+  using C = Cfg<D>;
+  const int64_t lds = (int64_t)C::LANE_WORDS * 4 * 64 * C::WAVES;
+  const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(8, (160 * 1024) / lds));
+  const int64_t need = (n + units_per_block - 1) / units_per_block;
+  return (int)std::max<int64_t>(1, std::min(need, (int64_t)cu_count() * per_cu));
 }
 
 template <int D>
