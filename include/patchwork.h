@@ -156,6 +156,34 @@ pw_status patchwork_scheme_enumerate_range(pw_tri_t tri, uint64_t first, uint64_
                                            const uint64_t fixed_zero_bits[2], pw_hist_t hist,
                                            hipStream_t stream);
 
+/*
+ * Many triangulations of uneven degree in one persistent launch (Sec. 3:
+ * the second search mode sweeps many triangulations; kernel dispatch and
+ * histogram aggregation are the costs at scale).
+ *   tris      n_tris handles (host array), any mix of degrees.
+ *   d_masks   one array of 128-bit masks (two uint64 per mask, whatever the
+ *             degree); triangulation t owns masks [offsets[t], offsets[t+1]).
+ *   offsets   host array of n_tris + 1 non-decreasing indices.
+ *   hists     host array of n_tris histogram handles, or NULL; the witness
+ *             of a code is its smallest global mask index.
+ *   d_codes   NULL, or n x 2 uint64 codes written at the masks' positions.
+ *   cfg       NULL for the defaults, or the tuned launch shape: masks per
+ *             work item, waves per block, blocks per CU (0 = as many as the
+ *             LDS of the largest degree allows).
+ * Work items (chunks of one triangulation's masks) are taken from an atomic
+ * queue in decreasing order of cost.  The call returns after the launch has
+ * finished (its device tables are reused by the next call).
+ */
+typedef struct {
+  int32_t chunk;
+  int32_t waves_per_block;
+  int32_t blocks_per_cu;
+} pw_multi_config;
+
+pw_status patchwork_scheme_batch_multi(const pw_tri_t *tris, int32_t n_tris, const void *d_masks,
+                                       const int64_t *offsets, const pw_hist_t *hists, uint64_t *d_codes,
+                                       const pw_multi_config *cfg, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,411 @@
+// mlp.hip -- kernels of the learned sign-distribution proposal: a small MLP
+// (inputs = the +-1 signs of one mask, outputs = logits of scheme features)
+// trained on masks labelled by the exact scheme kernels, then used to rank
+// mutated candidate masks before the exact kernels judge them.
+//
+// Dense products use gfx950 matrix cores (v_mfma_f32_16x16x16_bf16: BF16
+// operands, FP32 accumulation).  Everything else is elementwise or a small
+// reduction on the vector units.  bfloat16 values are kept as uint16_t bit
+// patterns; conversion rounds to nearest-even from the IEEE-754 binary32
+// layout (the upper 16 bits of a float are a bfloat16).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "patchwork.h"
+#include "pw_host.h"
+
+namespace pw {
+
+typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  const uint32_t u = __float_as_uint(f);
+  const uint32_t rounding = 0x7FFFu + ((u >> 16) & 1u);  // ties to even
+  return (uint16_t)((u + rounding) >> 16);
+}
+
+// --------------------------------------------------------------------- GEMM
+//
+// C[M x N] = A[M x K] * B[K x N] with arbitrary element strides (so the
+// same kernel serves X W, dY W^T and X^T dY).  Tile 64 x 64 per block of
+// four waves, each wave owning a 32 x 32 sub-tile = 2 x 2 MFMA 16x16 tiles;
+// K advances 32 at a time through LDS.
+//
+// MFMA 16x16x16 operand layout (wave of 64 lanes, l = lane):
+//   A: lane l holds A[l % 16][4 (l / 16) + 0..3]
+//   B: lane l holds B[4 (l / 16) + 0..3][l % 16]
+//   C: lane l holds C[4 (l / 16) + 0..3][l % 16]
+// Epilogue per element: + bias[n], ReLU, times [gate > 0], stored as fp32
+// and/or bf16.
+
+constexpr int TBM = 64, TBN = 64, TBK = 32;
+
+struct GemmArgs {
+  const uint16_t* A;
+  int64_t a_m, a_k;
+  const uint16_t* B;
+  int64_t b_k, b_n;
+  int M, N, K;
+  const float* bias;     // N or null
+  const uint16_t* gate;  // M x N (ld g_m) or null: multiply by [gate > 0]
+  int64_t g_m;
+  int relu;
+  float* C32;  // or null
+  uint16_t* C16;  // or null
+  int64_t c_m;
+  int accumulate;  // C32 += result
+};
+
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
+  __shared__ uint16_t As[TBM][TBK + 4];  // [m][k]
+  __shared__ uint16_t Bs[TBN][TBK + 4];  // [n][k] (transposed for k-contiguous fragments)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.y * TBM, n0 = blockIdx.x * TBN;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  float4_t acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = float4_t{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < g.K; k0 += TBK) {
+    // stage A and B tiles: 64 x 32 elements each, 8 per thread
+    for (int e = tid; e < TBM * TBK; e += 256) {
+      const int r = e / TBK, c = e % TBK;
+      As[r][c] = g.A[(int64_t)(m0 + r) * g.a_m + (int64_t)(k0 + c) * g.a_k];
+      Bs[r][c] = g.B[(int64_t)(k0 + c) * g.b_k + (int64_t)(n0 + r) * g.b_n];
+    }
+    __syncthreads();
+    for (int ks = 0; ks < TBK; ks += 16) {
+      const int kk = ks + 4 * (lane >> 4);
+      short4_t af[2], bf[2];
+      for (int a = 0; a < 2; ++a) {
+        const uint16_t* p = &As[wm + 16 * a + (lane & 15)][kk];
+        af[a] = short4_t{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
+      }
+      for (int b = 0; b < 2; ++b) {
+        const uint16_t* p = &Bs[wn + 16 * b + (lane & 15)][kk];
+        bf[b] = short4_t{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
+      }
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[a], bf[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + 16 * a + 4 * (lane >> 4) + r;
+        const int n = n0 + wn + 16 * b + (lane & 15);
+        float v = acc[a][b][r];
+        if (g.bias) v += g.bias[n];
+        if (g.relu) v = v > 0.f ? v : 0.f;
+        if (g.gate && !(bf16_to_f32(g.gate[(int64_t)m * g.g_m + n]) > 0.f)) v = 0.f;
+        if (g.C32) {
+          float* o = &g.C32[(int64_t)m * g.c_m + n];
+          *o = g.accumulate ? *o + v : v;
+        }
+        if (g.C16) g.C16[(int64_t)m * g.c_m + n] = f32_to_bf16(v);
+      }
+}
+
+// ------------------------------------------------------------- elementwise
+
+// X[k][j] = +1 if bit j of mask k is 0 ('+'), -1 if it is 1, for j < n_bits;
+// 0 for the padding columns n_bits <= j < width.
+__global__ void k_encode(const uint64_t* __restrict__ masks, int64_t n, int n_bits, int width,
+                         uint16_t* __restrict__ X) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * width) return;
+  const int64_t k = e / width;
+  const int j = (int)(e % width);
+  float v = 0.f;
+  if (j < n_bits) v = ((masks[2 * k + (j >> 6)] >> (j & 63)) & 1) ? -1.f : 1.f;
+  X[e] = f32_to_bf16(v);
+}
+
+// Feature classes of a scheme code (targets of the six softmax heads):
+//   0: number of ovals, clamped to 22          (23 classes, logits 0..22)
+//   1: deepest nesting level, clamped to 4     (5 classes,  logits 23..27)
+//   2..5: number of ovals at depth 1..4, in buckets
+//         0,1,2,3,4,5-6,7-9,10-14,15+          (9 classes each, logits 28..63)
+// The depth of an oval is the running balance of the code word at its '1'
+// (outermost = 1).
+__device__ __forceinline__ int bucket9(int c) {
+  return c <= 4 ? c : (c <= 6 ? 5 : (c <= 9 ? 6 : (c <= 14 ? 7 : 8)));
+}
+
+__global__ void k_features(const uint64_t* __restrict__ codes, int64_t n, int32_t* __restrict__ labels) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const uint64_t lo = codes[2 * k], hi = codes[2 * k + 1] & ~(1ull << 63);
+  const int len = hi ? 128 - __clzll((long long)hi) : 64 - __clzll((long long)lo);  // bit length of 2^|W| + W
+  const int wl = len - 1;
+  int depth = 0, maxd = 0, ovals = 0, cnt[4] = {0, 0, 0, 0};
+  for (int b = wl - 1; b >= 0; --b) {
+    const int bit = b >= 64 ? (int)((hi >> (b - 64)) & 1) : (int)((lo >> b) & 1);
+    if (bit) {
+      ++depth;
+      ++ovals;
+      maxd = depth > maxd ? depth : maxd;
+      if (depth <= 4) ++cnt[depth - 1];
+    } else {
+      --depth;
+    }
+  }
+  int32_t* o = labels + 6 * k;
+  o[0] = ovals < 22 ? ovals : 22;
+  o[1] = maxd < 4 ? maxd : 4;
+  for (int h = 0; h < 4; ++h) o[2 + h] = bucket9(cnt[h]);
+}
+
+// Softmax cross-entropy over the six heads, averaged over the batch:
+// loss += sum_h -log softmax(Y[k, head h])[label_h] / n and
+// dY[k, head h] = (softmax - onehot) / n (fp32 and bf16 copies).
+__constant__ int kHeadStart[7] = {0, 23, 28, 37, 46, 55, 64};
+
+__global__ void k_softmax_xent(const float* __restrict__ Y, const int32_t* __restrict__ labels, int64_t n,
+                               float* __restrict__ dY32, uint16_t* __restrict__ dY16, float* __restrict__ loss) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const float* y = Y + 64 * k;
+  float l = 0.f;
+  for (int h = 0; h < 6; ++h) {
+    const int s = kHeadStart[h], e = kHeadStart[h + 1];
+    float mx = -INFINITY;
+    for (int j = s; j < e; ++j) mx = fmaxf(mx, y[j]);
+    float z = 0.f;
+    for (int j = s; j < e; ++j) z += expf(y[j] - mx);
+    const int t = labels[6 * k + h];
+    l += logf(z) - (y[s + t] - mx);
+    for (int j = s; j < e; ++j) {
+      const float g = (expf(y[j] - mx) / z - (j - s == t ? 1.f : 0.f)) / (float)n;
+      if (dY32) dY32[64 * k + j] = g;
+      if (dY16) dY16[64 * k + j] = f32_to_bf16(g);
+    }
+  }
+  atomicAdd(loss, l / (float)n);
+}
+
+// out[j] = sum_k X[k][j]  (bias gradients), one thread per column
+__global__ void k_colsum(const float* __restrict__ X, int64_t n, int cols, float* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cols) return;
+  float s = 0.f;
+  for (int64_t k = 0; k < n; ++k) s += X[k * cols + j];
+  out[j] = s;
+}
+
+// Adam (Kingma & Ba, 2015) on fp32 master weights, refreshing the bf16 copy.
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float bc1,
+                       float bc2, uint16_t* __restrict__ w16) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float wi = w[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+  w[i] = wi;
+  if (w16) w16[i] = f32_to_bf16(wi);
+}
+
+// Novelty score of a candidate: sum over heads of the expected rarity of
+// its predicted class, sum_j softmax(Y)_j * rarity_j.
+__global__ void k_score(const float* __restrict__ Y, const float* __restrict__ rarity, int64_t n,
+                        float* __restrict__ score) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const float* y = Y + 64 * k;
+  float s = 0.f;
+  for (int h = 0; h < 6; ++h) {
+    const int a = kHeadStart[h], e = kHeadStart[h + 1];
+    float mx = -INFINITY;
+    for (int j = a; j < e; ++j) mx = fmaxf(mx, y[j]);
+    float z = 0.f, acc = 0.f;
+    for (int j = a; j < e; ++j) {
+      const float p = expf(y[j] - mx);
+      z += p;
+      acc += p * rarity[j];
+    }
+    s += acc / z;
+  }
+  score[k] = s;
+}
+
+// SplitMix64 finaliser as a counter-based generator: out(key) depends only
+// on key (Steele, Lea, Flood 2014).
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Candidate k = parent[k % n_parents] with `flips` random bits in
+// [1, n_bits) toggled (bit 0, sigma(0,0), stays '+').
+__global__ void k_mutate(const uint64_t* __restrict__ parents, int64_t n_parents, int64_t n, int n_bits, int flips,
+                         uint64_t seed, uint64_t* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int64_t p = k % n_parents;
+  uint64_t lo = parents[2 * p], hi = parents[2 * p + 1];
+  for (int f = 0; f < flips; ++f) {
+    const uint64_t r = mix64(seed ^ mix64((uint64_t)k * 0x100000001B3ull + (uint64_t)f));
+    const int b = 1 + (int)(r % (uint64_t)(n_bits - 1));
+    if (b < 64)
+      lo ^= 1ull << b;
+    else
+      hi ^= 1ull << (b - 64);
+  }
+  out[2 * k] = lo;
+  out[2 * k + 1] = hi;
+}
+
+// Uniform masks: word w of mask k is SplitMix64 output 2k + w of the stream
+// started at `seed` (state seed + (i+1) * golden gamma), bits >= n_bits and
+// bit 0 (sigma(0,0) = '+') cleared.
+__global__ void k_random_masks(uint64_t seed, uint64_t offset, int64_t n, int n_bits, uint64_t* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const uint64_t i = 2 * (offset + (uint64_t)k);
+  uint64_t lo = mix64(seed + i * 0x9E3779B97F4A7C15ull);
+  uint64_t hi = mix64(seed + (i + 1) * 0x9E3779B97F4A7C15ull);
+  if (n_bits < 64) lo &= (1ull << n_bits) - 1;
+  hi = n_bits <= 64 ? 0 : (n_bits < 128 ? hi & ((1ull << (n_bits - 64)) - 1) : hi);
+  out[2 * k] = lo & ~1ull;
+  out[2 * k + 1] = hi;
+}
+
+// Keep the candidates scoring above `threshold`, in any order, up to cap.
+__global__ void k_select(const float* __restrict__ score, const uint64_t* __restrict__ cand, int64_t n,
+                         float threshold, uint64_t* __restrict__ out, int64_t cap,
+                         unsigned long long* __restrict__ count) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n || !(score[k] > threshold)) return;
+  const unsigned long long slot = atomicAdd(count, 1ull);
+  if ((int64_t)slot < cap) {
+    out[2 * slot] = cand[2 * k];
+    out[2 * slot + 1] = cand[2 * k + 1];
+  }
+}
+
+__global__ void k_to_bf16(const float* __restrict__ x, int64_t n, uint16_t* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = f32_to_bf16(x[i]);
+}
+
+int grid1d(int64_t n, int threads) { return (int)((n + threads - 1) / threads); }
+
+}  // namespace pw
+
+using namespace pw;
+
+extern "C" {
+
+pw_status pw_mlp_gemm(const uint16_t* A, int64_t a_m, int64_t a_k, const uint16_t* B, int64_t b_k, int64_t b_n,
+                      int32_t M, int32_t N, int32_t K, const float* bias, const uint16_t* gate, int64_t g_m,
+                      int32_t relu, float* C32, uint16_t* C16, int64_t c_m, int32_t accumulate, hipStream_t s) {
+  if (!A || !B || (!C32 && !C16)) return set_err(PW_ERR_ARG, "null operand");
+  if (M <= 0 || N <= 0 || K <= 0 || M % TBM || N % TBN || K % TBK)
+    return set_err(PW_ERR_ARG, "gemm sizes must be positive multiples of 64 (M, N) and 32 (K): %d %d %d", M, N, K);
+  if (accumulate && !C32) return set_err(PW_ERR_ARG, "accumulate needs the fp32 output");
+  GemmArgs g{A, a_m, a_k, B, b_k, b_n, M, N, K, bias, gate, g_m, relu, C32, C16, c_m, accumulate};
+  hipLaunchKernelGGL(k_gemm_bf16, dim3(N / TBN, M / TBM), dim3(256), 0, s, g);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
+pw_status pw_mlp_encode(const uint64_t* masks, int64_t n, int32_t n_bits, int32_t width, uint16_t* X,
+                        hipStream_t s) {
+  if (n < 0 || n_bits < 1 || n_bits > 128 || width < n_bits) return set_err(PW_ERR_ARG, "bad encode sizes");
+  if (n == 0) return PW_OK;
+  if (!masks || !X) return set_err(PW_ERR_ARG, "null buffer");
+  hipLaunchKernelGGL(k_encode, dim3(grid1d(n * width, 256)), dim3(256), 0, s, masks, n, n_bits, width, X);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
+pw_status pw_features(const uint64_t* codes, int64_t n, int32_t* labels, hipStream_t s) {
+  if (n < 0) return set_err(PW_ERR_ARG, "negative count");
+  if (n == 0) return PW_OK;
+  if (!codes || !labels) return set_err(PW_ERR_ARG, "null buffer");
+  hipLaunchKernelGGL(k_features, dim3(grid1d(n, 256)), dim3(256), 0, s, codes, n, labels);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
+pw_status pw_mlp_softmax_xent(const float* Y, const int32_t* labels, int64_t n, float* dY32, uint16_t* dY16,
+                              float* loss, hipStream_t s) {
+  if (n <= 0 || !Y || !labels || !loss) return set_err(PW_ERR_ARG, "bad loss arguments");
+  hipLaunchKernelGGL(k_softmax_xent, dim3(grid1d(n, 256)), dim3(256), 0, s, Y, labels, n, dY32, dY16, loss);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
+pw_status pw_mlp_colsum(const float* X, int64_t n, int32_t cols, float* out, hipStream_t s) {
+  if (n < 0 || cols <= 0 || !X || !out) return set_err(PW_ERR_ARG, "bad colsum arguments");
+  hipLaunchKernelGGL(k_colsum, dim3(grid1d(cols, 64)), dim3(64), 0, s, X, n, cols, out);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
+pw_status pw_mlp_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float beta1, float beta2,
+                      float eps, int32_t step, uint16_t* w16, hipStream_t s) {
+  if (n <= 0 || step < 1 || !w || !g || !m || !v) return set_err(PW_ERR_ARG, "bad adam arguments");
+  const float bc1 = 1.f - std::pow(beta1, (float)step), bc2 = 1.f - std::pow(beta2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3(grid1d(n, 256)), dim3(256), 0, s, w, g, m, v, n, lr, beta1, beta2, eps, bc1, bc2,
+                     w16);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
+pw_status pw_to_bf16(const float* x, int64_t n, uint16_t* y, hipStream_t s) {
+  if (n < 0 || !x || !y) return set_err(PW_ERR_ARG, "bad conversion arguments");
+  if (n == 0) return PW_OK;
+  hipLaunchKernelGGL(k_to_bf16, dim3(grid1d(n, 256)), dim3(256), 0, s, x, n, y);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
+pw_status pw_mlp_score(const float* Y, const float* rarity, int64_t n, float* score, hipStream_t s) {
+  if (n < 0 || !Y || !rarity || !score) return set_err(PW_ERR_ARG, "bad score arguments");
+  if (n == 0) return PW_OK;
+  hipLaunchKernelGGL(k_score, dim3(grid1d(n, 256)), dim3(256), 0, s, Y, rarity, n, score);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
+pw_status pw_mutate(const uint64_t* parents, int64_t n_parents, int64_t n, int32_t n_bits, int32_t flips,
+                    uint64_t seed, uint64_t* out, hipStream_t s) {
+  if (n < 0 || n_parents <= 0 || n_bits < 2 || n_bits > 128 || flips < 0 || !parents || !out)
+    return set_err(PW_ERR_ARG, "bad mutate arguments");
+  if (n == 0) return PW_OK;
+  hipLaunchKernelGGL(k_mutate, dim3(grid1d(n, 256)), dim3(256), 0, s, parents, n_parents, n, n_bits, flips, seed,
+                     out);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
+pw_status pw_random_masks(uint64_t seed, uint64_t offset, int64_t n, int32_t n_bits, uint64_t* out, hipStream_t s) {
+  if (n < 0 || n_bits < 1 || n_bits > 128 || !out) return set_err(PW_ERR_ARG, "bad random mask arguments");
+  if (n == 0) return PW_OK;
+  hipLaunchKernelGGL(k_random_masks, dim3(grid1d(n, 256)), dim3(256), 0, s, seed, offset, n, n_bits, out);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
+pw_status pw_select(const float* score, const uint64_t* cand, int64_t n, float threshold, uint64_t* out,
+                    int64_t cap, unsigned long long* count, hipStream_t s) {
+  if (n < 0 || cap < 0 || !score || !cand || !out || !count) return set_err(PW_ERR_ARG, "bad select arguments");
+  if (n == 0) return PW_OK;
+  hipLaunchKernelGGL(k_select, dim3(grid1d(n, 256)), dim3(256), 0, s, score, cand, n, threshold, out, cap, count);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,224 @@
+// multi.hip -- one persistent launch over many triangulations of uneven
+// degree (Sec. 3: the second search mode checks many triangulations against
+// sign distributions; the paper names kernel dispatch and histogram
+// aggregation as the costs at scale).
+//
+// The host cuts every triangulation's mask list into chunks, orders the
+// chunks by decreasing cost (chunk length x |E(T<>)|, longest processing
+// time first) and uploads them.  Resident waves take chunks from an atomic
+// ticket counter until none is left; each chunk is evaluated with the
+// degree-specialised Eval<D> and aggregated in the wave's register table,
+// which is flushed to that triangulation's histogram when the chunk ends.
+// The ticket counter only grows, so no launch ever has to reset it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "patchwork.h"
+#include "pw_device.h"
+#include "pw_host.h"
+
+namespace pw {
+
+struct TriDesc {
+  const uint32_t* prog;
+  uint32_t* err;
+  HistDev hist;
+  int32_t d;
+  int32_t use_hist;
+};
+
+struct Item {
+  int32_t tri;
+  int32_t pad;
+  int64_t begin;  // first mask (global index into the mask array)
+  int64_t count;
+};
+
+template <int D>
+__device__ __forceinline__ void run_item(const TriDesc& t, const Item& w, const uint64_t* __restrict__ masks,
+                                         uint64_t* __restrict__ codes, const Lane& L, int lane) {
+  using C = Cfg<D>;
+  uint32_t errs = 0;
+  WaveTable tab;
+  tab.clear();
+  for (int64_t base = 0; base < w.count; base += 64) {
+    const int64_t i = w.begin + base + lane;
+    const bool valid = base + lane < w.count;
+    typename C::Mask m = 0;
+    if (valid) {
+      if constexpr (sizeof(typename C::Mask) == 8) {
+        m = masks[2 * i];
+      } else {
+        m = ((u128)masks[2 * i + 1] << 64) | (u128)masks[2 * i];
+      }
+    }
+    const u128 code = Eval<D>::run(t.prog, m, L, errs);
+    if (codes && valid) {
+      codes[2 * i] = (uint64_t)code;
+      codes[2 * i + 1] = (uint64_t)(code >> 64);
+    }
+    if (t.use_hist) tab.add_batch((uint64_t)code, (uint64_t)(code >> 64), valid, (uint64_t)i, lane, t.hist);
+  }
+  if (t.use_hist) tab.flush(t.hist);
+  if (errs) atomicOr(t.err, errs);
+}
+
+__global__ __launch_bounds__(256) void k_multi(const TriDesc* __restrict__ tris, const Item* __restrict__ items,
+                                               int64_t n_items, unsigned long long* __restrict__ ticket,
+                                               unsigned long long base, const uint64_t* __restrict__ masks,
+                                               uint64_t* __restrict__ codes, int lane_words) {
+  extern __shared__ uint32_t smem[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const Lane L{smem + wave * lane_words * 64 + lane};
+  while (true) {
+    unsigned long long tk = 0;
+    if (lane == 0) tk = atomicAdd(ticket, 1ull);
+    tk = (unsigned long long)__builtin_amdgcn_readfirstlane((int)(uint32_t)tk) |
+         ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(tk >> 32)) << 32);
+    const int64_t it = (int64_t)(tk - base);
+    if (it >= n_items) break;
+    const Item w = items[it];
+    const TriDesc t = tris[w.tri];
+    switch (t.d) {
+      case 1: run_item<1>(t, w, masks, codes, L, lane); break;
+      case 2: run_item<2>(t, w, masks, codes, L, lane); break;
+      case 3: run_item<3>(t, w, masks, codes, L, lane); break;
+      case 4: run_item<4>(t, w, masks, codes, L, lane); break;
+      case 5: run_item<5>(t, w, masks, codes, L, lane); break;
+      case 6: run_item<6>(t, w, masks, codes, L, lane); break;
+      case 7: run_item<7>(t, w, masks, codes, L, lane); break;
+      case 8: run_item<8>(t, w, masks, codes, L, lane); break;
+      case 9: run_item<9>(t, w, masks, codes, L, lane); break;
+      case 10: run_item<10>(t, w, masks, codes, L, lane); break;
+      case 11: run_item<11>(t, w, masks, codes, L, lane); break;
+      case 12: run_item<12>(t, w, masks, codes, L, lane); break;
+      default: break;
+    }
+  }
+}
+
+int lane_words_for(int d) {
+  switch (d) {
+    case 1: return Cfg<1>::LANE_WORDS;
+    case 2: return Cfg<2>::LANE_WORDS;
+    case 3: return Cfg<3>::LANE_WORDS;
+    case 4: return Cfg<4>::LANE_WORDS;
+    case 5: return Cfg<5>::LANE_WORDS;
+    case 6: return Cfg<6>::LANE_WORDS;
+    case 7: return Cfg<7>::LANE_WORDS;
+    case 8: return Cfg<8>::LANE_WORDS;
+    case 9: return Cfg<9>::LANE_WORDS;
+    case 10: return Cfg<10>::LANE_WORDS;
+    case 11: return Cfg<11>::LANE_WORDS;
+    case 12: return Cfg<12>::LANE_WORDS;
+    default: return 0;
+  }
+}
+
+// Device buffers reused across calls (grown on demand, freed at exit).
+struct MultiScratch {
+  std::mutex mu;
+  TriDesc* d_tris = nullptr;
+  size_t tri_cap = 0;
+  Item* d_items = nullptr;
+  size_t item_cap = 0;
+  unsigned long long* d_ticket = nullptr;
+  unsigned long long issued = 0;  // tickets handed out by earlier launches
+};
+
+MultiScratch& scratch_for_multi() {
+  static MultiScratch s;
+  return s;
+}
+
+}  // namespace pw
+
+using namespace pw;
+
+extern "C" pw_status patchwork_scheme_batch_multi(const pw_tri_t* tris, int32_t n_tris, const void* d_masks,
+                                                  const int64_t* offsets, const pw_hist_t* hists,
+                                                  uint64_t* d_codes, const pw_multi_config* cfg,
+                                                  hipStream_t stream) {
+  if (!tris || n_tris < 0 || !offsets) return set_err(PW_ERR_ARG, "null or negative argument");
+  if (n_tris == 0) return PW_OK;
+  if (!hists && !d_codes) return set_err(PW_ERR_ARG, "need histograms, codes or both");
+  pw_multi_config c = {4096, 1, 0};
+  if (cfg) c = *cfg;
+  if (c.chunk < 64 || c.chunk > (1 << 24) || c.waves_per_block < 1 || c.waves_per_block > 4 ||
+      c.blocks_per_cu < 0 || c.blocks_per_cu > 32)
+    return set_err(PW_ERR_ARG, "bad multi config (chunk %d, waves %d, blocks/CU %d)", c.chunk, c.waves_per_block,
+                   c.blocks_per_cu);
+  std::vector<TriDesc> desc(n_tris);
+  std::vector<Item> items;
+  int max_words = 0;
+  for (int t = 0; t < n_tris; ++t) {
+    if (!tris[t]) return set_err(PW_ERR_ARG, "null triangulation %d", t);
+    if (offsets[t + 1] < offsets[t] || offsets[t] < 0) return set_err(PW_ERR_ARG, "offsets must not decrease");
+    if (hists && !hists[t]) return set_err(PW_ERR_ARG, "null histogram %d", t);
+    const int d = tris[t]->prog.d;
+    desc[t].prog = tris[t]->d_prog;
+    desc[t].err = tris[t]->d_err;
+    desc[t].hist = hists ? hists[t]->dev() : HistDev{};
+    desc[t].d = d;
+    desc[t].use_hist = hists ? 1 : 0;
+    max_words = std::max(max_words, lane_words_for(d));
+    for (int64_t b = offsets[t]; b < offsets[t + 1]; b += c.chunk)
+      items.push_back(Item{t, 0, b, std::min<int64_t>(c.chunk, offsets[t + 1] - b)});
+  }
+  if (items.empty()) return PW_OK;
+  if (!d_masks) return set_err(PW_ERR_ARG, "null mask buffer");
+  // longest processing time first: cost ~ chunk length x diamond edges
+  std::stable_sort(items.begin(), items.end(), [&](const Item& a, const Item& b) {
+    const int64_t ca = a.count * n_diamond_edges(desc[a.tri].d), cb = b.count * n_diamond_edges(desc[b.tri].d);
+    return ca > cb;
+  });
+  MultiScratch& S = scratch_for_multi();
+  std::lock_guard<std::mutex> lock(S.mu);
+  if (S.tri_cap < desc.size()) {
+    if (S.d_tris) (void)hipFree(S.d_tris);
+    S.d_tris = nullptr;
+    PW_HIP(hipMalloc(&S.d_tris, sizeof(TriDesc) * desc.size()));
+    S.tri_cap = desc.size();
+  }
+  if (S.item_cap < items.size()) {
+    if (S.d_items) (void)hipFree(S.d_items);
+    S.d_items = nullptr;
+    PW_HIP(hipMalloc(&S.d_items, sizeof(Item) * items.size()));
+    S.item_cap = items.size();
+  }
+  if (!S.d_ticket) {
+    PW_HIP(hipMalloc(&S.d_ticket, sizeof(unsigned long long)));
+    PW_HIP(hipMemset(S.d_ticket, 0, sizeof(unsigned long long)));
+    S.issued = 0;
+  }
+  // the descriptor and item tables are reused by the next call: finish the
+  // copies before returning so the host vectors may go away
+  PW_HIP(hipMemcpyAsync(S.d_tris, desc.data(), sizeof(TriDesc) * desc.size(), hipMemcpyHostToDevice, stream));
+  PW_HIP(hipMemcpyAsync(S.d_items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice, stream));
+  const int threads = 64 * c.waves_per_block;
+  const size_t lds = (size_t)max_words * 4 * 64 * c.waves_per_block;
+  if (lds > 160 * 1024) return set_err(PW_ERR_ARG, "block needs %zu bytes of LDS", lds);
+  static std::once_flag once;
+  std::call_once(once, [] {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_multi), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+  });
+  int per_cu = (int)((160 * 1024) / lds);
+  if (c.blocks_per_cu > 0) per_cu = std::min(per_cu, c.blocks_per_cu);
+  per_cu = std::max(1, std::min(per_cu, 32 / c.waves_per_block));
+  const int64_t blocks = std::min<int64_t>((int64_t)cu_count() * per_cu, (int64_t)items.size());
+  const unsigned long long base = S.issued;
+  // every block takes one ticket past the end before it stops
+  S.issued += items.size() + (unsigned long long)blocks * c.waves_per_block;
+  hipLaunchKernelGGL(k_multi, dim3((unsigned)blocks), dim3(threads), lds, stream, S.d_tris, S.d_items,
+                     (int64_t)items.size(), S.d_ticket, base, static_cast<const uint64_t*>(d_masks), d_codes,
+                     max_words);
+  PW_HIP(hipGetLastError());
+  PW_HIP(hipStreamSynchronize(stream));
+  return PW_OK;
+}

@@ -1,0 +1,564 @@
+// pw_device.h -- device-side building blocks shared by the scheme kernels:
+// per-degree configuration, per-lane LDS views, the evaluation of one sign
+// mask (Alg. 1 of "Fast Isotopy Computation for T-Curves", Sec. 2), the
+// in-kernel mask generator and the two-level code histogram.
+//
+// LDS layout: each wave owns LANE_WORDS * 64 dwords; word k of lane l sits
+// at index k * 64 + l, so every lane always hits its own bank whatever the
+// per-lane index (conflict-free for uniform and divergent accesses alike).
+//
+// Per mask (thread) the phases are:
+//   1 components  (Alg. 1 "compute connected components of same-sign
+//     vertices"): vertices in program order; each earlier neighbour with
+//     the same sign is unioned.  Entry of v (u16): bits 0..8 parent,
+//     bit 9 parity to parent, bit 10 odd-cycle flag (roots), bit 15 sign.
+//     Links always go from the larger root to the smaller one, so every
+//     parent index is smaller than its child's.
+//   2 regions (Alg. 1 "coarsen into regions by identifying antipodal
+//     boundary pairs"): union along the 2d pairs.  For even d the union
+//     carries parity 1 (each identification reverses orientation, proof of
+//     Thm. 2) and a same-parity closure marks an odd cycle.
+//   3 region ids and the region tree: vertices in order again; a root gets
+//     the next region id, any other vertex copies the id of its parent
+//     (already relabelled because parents are smaller).  The region tree is
+//     read off a fixed spanning tree of T<> (each vertex's first earlier
+//     neighbour): the first vertex of a region hangs below the region of its
+//     tree parent (Alg. 1 "build region adjacency graph from crossed
+//     edges", restricted to spanning-tree edges, which cross every curve
+//     component).  For odd d a crossed tree edge inside one region marks
+//     the root (the pseudo-line's region).
+//   4 re-root the tree at the root region (Alg. 1 root rule), breadth-first
+//     order, canonical code (Alg. 1 last step, AHU encoding): children codes
+//     sorted descending by their left-aligned bit strings; leaves ('10')
+//     sort last.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "pw_internal.h"
+
+namespace pw {
+
+typedef unsigned __int128 u128;
+
+// ------------------------------------------------------------------ config
+
+template <int D>
+struct Cfg {
+  static constexpr int NA = n_points(D);
+  static constexpr int NV = n_vertices(D);
+  static constexpr int NE = n_diamond_edges(D);
+  static constexpr int NP = 2 * D;
+  static constexpr int RMAX = harnack(D) + 1;  // regions = ovals + 1 <= M + 1
+  static constexpr bool EVEN = (D % 2) == 0;
+  using Mask = typename std::conditional<(NA <= 64), uint64_t, u128>::type;
+  using Adj = typename std::conditional<(RMAX <= 32), uint32_t, uint64_t>::type;
+  using Code = typename std::conditional<(D <= 9), uint64_t, u128>::type;
+  static constexpr int ADJ_W = sizeof(Adj) / 4;
+  static constexpr int CODE_W = sizeof(Code) / 4;
+  // per-lane LDS words:
+  //   [0, E_WORDS)            u16 vertex entries (phases 1-3)
+  //   [PAR_BASE, +PAR_WORDS)  u8 parent region of every region (phases 3-4)
+  // after phase 3 the entry words hold, per region: child mask (ADJ_W
+  // words), breadth-first order (byte 0 of one word) and code (CODE_W).
+  static constexpr int E_WORDS = (NV + 1) / 2;
+  static constexpr int CHILD_BASE = 0;
+  static constexpr int ORD_BASE = RMAX * ADJ_W;
+  static constexpr int CODE_BASE = ORD_BASE + RMAX;
+  static constexpr int TAIL_WORDS = CODE_BASE + RMAX * CODE_W;
+  static constexpr int LOW_WORDS = E_WORDS > TAIL_WORDS ? E_WORDS : TAIL_WORDS;
+  static constexpr int PAR_BASE = LOW_WORDS;
+  static constexpr int PAR_WORDS = (RMAX + 3) / 4;
+  static constexpr int LANE_WORDS = LOW_WORDS + PAR_WORDS;
+  static constexpr int WAVE_BYTES = LANE_WORDS * 4 * 64;
+  // waves per block: as many waves per CU as the 160 KiB of LDS allows,
+  // in blocks of at most 4 waves
+  static constexpr int WAVES_PER_CU = (160 * 1024) / WAVE_BYTES;
+  static constexpr int WAVES = WAVES_PER_CU >= 16 ? 4 : (WAVES_PER_CU >= 4 ? 2 : 1);
+};
+
+// ------------------------------------------------------------ lane memory
+
+struct Lane {
+  uint32_t* w;  // word 0 of this lane; word k at w[k * 64]
+  __device__ __forceinline__ uint32_t& word(int k) const { return w[k * 64]; }
+  __device__ __forceinline__ uint16_t& ent(int v) const {
+    return reinterpret_cast<uint16_t*>(w + (v >> 1) * 64)[v & 1];
+  }
+  __device__ __forceinline__ uint8_t& byte(int k, int b) const {
+    return reinterpret_cast<uint8_t*>(w + k * 64)[b];
+  }
+};
+
+constexpr uint32_t kParent = 0x1FFu;
+constexpr uint32_t kParity = 1u << 9;
+constexpr uint32_t kOdd = 1u << 10;
+constexpr int kSignShift = 15;
+
+template <typename T>
+__device__ __forceinline__ int clz_t(T x);
+template <>
+__device__ __forceinline__ int clz_t<uint64_t>(uint64_t x) {
+  return __clzll((long long)x);
+}
+template <>
+__device__ __forceinline__ int clz_t<u128>(u128 x) {
+  uint64_t hi = (uint64_t)(x >> 64), lo = (uint64_t)x;
+  return hi ? __clzll((long long)hi) : 64 + __clzll((long long)lo);
+}
+
+template <typename T>
+__device__ __forceinline__ int ctz_t(T x) {
+  return __builtin_ctzll((unsigned long long)x);
+}
+
+template <typename T>
+__device__ __forceinline__ int popc_t(T x) {
+  return __popcll((unsigned long long)x);
+}
+
+template <typename Code>
+__device__ __forceinline__ Code load_code(const Lane& L, int base, int x) {
+  if constexpr (sizeof(Code) == 8) {
+    return (uint64_t)L.word(base + 2 * x) | ((uint64_t)L.word(base + 2 * x + 1) << 32);
+  } else {
+    u128 r = 0;
+    for (int k = 3; k >= 0; --k) r = (r << 32) | L.word(base + 4 * x + k);
+    return r;
+  }
+}
+
+template <typename Code>
+__device__ __forceinline__ void store_code(const Lane& L, int base, int x, Code c) {
+  constexpr int W = sizeof(Code) / 4;
+  for (int k = 0; k < W; ++k) L.word(base + W * x + k) = (uint32_t)(c >> (32 * k));
+}
+
+template <typename Adj>
+__device__ __forceinline__ Adj load_adj(const Lane& L, int base, int x) {
+  if constexpr (sizeof(Adj) == 4) {
+    return L.word(base + x);
+  } else {
+    return (uint64_t)L.word(base + 2 * x) | ((uint64_t)L.word(base + 2 * x + 1) << 32);
+  }
+}
+
+template <typename Adj>
+__device__ __forceinline__ void store_adj(const Lane& L, int base, int x, Adj a) {
+  if constexpr (sizeof(Adj) == 4) {
+    L.word(base + x) = a;
+  } else {
+    L.word(base + 2 * x) = (uint32_t)a;
+    L.word(base + 2 * x + 1) = (uint32_t)(a >> 32);
+  }
+}
+
+// ------------------------------------------------------------- one mask
+
+template <int D>
+struct Eval {
+  using C = Cfg<D>;
+  using Mask = typename C::Mask;
+  using Adj = typename C::Adj;
+  using Code = typename C::Code;
+
+  __device__ static __forceinline__ uint32_t bit(Mask m, int p) { return (uint32_t)(m >> p) & 1u; }
+
+  // root of u (walk only), starting from its entry eu
+  __device__ static __forceinline__ int find(const Lane& L, int u, uint32_t eu, uint32_t& er) {
+    int r = (int)(eu & kParent);
+    er = eu;
+    if (r != u) {
+      er = L.ent(r);
+      while ((int)(er & kParent) != r) {
+        r = (int)(er & kParent);
+        er = L.ent(r);
+      }
+    }
+    return r;
+  }
+
+  // root and parity of u relative to its root
+  __device__ static __forceinline__ int find_parity(const Lane& L, int u, uint32_t& er, uint32_t& par) {
+    int r = u;
+    er = L.ent(u);
+    par = 0;
+    while ((int)(er & kParent) != r) {
+      par ^= (er & kParity) ? 1u : 0u;
+      r = (int)(er & kParent);
+      er = L.ent(r);
+    }
+    return r;
+  }
+
+  // Returns the scheme code (0 on a failed consistency check, with the
+  // reason or-ed into errs).
+  __device__ static u128 run(const uint32_t* __restrict__ prog, Mask m, const Lane& L, uint32_t& errs) {
+    const uint32_t* nbr = prog + C::NV;
+    const uint32_t* pairs = prog + C::NV + C::NE;
+
+    // ---- phase 1: components of same-sign vertices
+    for (int v = 0; v < C::NV; ++v) {
+      const uint32_t rec = prog[v];
+      const int p = rec & 0x7F;
+      const uint32_t sv = bit(m, p) ^ ((rec >> 7) & 1u);
+      const int nn = (rec >> 8) & 0xFF;
+      const int off = rec >> 16;
+      int rv = v;
+      for (int k = 0; k < nn; ++k) {
+        const int u = (int)nbr[off + k];
+        const uint32_t eu = L.ent(u);
+        if ((eu >> kSignShift) == sv) {
+          uint32_t er;
+          const int r = find(L, u, eu, er);
+          if (r != (int)(eu & kParent)) L.ent(u) = (uint16_t)((eu & ~kParent) | (uint32_t)r);
+          if (rv == v) {
+            rv = r;
+          } else if (r != rv) {
+            const int lo = r < rv ? r : rv, hi = r < rv ? rv : r;
+            L.ent(hi) = (uint16_t)((sv << kSignShift) | (uint32_t)lo);
+            rv = lo;
+          }
+        }
+      }
+      L.ent(v) = (uint16_t)((sv << kSignShift) | (uint32_t)rv);
+    }
+
+    // ---- phase 2: regions (antipodal identification)
+    for (int t = 0; t < C::NP; ++t) {
+      const uint32_t pr = pairs[t];
+      const int a = pr & 0xFFFF, b = pr >> 16;
+      uint32_t ea, eb, pa, pb;
+      const int ra = find_parity(L, a, ea, pa);
+      const int rb = find_parity(L, b, eb, pb);
+      if (ra == rb) {
+        if (C::EVEN && pa == pb) L.ent(ra) = (uint16_t)(ea | kOdd);
+      } else {
+        const bool a_lo = ra < rb;
+        const int lo = a_lo ? ra : rb, hi = a_lo ? rb : ra;
+        const uint32_t elo = a_lo ? ea : eb, ehi = a_lo ? eb : ea;
+        const uint32_t par = C::EVEN ? ((pa ^ pb ^ 1u) ? kParity : 0u) : 0u;
+        L.ent(hi) = (uint16_t)((ehi & (1u << kSignShift)) | par | (uint32_t)lo);
+        if (ehi & kOdd) L.ent(lo) = (uint16_t)(elo | kOdd);
+      }
+    }
+
+    // ---- phase 3: region ids and the region tree.  Vertices in order; a
+    // union-find root is the first vertex of its region and gets the next
+    // id.  Every vertex v > 0 has a fixed earlier neighbour t(v) (the first
+    // of its list), so these edges form a spanning tree of T<>.  Each oval
+    // separates two regions that both contain vertices, so some tree edge
+    // crosses it; in particular the tree edge into the first vertex of a
+    // region B comes from the region on the other side of an oval of B,
+    // and "parent(B) = region of t(first vertex of B)" is exactly the
+    // region adjacency tree, rooted at the region of vertex 0.  For odd d
+    // a crossed tree edge inside one region crosses the pseudo-line: that
+    // region is the root (Alg. 1).
+    int nR = 0;
+    int root = -1;
+    uint32_t err = 0;
+    for (int v = 0; v < C::NV; ++v) {
+      const uint32_t rec = prog[v];
+      const int off = rec >> 16;
+      const uint32_t ev = L.ent(v);
+      const uint32_t sv = ev >> kSignShift;
+      const int p = (int)(ev & kParent);
+      int cid;
+      if (p == v) {
+        cid = nR < C::RMAX ? nR : C::RMAX - 1;
+        err |= nR < C::RMAX ? 0u : kErrRegions;
+        ++nR;
+        if (C::EVEN && (ev & kOdd)) {
+          if (root >= 0) err |= kErrRoot;
+          root = cid;
+        }
+        const int pc = v > 0 ? (int)(L.ent((int)nbr[off]) & kParent) : 0xFF;
+        L.byte(C::PAR_BASE + (cid >> 2), cid & 3) = (uint8_t)pc;
+      } else {
+        cid = (int)(L.ent(p) & kParent);
+        if (!C::EVEN) {
+          const uint32_t et = L.ent((int)nbr[off]);
+          if ((et >> kSignShift) != sv && (int)(et & kParent) == cid) {
+            if (root >= 0 && root != cid) err |= kErrRoot;
+            root = cid;
+          }
+        }
+      }
+      L.ent(v) = (uint16_t)((sv << kSignShift) | (uint32_t)cid);
+    }
+    if (root < 0) err |= kErrRoot;
+    if (err) {
+      errs |= err;
+      return 0;
+    }
+
+    // ---- phase 4: re-root the region tree at `root`, breadth-first order,
+    // then AHU codes from the leaves up
+    {
+      int x = root, prev = 0xFF;
+      while (x != 0xFF) {
+        const int nx = L.byte(C::PAR_BASE + (x >> 2), x & 3);
+        L.byte(C::PAR_BASE + (x >> 2), x & 3) = (uint8_t)prev;
+        prev = x;
+        x = nx;
+      }
+    }
+    for (int x = 0; x < nR; ++x) store_adj<Adj>(L, C::CHILD_BASE, x, (Adj)0);
+    for (int x = 0; x < nR; ++x) {
+      const int px = L.byte(C::PAR_BASE + (x >> 2), x & 3);
+      if (px != 0xFF) store_adj<Adj>(L, C::CHILD_BASE, px, load_adj<Adj>(L, C::CHILD_BASE, px) | ((Adj)1 << x));
+    }
+    L.byte(C::ORD_BASE + 0, 0) = (uint8_t)root;
+    int tail = 1;
+    for (int head = 0; head < tail && head < C::RMAX; ++head) {
+      const int x = L.byte(C::ORD_BASE + head, 0);
+      Adj nb = load_adj<Adj>(L, C::CHILD_BASE, x);
+      while (nb) {
+        const int y = ctz_t(nb);
+        nb &= nb - 1;
+        if (tail < C::RMAX) L.byte(C::ORD_BASE + tail, 0) = (uint8_t)y;
+        ++tail;
+      }
+    }
+    if (tail != nR) {
+      errs |= kErrTree;
+      return 0;
+    }
+    Adj leaves = 0;
+    Code word = 0;
+    int wlen = 0;
+    for (int i = nR - 1; i >= 0; --i) {
+      const int x = L.byte(C::ORD_BASE + i, 0);
+      const Adj kids = load_adj<Adj>(L, C::CHILD_BASE, x);
+      if (kids == 0) {
+        leaves |= (Adj)1 << x;
+        continue;
+      }
+      Adj rest = kids & ~leaves;
+      const int nleaf = popc_t(kids & leaves);
+      Code acc = 0;
+      int len = 0;
+      while (rest) {
+        int best = -1;
+        Code bkey = 0, bcode = 0;
+        Adj t = rest;
+        while (t) {
+          const int y = ctz_t(t);
+          t &= t - 1;
+          const Code cy = load_code<Code>(L, C::CODE_BASE, y);
+          const Code ky = cy << clz_t(cy);
+          if (best < 0 || ky > bkey) {
+            best = y;
+            bkey = ky;
+            bcode = cy;
+          }
+        }
+        rest &= ~((Adj)1 << best);
+        const int lb = (int)(8 * sizeof(Code)) - clz_t(bcode);
+        acc = (acc << lb) | bcode;
+        len += lb;
+      }
+      if (nleaf) {
+        const Code pat = (~(Code)0 / 3) << 1;  // ...101010
+        acc = (acc << (2 * nleaf)) | (pat >> (8 * (int)sizeof(Code) - 2 * nleaf));
+        len += 2 * nleaf;
+      }
+      if (i > 0) {
+        store_code<Code>(L, C::CODE_BASE, x, ((Code)1 << (len + 1)) | (acc << 1));
+      } else {
+        word = acc;
+        wlen = len;
+      }
+    }
+    u128 code = ((u128)1 << wlen) | (u128)word;
+    if (!C::EVEN) code |= (u128)1 << 127;
+    return code;
+  }
+};
+
+// ---------------------------------------------------------------- masks
+
+template <int D>
+__device__ __forceinline__ typename Cfg<D>::Mask load_mask(const void* __restrict__ masks, int64_t i) {
+  constexpr int B = mask_bytes(D);
+  if constexpr (B == 4) {
+    return (uint64_t)static_cast<const uint32_t*>(masks)[i];
+  } else if constexpr (B == 8) {
+    return static_cast<const uint64_t*>(masks)[i];
+  } else {
+    const uint64_t* p = static_cast<const uint64_t*>(masks) + 2 * i;
+    return ((u128)p[1] << 64) | (u128)p[0];
+  }
+}
+
+struct Runs {
+  int n;
+  uint8_t src[8], len[8], dst[8];
+};
+
+// Runs unpacked into wave-uniform scalars once per kernel.
+struct RunRegs {
+  int n;
+  int src[8], dst[8];
+  uint64_t keep[8];
+};
+
+__device__ __forceinline__ RunRegs unpack_runs(const Runs& r) {
+  RunRegs q;
+  q.n = r.n;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    q.src[k] = r.src[k];
+    q.dst[k] = r.dst[k];
+    q.keep[k] = r.len[k] >= 64 ? ~0ull : ((1ull << r.len[k]) - 1);
+  }
+  return q;
+}
+
+template <typename Mask>
+__device__ __forceinline__ Mask deposit(uint64_t idx, const RunRegs& r) {
+  Mask m = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (k < r.n) m |= (Mask)((idx >> r.src[k]) & r.keep[k]) << r.dst[k];
+  return m;
+}
+
+// ------------------------------------------------------------ histograms
+
+struct HistDev {
+  uint32_t* state;  // 0 empty, 1 being filled, 2 ready
+  uint64_t* key;    // 2 per slot (lo, hi)
+  uint64_t* cnt;
+  uint64_t* wit;
+  uint32_t* overflow;
+  uint32_t cap_mask;
+};
+
+__device__ __forceinline__ uint32_t hash_code(uint64_t lo, uint64_t hi) {
+  uint64_t z = lo ^ (hi * 0x9E3779B97F4A7C15ull) ^ 0x632BE59BD9B4E019ull;
+  z = (z ^ (z >> 31)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 29)) * 0x94D049BB133111EBull;
+  return (uint32_t)(z ^ (z >> 32));
+}
+
+// Insert (lo,hi) += k, witness min.  A slot goes 0 -> 1 (claimed by one
+// lane's CAS) -> 2 (key, count and witness written, released).  A lane that
+// meets a slot in state 1 re-reads it until the claiming lane has
+// published it (a handful of stores, so the wait is short); after
+// kClaimWait reads it moves on instead, which can only leave a duplicate
+// key that pw_hist_read merges.
+constexpr int kClaimWait = 1 << 16;
+
+__device__ void global_insert(const HistDev& h, uint64_t lo, uint64_t hi, uint64_t k, uint64_t w) {
+  uint32_t s = hash_code(lo, hi) & h.cap_mask;
+  int waited = 0;
+  for (uint32_t probe = 0; probe <= h.cap_mask;) {
+    uint32_t st = __hip_atomic_load(&h.state[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    if (st == 0) {
+      uint32_t expected = 0;
+      if (__hip_atomic_compare_exchange_strong(&h.state[s], &expected, 1u, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+                                               __HIP_MEMORY_SCOPE_AGENT)) {
+        h.key[2 * s] = lo;
+        h.key[2 * s + 1] = hi;
+        h.cnt[s] = k;
+        h.wit[s] = w;
+        __hip_atomic_store(&h.state[s], 2u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+      }
+      st = expected;
+    }
+    if (st == 1 && ++waited < kClaimWait) continue;  // same slot again
+    if (st == 2 && h.key[2 * s] == lo && h.key[2 * s + 1] == hi) {
+      atomicAdd(reinterpret_cast<unsigned long long*>(&h.cnt[s]), (unsigned long long)k);
+      atomicMin(reinterpret_cast<unsigned long long*>(&h.wit[s]), (unsigned long long)w);
+      return;
+    }
+    waited = 0;
+    ++probe;
+    s = (s + 1) & h.cap_mask;
+  }
+  atomicOr(h.overflow, 1u);
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+  return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// Per-wave code table held in registers: two entries per lane, 128 per
+// wave.  Every member is called by the whole wave with uniform arguments.
+struct Slot {
+  uint64_t lo, hi, cnt, wit;  // lo = hi = 0: empty (valid codes are never 0)
+  __device__ __forceinline__ bool holds(uint64_t a, uint64_t b) const { return lo == a && hi == b; }
+  __device__ __forceinline__ bool empty() const { return (lo | hi) == 0; }
+  __device__ __forceinline__ void put(uint64_t a, uint64_t b, uint64_t k, uint64_t w) {
+    lo = a;
+    hi = b;
+    cnt = k;
+    wit = w;
+  }
+  __device__ __forceinline__ void bump(uint64_t k, uint64_t w) {
+    cnt += k;
+    wit = w < wit ? w : wit;
+  }
+};
+
+struct WaveTable {
+  Slot s0, s1;
+
+  __device__ __forceinline__ void clear() {
+    s0.put(0, 0, 0, 0);
+    s1.put(0, 0, 0, 0);
+  }
+
+  __device__ __forceinline__ void flush(const HistDev& h) {
+    if (!s0.empty()) global_insert(h, s0.lo, s0.hi, s0.cnt, s0.wit);
+    if (!s1.empty()) global_insert(h, s1.lo, s1.hi, s1.cnt, s1.wit);
+    clear();
+  }
+
+  __device__ __forceinline__ void add(uint64_t lo, uint64_t hi, uint64_t k, uint64_t w, int lane,
+                                      const HistDev& h) {
+    const bool h0 = s0.holds(lo, hi), h1 = s1.holds(lo, hi);
+    if (__ballot(h0 || h1)) {
+      if (h0) s0.bump(k, w);
+      if (h1) s1.bump(k, w);
+      return;
+    }
+    const uint64_t e0 = __ballot(s0.empty());
+    if (e0) {
+      if (lane == __ffsll((unsigned long long)e0) - 1) s0.put(lo, hi, k, w);
+      return;
+    }
+    const uint64_t e1 = __ballot(s1.empty());
+    if (e1) {
+      if (lane == __ffsll((unsigned long long)e1) - 1) s1.put(lo, hi, k, w);
+      return;
+    }
+    flush(h);
+    if (lane == 0) s0.put(lo, hi, k, w);
+  }
+
+  // Aggregate one batch (one code per lane, `valid` lanes only).  Lanes
+  // hold consecutive indices, so the lowest lane of a match carries the
+  // smallest witness.
+  __device__ __forceinline__ void add_batch(uint64_t lo, uint64_t hi, bool valid, uint64_t widx, int lane,
+                                            const HistDev& h) {
+    uint64_t act = __ballot(valid && (lo | hi) != 0);
+    while (act) {
+      const int L = __ffsll((unsigned long long)act) - 1;
+      const uint64_t clo = readlane64(lo, L), chi = readlane64(hi, L);
+      const uint64_t match = __ballot(lo == clo && hi == chi) & act;
+      const uint64_t w = readlane64(widx, L);
+      add(clo, chi, (uint64_t)__popcll((unsigned long long)match), w, lane, h);
+      act &= ~match;
+    }
+  }
+};
+
+
+}  // namespace pw

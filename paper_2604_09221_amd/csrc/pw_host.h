@@ -1,0 +1,43 @@
+// pw_host.h -- host-side definitions shared by the C-ABI translation units:
+// the opaque handle structs, error reporting and device queries.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "patchwork.h"
+#include "pw_device.h"
+#include "pw_internal.h"
+
+struct pw_tri {
+  pw::HostProgram prog;
+  uint32_t* d_prog = nullptr;
+  uint32_t* d_err = nullptr;
+  int device = 0;
+};
+
+struct pw_hist {
+  int32_t cap = 0;
+  uint32_t* state = nullptr;
+  uint64_t* key = nullptr;
+  uint64_t* cnt = nullptr;
+  uint64_t* wit = nullptr;
+  uint32_t* overflow = nullptr;
+  pw::HistDev dev() const { return pw::HistDev{state, key, cnt, wit, overflow, (uint32_t)(cap - 1)}; }
+};
+
+namespace pw {
+
+// Record a message for pw_last_error() and return `code`.
+__attribute__((format(printf, 2, 3))) pw_status set_err(pw_status code, const char* fmt, ...);
+
+// Number of compute units of the current device (256 on MI355X).
+int cu_count();
+
+}  // namespace pw
+
+#define PW_HIP(call)                                                                                     \
+  do {                                                                                                   \
+    hipError_t e_ = (call);                                                                              \
+    if (e_ != hipSuccess) return pw::set_err(PW_ERR_HIP, "%s (code %d)", hipGetErrorString(e_), (int)e_); \
+  } while (0)

@@ -156,6 +156,8 @@ int build_program(int d, const int16_t* edges_ij, int n_edges, HostProgram* prog
     std::sort(earlier[v].begin(), earlier[v].end());
     uint32_t n = (uint32_t)earlier[v].size();
     if (n > 255) return fail(err, errlen, kTri, "vertex degree too large");
+    // the kernels use the first earlier neighbour as the spanning-tree parent
+    if (v > 0 && n == 0) return fail(err, errlen, kTri, "a diamond vertex has no earlier neighbour");
     prog->words[v] = p | (g << 7) | (n << 8) | ((uint32_t)off << 16);
     for (int u : earlier[v]) prog->words[nV + off++] = (uint32_t)u;
   }

@@ -169,3 +169,14 @@ def harnack_mask(d: int) -> int:
         if not (i % 2 == 0 and j % 2 == 0):
             m |= 1 << k
     return m
+
+
+def batched_degrees(n: int, seed: int = 0, lo: int = 4, hi: int = 12) -> np.ndarray:
+    """Degree of slot t: lo + (SplitMix64(seed)_t mod (hi - lo + 1))."""
+    return (lo + (splitmix64(seed, n) % np.uint64(hi - lo + 1))).astype(np.int64)
+
+
+def masks128(masks2: np.ndarray) -> np.ndarray:
+    """(n,2) uint64 masks -> flat int64 array, two words per mask (the
+    layout of the multi-triangulation launch)."""
+    return np.ascontiguousarray(masks2, dtype=np.uint64).reshape(-1).view(np.int64)

@@ -28,6 +28,11 @@ J_BIT = 1 << 127
 _lib = None
 
 
+class MultiConfig(ctypes.Structure):
+    """Launch shape of patchwork_scheme_batch_multi (pw_multi_config)."""
+    _fields_ = [("chunk", ctypes.c_int32), ("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
+
+
 class PatchworkError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"patchwork error {status}: {msg}")
@@ -61,9 +66,11 @@ def lib():
     L.pw_hist_destroy.argtypes = [vp]
     L.patchwork_scheme_histogram.argtypes = [vp, vp, i64, u64, vp, vp]
     L.patchwork_scheme_enumerate_range.argtypes = [vp, u64, u64, u64p, vp, vp]
+    L.patchwork_scheme_batch_multi.argtypes = [ctypes.POINTER(vp), i32, vp, ctypes.POINTER(ctypes.c_int64),
+                                               ctypes.POINTER(vp), vp, ctypes.POINTER(MultiConfig), vp]
     for name in ("pw_tri_create", "pw_tri_destroy", "pw_tri_info", "pw_tri_errors", "patchwork_scheme_batch",
                  "pw_hist_create", "pw_hist_reset", "pw_hist_read", "pw_hist_destroy",
-                 "patchwork_scheme_histogram", "patchwork_scheme_enumerate_range"):
+                 "patchwork_scheme_histogram", "patchwork_scheme_enumerate_range", "patchwork_scheme_batch_multi"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -207,3 +214,29 @@ class Histogram:
         for k in range(n.value):
             out[int(codes[k, 0]) | (int(codes[k, 1]) << 64)] = (int(counts[k]), int(wit[k]))
         return out
+
+
+def batch_multi(tris, masks128, offsets, hists=None, codes=None, config=None, stream=None):
+    """One persistent launch over many triangulations (any mix of degrees).
+
+    masks128: device int64 tensor holding two words per mask; triangulation
+    t owns masks [offsets[t], offsets[t+1]).  hists: list of Histogram (one
+    per triangulation) or None; codes: (n,2) int64 device tensor or None.
+    config: (chunk, waves_per_block, blocks_per_cu), or None for the tuned
+    shape from the tuning cache (defaults if there is none)."""
+    n = len(tris)
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    if len(off) != n + 1:
+        raise ValueError("offsets must have len(tris) + 1 entries")
+    th = (ctypes.c_void_p * n)(*[t.handle for t in tris])
+    hh = (ctypes.c_void_p * n)(*[h.handle for h in hists]) if hists is not None else None
+    if config is None:
+        from . import tune
+
+        config = tune.lookup_multi([t.d for t in tris])
+    cfg = MultiConfig(*config) if config is not None else None
+    check(lib().patchwork_scheme_batch_multi(
+        th, n, _ptr(masks128), off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+        hh, _ptr(codes) if codes is not None else None, ctypes.byref(cfg) if cfg is not None else None,
+        _stream(stream)))
+    return codes

@@ -1,0 +1,80 @@
+"""Autotuner for the persistent multi-triangulation launch.
+
+The launch shape of patchwork_scheme_batch_multi -- masks per work item,
+waves per block, blocks per CU -- is chosen by timing every candidate on the
+caller's own workload (device events around each launch, best of `repeats`)
+and cached per degree mix in tune_cache_gfx950.json next to this file (or the
+file named by $PW_TUNE).  lookup_multi() returns the cached shape, or None
+(the library defaults) if the mix was never tuned.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.environ.get("PW_TUNE", os.path.join(HERE, "tune_cache_gfx950.json"))
+
+CHUNKS = (1024, 4096, 16384)
+WAVES = (1, 2)
+BLOCKS_PER_CU = (0, 2)
+
+
+def mix_key(degrees) -> str:
+    ds = sorted(set(int(d) for d in degrees))
+    return "multi:" + ",".join(str(d) for d in ds)
+
+
+def _load():
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def lookup_multi(degrees):
+    entry = _load().get(mix_key(degrees))
+    if not entry:
+        return None
+    return tuple(entry["config"])
+
+
+def tune_multi(tris, masks128, offsets, hists=None, repeats=2, save=True, log=print):
+    """Time every candidate shape on this workload; cache and return the
+    fastest (chunk, waves_per_block, blocks_per_cu)."""
+    import torch
+
+    from . import patchwork as pw
+
+    results = []
+    for chunk in CHUNKS:
+        for waves in WAVES:
+            for bpc in BLOCKS_PER_CU:
+                cfg = (chunk, waves, bpc)
+                best = None
+                for _ in range(repeats):
+                    if hists is not None:
+                        for h in hists:
+                            h.reset()
+                    torch.cuda.synchronize()
+                    a = torch.cuda.Event(enable_timing=True)
+                    b = torch.cuda.Event(enable_timing=True)
+                    a.record()
+                    pw.batch_multi(tris, masks128, offsets, hists=hists, config=cfg)
+                    b.record()
+                    torch.cuda.synchronize()
+                    ms = a.elapsed_time(b)
+                    best = ms if best is None else min(best, ms)
+                results.append((best, cfg))
+                if log:
+                    log(f"tune multi {cfg}: {best:.3f} ms")
+    results.sort()
+    best_ms, best_cfg = results[0]
+    if save:
+        data = _load()
+        data[mix_key([t.d for t in tris])] = {"config": list(best_cfg), "ms": best_ms,
+                                              "candidates": [[list(c), ms] for ms, c in results]}
+        with open(CACHE, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+    return best_cfg
