@@ -18,6 +18,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -65,6 +67,112 @@ def cpu_baseline(d, E, n, codes_gpu_fn):
     }
 
 
+def _lift(args):
+    from paper_2604_09221_amd import inputs as I
+
+    d, seed, noise = args
+    return I.lift_triangulation(int(d), int(seed), noise=noise)
+
+
+def hist_capacity(d):
+    return {4: 64, 5: 64, 6: 128, 7: 256, 8: 1024, 9: 4096}.get(d, 1 << 15)
+
+
+def bench_multi(args):
+    """Batched uneven workload: 4096 triangulations, degree 4 + (SplitMix64(0)_t
+    mod 9), lift seed t, 2^16 masks each (SplitMix64 stream t, two outputs
+    per 128-bit mask, bits >= |A| and bit 0 cleared), per-triangulation
+    histograms, one persistent launch per step."""
+    from multiprocessing import Pool
+
+    import torch
+
+    from paper_2604_09221_amd import inputs as I
+    from paper_2604_09221_amd import learn as Lr
+    from paper_2604_09221_amd import patchwork as pw
+    from paper_2604_09221_amd import tune
+
+    n_slots, per = args.slots, 1 << 16
+    noise = 1.0 if args.varied else 0.05
+    degs = I.batched_degrees(n_slots, 0)
+    with Pool(min(16, os.cpu_count() or 1)) as pool:
+        edges = pool.map(_lift, [(int(d), t, noise) for t, d in enumerate(degs)])
+    torch.cuda.set_device(0)
+    tris = [pw.Triangulation(int(d), E) for d, E in zip(degs, edges)]
+    masks = torch.empty((n_slots * per, 2), dtype=torch.int64, device="cuda")
+    for t, d in enumerate(degs):
+        nA = (int(d) + 1) * (int(d) + 2) // 2
+        masks[t * per:(t + 1) * per] = Lr.random_masks(t, 0, per, nA)
+    offsets = np.arange(n_slots + 1, dtype=np.int64) * per
+    hists = [pw.Histogram(hist_capacity(int(d))) for d in degs]
+    flat = masks.view(-1)
+    cfg = tune.lookup_multi(degs)
+    if args.tune or cfg is None:
+        cfg = tune.tune_multi(tris, flat, offsets, hists=hists, repeats=1, log=lambda m: print(m, file=sys.stderr))
+    for _ in range(args.warmup):
+        pw.batch_multi(tris, flat, offsets, hists=hists, config=cfg)
+    for h in hists:
+        h.reset()
+    torch.cuda.synchronize()
+    times = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        pw.batch_multi(tris, flat, offsets, hists=hists, config=cfg)
+        b.record()
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b) / 1e3)
+    elapsed = time.perf_counter() - t0
+    evals = args.steps * n_slots * per
+    ops = sum(algorithmic_ops_per_mask(int(d)) for d in degs) * per
+    total = sum(c for c, _ in hists[0].read().values())
+    assert total == args.steps * per
+    assert all(t.errors() == 0 for t in tris[:64])
+    achieved = ops / (sum(times) / len(times)) / 1e12
+    return {
+        "metric": "sign distributions/sec, batched uneven degrees 4..12",
+        "value": evals / elapsed, "unit": "masks/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u128", "data": "synthetic",
+        "config": {"workload": f"{n_slots} triangulations ({'varied' if args.varied else 'literal'} lifts) x 2^16 "
+                               f"masks, degrees 4..12, per-triangulation histograms, one persistent launch",
+                   "launch_shape": list(cfg)},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_INT_OPS / 1e12, "unit": "TOP/s",
+                     "frac": achieved * 1e12 / PEAK_INT_OPS, "traffic": None, "kernel": "pw::k_multi",
+                     "avg_launch_ms": sum(times) / len(times) * 1e3},
+    }
+
+
+def bench_learned(args):
+    """d = 8 (seed-8 lift = the standard triangulation): distinct schemes
+    per GPU-second for uniform sampling, the learned proposal and its
+    ablation (random ranking), each judged by the exact kernel."""
+    import torch
+
+    from paper_2604_09221_amd import inputs as I
+    from paper_2604_09221_amd import learn as Lr
+    from paper_2604_09221_amd import patchwork as pw
+
+    d = 8
+    torch.cuda.set_device(0)
+    tri = pw.Triangulation(d, I.lift_triangulation(d, 8, noise=0.05))
+    budget = 1 << args.budget_log2
+    log = (lambda m: print(m, file=sys.stderr, flush=True))
+    res = [Lr.run_uniform(tri, d, budget)]
+    res.append(Lr.run_search(tri, d, budget, use_net=True, train_n=min(1 << 24, budget // 4), log=log))
+    res.append(Lr.run_search(tri, d, budget, use_net=False, train_n=min(1 << 24, budget // 4), log=log))
+    for r in res:
+        r["distinct_per_gpu_second"] = r["distinct"] / r["gpu_seconds"]
+    return {
+        "metric": "distinct real schemes found per GPU-second at d=8",
+        "value": res[1]["distinct_per_gpu_second"], "unit": "schemes/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16+u64", "data": "synthetic",
+        "config": {"workload": f"d=8 standard triangulation, {budget} judged masks per method", "results": res},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,11 +180,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=1 << 24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--config", choices=("d7", "multi", "learned"), default="d7")
+    ap.add_argument("--slots", type=int, default=4096)
+    ap.add_argument("--varied", action="store_true")
+    ap.add_argument("--tune", action="store_true")
+    ap.add_argument("--budget-log2", type=int, default=26)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(sharding is one histogram merge; see the design notes).", file=sys.stderr)
         sys.exit(2)
+    if args.config == "multi":
+        print(json.dumps(bench_multi(args)), flush=True)
+        return
+    if args.config == "learned":
+        print(json.dumps(bench_learned(args)), flush=True)
+        return
 
     import numpy as np
     import torch

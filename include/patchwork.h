@@ -168,8 +168,9 @@ pw_status patchwork_scheme_enumerate_range(pw_tri_t tri, uint64_t first, uint64_
  *             of a code is its smallest global mask index.
  *   d_codes   NULL, or n x 2 uint64 codes written at the masks' positions.
  *   cfg       NULL for the defaults, or the tuned launch shape: masks per
- *             work item, waves per block, blocks per CU (0 = as many as the
- *             LDS of the largest degree allows).
+ *             work item, waves per block (lowered until a block's LDS for
+ *             the largest degree fits in 160 KiB), blocks per CU (0 = as
+ *             many as the LDS allows).
  * Work items (chunks of one triangulation's masks) are taken from an atomic
  * queue in decreasing order of cost.  The call returns after the launch has
  * finished (its device tables are reused by the next call).

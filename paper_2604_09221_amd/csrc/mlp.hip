@@ -281,6 +281,17 @@ __global__ void k_random_masks(uint64_t seed, uint64_t offset, int64_t n, int n_
   out[2 * k + 1] = hi;
 }
 
+// counts[b] += #{k : lo + b w <= x[k] < lo + (b+1) w}, w = (hi - lo) / bins,
+// values outside [lo, hi) clamped into the end bins
+__global__ void k_bin_floats(const float* __restrict__ x, int64_t n, float lo, float hi, int bins,
+                             unsigned int* __restrict__ counts) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int b = (int)floorf((x[k] - lo) / (hi - lo) * (float)bins);
+  b = b < 0 ? 0 : (b >= bins ? bins - 1 : b);
+  atomicAdd(&counts[b], 1u);
+}
+
 // Keep the candidates scoring above `threshold`, in any order, up to cap.
 __global__ void k_select(const float* __restrict__ score, const uint64_t* __restrict__ cand, int64_t n,
                          float threshold, uint64_t* __restrict__ out, int64_t cap,
@@ -395,6 +406,15 @@ pw_status pw_random_masks(uint64_t seed, uint64_t offset, int64_t n, int32_t n_b
   if (n < 0 || n_bits < 1 || n_bits > 128 || !out) return set_err(PW_ERR_ARG, "bad random mask arguments");
   if (n == 0) return PW_OK;
   hipLaunchKernelGGL(k_random_masks, dim3(grid1d(n, 256)), dim3(256), 0, s, seed, offset, n, n_bits, out);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
+pw_status pw_bin_floats(const float* x, int64_t n, float lo, float hi, int32_t bins, uint32_t* counts,
+                        hipStream_t s) {
+  if (n < 0 || bins < 1 || !(hi > lo) || !x || !counts) return set_err(PW_ERR_ARG, "bad binning arguments");
+  if (n == 0) return PW_OK;
+  hipLaunchKernelGGL(k_bin_floats, dim3(grid1d(n, 256)), dim3(256), 0, s, x, n, lo, hi, bins, counts);
   PW_HIP(hipGetLastError());
   return PW_OK;
 }

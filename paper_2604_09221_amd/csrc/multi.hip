@@ -200,6 +200,8 @@ extern "C" pw_status patchwork_scheme_batch_multi(const pw_tri_t* tris, int32_t 
   // copies before returning so the host vectors may go away
   PW_HIP(hipMemcpyAsync(S.d_tris, desc.data(), sizeof(TriDesc) * desc.size(), hipMemcpyHostToDevice, stream));
   PW_HIP(hipMemcpyAsync(S.d_items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice, stream));
+  // fewer waves per block if the largest degree's LDS does not fit
+  while (c.waves_per_block > 1 && (size_t)max_words * 4 * 64 * c.waves_per_block > 160 * 1024) --c.waves_per_block;
   const int threads = 64 * c.waves_per_block;
   const size_t lds = (size_t)max_words * 4 * 64 * c.waves_per_block;
   if (lds > 160 * 1024) return set_err(PW_ERR_ARG, "block needs %zu bytes of LDS", lds);

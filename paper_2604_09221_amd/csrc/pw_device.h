@@ -32,16 +32,33 @@
 //     sorted descending by their left-aligned bit strings; leaves ('10')
 //     sort last.
 #pragma once
+#if defined(__HIPCC_RTC__)
+// compiled at run time for one triangulation: no standard headers there
+typedef __hip_internal::uint8_t uint8_t;
+typedef __hip_internal::uint16_t uint16_t;
+typedef __hip_internal::uint32_t uint32_t;
+typedef __hip_internal::uint64_t uint64_t;
+typedef __hip_internal::int64_t int64_t;
+#else
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
-#include <type_traits>
+#endif
 
 #include "pw_internal.h"
 
 namespace pw {
 
 typedef unsigned __int128 u128;
+
+template <bool B, class X, class Y>
+struct cond {
+  using type = X;
+};
+template <class X, class Y>
+struct cond<false, X, Y> {
+  using type = Y;
+};
 
 // ------------------------------------------------------------------ config
 
@@ -53,9 +70,9 @@ struct Cfg {
   static constexpr int NP = 2 * D;
   static constexpr int RMAX = harnack(D) + 1;  // regions = ovals + 1 <= M + 1
   static constexpr bool EVEN = (D % 2) == 0;
-  using Mask = typename std::conditional<(NA <= 64), uint64_t, u128>::type;
-  using Adj = typename std::conditional<(RMAX <= 32), uint32_t, uint64_t>::type;
-  using Code = typename std::conditional<(D <= 9), uint64_t, u128>::type;
+  using Mask = typename cond<(NA <= 64), uint64_t, u128>::type;
+  using Adj = typename cond<(RMAX <= 32), uint32_t, uint64_t>::type;
+  using Code = typename cond<(D <= 9), uint64_t, u128>::type;
   static constexpr int ADJ_W = sizeof(Adj) / 4;
   static constexpr int CODE_W = sizeof(Code) / 4;
   // per-lane LDS words:
@@ -193,101 +210,103 @@ struct Eval {
     return r;
   }
 
+  // Phase 1 step: v's earlier neighbour u; sv = sign of v, rv = v's root so
+  // far (v itself until v is linked).
+  __device__ static __forceinline__ void edge(const Lane& L, uint32_t sv, int v, int& rv, int u) {
+    const uint32_t eu = L.ent(u);
+    if ((eu >> kSignShift) == sv) {
+      uint32_t er;
+      const int r = find(L, u, eu, er);
+      if (r != (int)(eu & kParent)) L.ent(u) = (uint16_t)((eu & ~kParent) | (uint32_t)r);
+      if (rv == v) {
+        rv = r;
+      } else if (r != rv) {
+        const int lo = r < rv ? r : rv, hi = r < rv ? rv : r;
+        L.ent(hi) = (uint16_t)((sv << kSignShift) | (uint32_t)lo);
+        rv = lo;
+      }
+    }
+  }
+
+  // Phase 2 step: one antipodal pair (a, b).
+  __device__ static __forceinline__ void pair(const Lane& L, int a, int b) {
+    uint32_t ea, eb, pa, pb;
+    const int ra = find_parity(L, a, ea, pa);
+    const int rb = find_parity(L, b, eb, pb);
+    if (ra == rb) {
+      if (C::EVEN && pa == pb) L.ent(ra) = (uint16_t)(ea | kOdd);
+    } else {
+      const bool a_lo = ra < rb;
+      const int lo = a_lo ? ra : rb, hi = a_lo ? rb : ra;
+      const uint32_t elo = a_lo ? ea : eb, ehi = a_lo ? eb : ea;
+      const uint32_t par = C::EVEN ? ((pa ^ pb ^ 1u) ? kParity : 0u) : 0u;
+      L.ent(hi) = (uint16_t)((ehi & (1u << kSignShift)) | par | (uint32_t)lo);
+      if (ehi & kOdd) L.ent(lo) = (uint16_t)(elo | kOdd);
+    }
+  }
+
+  // Phase 3 step for vertex v with spanning-tree parent t (t < 0 for v = 0).
+  // A union-find root is the first vertex of its region and gets the next
+  // id.  The tree edges t(v)-v form a spanning tree of T<>.  Each oval
+  // separates two regions that both contain vertices, so some tree edge
+  // crosses it; the tree edge into the first vertex of a region B comes
+  // from the region across one of B's boundary ovals, and "parent(B) =
+  // region of t(first vertex of B)" is exactly the region adjacency tree,
+  // rooted at the region of vertex 0.  For odd d a crossed tree edge inside
+  // one region crosses the pseudo-line: that region is the root (Alg. 1).
+  __device__ static __forceinline__ void vertex3(const Lane& L, int v, int t, int& nR, int& root, uint32_t& err) {
+    const uint32_t ev = L.ent(v);
+    const uint32_t sv = ev >> kSignShift;
+    const int p = (int)(ev & kParent);
+    int cid;
+    if (p == v) {
+      cid = nR < C::RMAX ? nR : C::RMAX - 1;
+      err |= nR < C::RMAX ? 0u : kErrRegions;
+      ++nR;
+      if (C::EVEN && (ev & kOdd)) {
+        if (root >= 0) err |= kErrRoot;
+        root = cid;
+      }
+      const int pc = t >= 0 ? (int)(L.ent(t) & kParent) : 0xFF;
+      L.byte(C::PAR_BASE + (cid >> 2), cid & 3) = (uint8_t)pc;
+    } else {
+      cid = (int)(L.ent(p) & kParent);
+      if (!C::EVEN) {
+        const uint32_t et = L.ent(t);
+        if ((et >> kSignShift) != sv && (int)(et & kParent) == cid) {
+          if (root >= 0 && root != cid) err |= kErrRoot;
+          root = cid;
+        }
+      }
+    }
+    L.ent(v) = (uint16_t)((sv << kSignShift) | (uint32_t)cid);
+  }
+
   // Returns the scheme code (0 on a failed consistency check, with the
-  // reason or-ed into errs).
+  // reason or-ed into errs), walking the program in device memory.
   __device__ static u128 run(const uint32_t* __restrict__ prog, Mask m, const Lane& L, uint32_t& errs) {
     const uint32_t* nbr = prog + C::NV;
     const uint32_t* pairs = prog + C::NV + C::NE;
-
-    // ---- phase 1: components of same-sign vertices
+    // phase 1: components of same-sign vertices
     for (int v = 0; v < C::NV; ++v) {
       const uint32_t rec = prog[v];
-      const int p = rec & 0x7F;
-      const uint32_t sv = bit(m, p) ^ ((rec >> 7) & 1u);
+      const uint32_t sv = bit(m, rec & 0x7F) ^ ((rec >> 7) & 1u);
       const int nn = (rec >> 8) & 0xFF;
       const int off = rec >> 16;
       int rv = v;
-      for (int k = 0; k < nn; ++k) {
-        const int u = (int)nbr[off + k];
-        const uint32_t eu = L.ent(u);
-        if ((eu >> kSignShift) == sv) {
-          uint32_t er;
-          const int r = find(L, u, eu, er);
-          if (r != (int)(eu & kParent)) L.ent(u) = (uint16_t)((eu & ~kParent) | (uint32_t)r);
-          if (rv == v) {
-            rv = r;
-          } else if (r != rv) {
-            const int lo = r < rv ? r : rv, hi = r < rv ? rv : r;
-            L.ent(hi) = (uint16_t)((sv << kSignShift) | (uint32_t)lo);
-            rv = lo;
-          }
-        }
-      }
+      for (int k = 0; k < nn; ++k) edge(L, sv, v, rv, (int)nbr[off + k]);
       L.ent(v) = (uint16_t)((sv << kSignShift) | (uint32_t)rv);
     }
-
-    // ---- phase 2: regions (antipodal identification)
-    for (int t = 0; t < C::NP; ++t) {
-      const uint32_t pr = pairs[t];
-      const int a = pr & 0xFFFF, b = pr >> 16;
-      uint32_t ea, eb, pa, pb;
-      const int ra = find_parity(L, a, ea, pa);
-      const int rb = find_parity(L, b, eb, pb);
-      if (ra == rb) {
-        if (C::EVEN && pa == pb) L.ent(ra) = (uint16_t)(ea | kOdd);
-      } else {
-        const bool a_lo = ra < rb;
-        const int lo = a_lo ? ra : rb, hi = a_lo ? rb : ra;
-        const uint32_t elo = a_lo ? ea : eb, ehi = a_lo ? eb : ea;
-        const uint32_t par = C::EVEN ? ((pa ^ pb ^ 1u) ? kParity : 0u) : 0u;
-        L.ent(hi) = (uint16_t)((ehi & (1u << kSignShift)) | par | (uint32_t)lo);
-        if (ehi & kOdd) L.ent(lo) = (uint16_t)(elo | kOdd);
-      }
-    }
-
-    // ---- phase 3: region ids and the region tree.  Vertices in order; a
-    // union-find root is the first vertex of its region and gets the next
-    // id.  Every vertex v > 0 has a fixed earlier neighbour t(v) (the first
-    // of its list), so these edges form a spanning tree of T<>.  Each oval
-    // separates two regions that both contain vertices, so some tree edge
-    // crosses it; in particular the tree edge into the first vertex of a
-    // region B comes from the region on the other side of an oval of B,
-    // and "parent(B) = region of t(first vertex of B)" is exactly the
-    // region adjacency tree, rooted at the region of vertex 0.  For odd d
-    // a crossed tree edge inside one region crosses the pseudo-line: that
-    // region is the root (Alg. 1).
-    int nR = 0;
-    int root = -1;
+    // phase 2: regions (antipodal identification)
+    for (int t = 0; t < C::NP; ++t) pair(L, pairs[t] & 0xFFFF, pairs[t] >> 16);
+    // phase 3: region ids and the region tree
+    int nR = 0, root = -1;
     uint32_t err = 0;
-    for (int v = 0; v < C::NV; ++v) {
-      const uint32_t rec = prog[v];
-      const int off = rec >> 16;
-      const uint32_t ev = L.ent(v);
-      const uint32_t sv = ev >> kSignShift;
-      const int p = (int)(ev & kParent);
-      int cid;
-      if (p == v) {
-        cid = nR < C::RMAX ? nR : C::RMAX - 1;
-        err |= nR < C::RMAX ? 0u : kErrRegions;
-        ++nR;
-        if (C::EVEN && (ev & kOdd)) {
-          if (root >= 0) err |= kErrRoot;
-          root = cid;
-        }
-        const int pc = v > 0 ? (int)(L.ent((int)nbr[off]) & kParent) : 0xFF;
-        L.byte(C::PAR_BASE + (cid >> 2), cid & 3) = (uint8_t)pc;
-      } else {
-        cid = (int)(L.ent(p) & kParent);
-        if (!C::EVEN) {
-          const uint32_t et = L.ent((int)nbr[off]);
-          if ((et >> kSignShift) != sv && (int)(et & kParent) == cid) {
-            if (root >= 0 && root != cid) err |= kErrRoot;
-            root = cid;
-          }
-        }
-      }
-      L.ent(v) = (uint16_t)((sv << kSignShift) | (uint32_t)cid);
-    }
+    for (int v = 0; v < C::NV; ++v) vertex3(L, v, v > 0 ? (int)nbr[prog[v] >> 16] : -1, nR, root, err);
+    return finish(L, nR, root, err, errs);
+  }
+
+  __device__ static u128 finish(const Lane& L, int nR, int root, uint32_t err, uint32_t& errs) {
     if (root < 0) err |= kErrRoot;
     if (err) {
       errs |= err;
@@ -560,5 +579,93 @@ struct WaveTable {
   }
 };
 
+
+// ------------------------------------------------------------ kernel bodies
+// An evaluator maps (mask, lane memory, error flags) to a scheme code:
+// RtEval walks the program in device memory; a kernel generated for one
+// triangulation supplies its own straight-line evaluator.
+
+template <int D>
+struct RtEval {
+  const uint32_t* prog;
+  __device__ __forceinline__ u128 operator()(typename Cfg<D>::Mask m, const Lane& L, uint32_t& errs) const {
+    return Eval<D>::run(prog, m, L, errs);
+  }
+};
+
+__device__ __forceinline__ Lane lane_memory(uint32_t* smem, int lane_words) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  return Lane{smem + wave * lane_words * 64 + lane};
+}
+
+// codes of n masks, one per thread, grid-stride
+template <int D, class EV>
+__device__ __forceinline__ void codes_body(const EV& ev, const void* __restrict__ masks, int64_t n,
+                                           uint64_t* __restrict__ codes, uint32_t* __restrict__ errflag,
+                                           uint32_t* smem) {
+  using C = Cfg<D>;
+  const Lane L = lane_memory(smem, C::LANE_WORDS);
+  uint32_t errs = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
+    const int64_t i = base + threadIdx.x;
+    const bool valid = i < n;
+    const typename C::Mask m = valid ? load_mask<D>(masks, i) : (typename C::Mask)0;
+    const u128 code = ev(m, L, errs);
+    if (valid) {
+      codes[2 * i] = (uint64_t)code;
+      codes[2 * i + 1] = (uint64_t)(code >> 64);
+    }
+  }
+  if (errs) atomicOr(errflag, errs);
+}
+
+// histogram of n masks; each wave takes batches of 64 consecutive masks
+template <int D, class EV>
+__device__ __forceinline__ void hist_body(const EV& ev, const void* __restrict__ masks, int64_t n,
+                                          uint64_t index_base, const HistDev& h, uint32_t* __restrict__ errflag,
+                                          uint32_t* smem) {
+  using C = Cfg<D>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const Lane L = lane_memory(smem, C::LANE_WORDS);
+  WaveTable tab;
+  tab.clear();
+  uint32_t errs = 0;
+  const int64_t waves_total = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t base = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * 64; base < n; base += waves_total * 64) {
+    const int64_t i = base + lane;
+    const bool valid = i < n;
+    const typename C::Mask m = valid ? load_mask<D>(masks, i) : (typename C::Mask)0;
+    const u128 code = ev(m, L, errs);
+    tab.add_batch((uint64_t)code, (uint64_t)(code >> 64), valid, index_base + (uint64_t)i, lane, h);
+  }
+  tab.flush(h);
+  if (errs) atomicOr(errflag, errs);
+}
+
+// histogram of the masks generated from indices first .. first+count-1
+template <int D, class EV>
+__device__ __forceinline__ void enum_body(const EV& ev, uint64_t first, uint64_t count, const Runs& runs,
+                                          const HistDev& h, uint32_t* __restrict__ errflag, uint32_t* smem) {
+  using C = Cfg<D>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const Lane L = lane_memory(smem, C::LANE_WORDS);
+  WaveTable tab;
+  tab.clear();
+  const RunRegs rr = unpack_runs(runs);
+  uint32_t errs = 0;
+  const uint64_t waves_total = (uint64_t)gridDim.x * (blockDim.x >> 6);
+  for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + wave) * 64; base < count;
+       base += waves_total * 64) {
+    const uint64_t k = base + lane;
+    const bool valid = k < count;
+    const uint64_t idx = first + k;
+    const typename C::Mask m = deposit<typename C::Mask>(idx, rr);
+    const u128 code = ev(m, L, errs);
+    tab.add_batch((uint64_t)code, (uint64_t)(code >> 64), valid, idx, lane, h);
+  }
+  tab.flush(h);
+  if (errs) atomicOr(errflag, errs);
+}
 
 }  // namespace pw

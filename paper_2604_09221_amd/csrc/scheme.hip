@@ -20,76 +20,30 @@
 namespace pw {
 
 // ---------------------------------------------------------------- kernels
+// The generic kernels walk the triangulation program in device memory; the
+// bodies are shared with the kernels generated for one triangulation.
 
 template <int D>
 __global__ __launch_bounds__(256) void k_codes(const uint32_t* __restrict__ prog, const void* __restrict__ masks,
                                                int64_t n, uint64_t* __restrict__ codes,
                                                uint32_t* __restrict__ errflag) {
-  using C = Cfg<D>;
   extern __shared__ uint32_t smem[];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const Lane L{smem + wave * C::LANE_WORDS * 64 + lane};
-  uint32_t errs = 0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
-    const int64_t i = base + threadIdx.x;
-    const bool valid = i < n;
-    const typename C::Mask m = valid ? load_mask<D>(masks, i) : (typename C::Mask)0;
-    const u128 code = Eval<D>::run(prog, m, L, errs);
-    if (valid) {
-      codes[2 * i] = (uint64_t)code;
-      codes[2 * i + 1] = (uint64_t)(code >> 64);
-    }
-  }
-  if (errs) atomicOr(errflag, errs);
+  codes_body<D>(RtEval<D>{prog}, masks, n, codes, errflag, smem);
 }
 
 template <int D>
 __global__ __launch_bounds__(256) void k_hist(const uint32_t* __restrict__ prog, const void* __restrict__ masks,
                                               int64_t n, uint64_t index_base, HistDev h,
                                               uint32_t* __restrict__ errflag) {
-  using C = Cfg<D>;
   extern __shared__ uint32_t smem[];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const Lane L{smem + wave * C::LANE_WORDS * 64 + lane};
-  WaveTable tab;
-  tab.clear();
-  uint32_t errs = 0;
-  const int64_t waves_total = (int64_t)gridDim.x * (blockDim.x >> 6);
-  for (int64_t base = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * 64; base < n; base += waves_total * 64) {
-    const int64_t i = base + lane;
-    const bool valid = i < n;
-    const typename C::Mask m = valid ? load_mask<D>(masks, i) : (typename C::Mask)0;
-    const u128 code = Eval<D>::run(prog, m, L, errs);
-    tab.add_batch((uint64_t)code, (uint64_t)(code >> 64), valid, index_base + (uint64_t)i, lane, h);
-  }
-  tab.flush(h);
-  if (errs) atomicOr(errflag, errs);
+  hist_body<D>(RtEval<D>{prog}, masks, n, index_base, h, errflag, smem);
 }
 
 template <int D>
 __global__ __launch_bounds__(256) void k_enum(const uint32_t* __restrict__ prog, uint64_t first, uint64_t count,
                                               Runs runs, HistDev h, uint32_t* __restrict__ errflag) {
-  using C = Cfg<D>;
   extern __shared__ uint32_t smem[];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const Lane L{smem + wave * C::LANE_WORDS * 64 + lane};
-  WaveTable tab;
-  tab.clear();
-  const RunRegs rr = unpack_runs(runs);
-  uint32_t errs = 0;
-  const uint64_t waves_total = (uint64_t)gridDim.x * (blockDim.x >> 6);
-  for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + wave) * 64; base < count;
-       base += waves_total * 64) {
-    const uint64_t k = base + lane;
-    const bool valid = k < count;
-    const uint64_t idx = first + k;
-    const typename C::Mask m = deposit<typename C::Mask>(idx, rr);
-    const u128 code = Eval<D>::run(prog, m, L, errs);
-    tab.add_batch((uint64_t)code, (uint64_t)(code >> 64), valid, idx, lane, h);
-  }
-  tab.flush(h);
-  if (errs) atomicOr(errflag, errs);
+  enum_body<D>(RtEval<D>{prog}, first, count, runs, h, errflag, smem);
 }
 
 }  // namespace pw

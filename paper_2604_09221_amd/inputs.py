@@ -94,13 +94,21 @@ def lift_triangulation(d: int, seed: int, noise: float = 0.05) -> np.ndarray:
             raise ValueError(f"lower face {P[a]},{P[b]},{P[c]} is not unimodular (d={d}, seed={seed})")
         if det2 < 0:
             b, c = c, b
-        for p in range(len(P)):
+        # every other lifted point strictly above the face's plane: decided
+        # in float64 where the margin is large, exactly otherwise
+        u = X[b] - X[a]
+        v = X[c] - X[a]
+        w = X - X[a]
+        det = (u[0] * (v[1] * w[:, 2] - v[2] * w[:, 1]) - u[1] * (v[0] * w[:, 2] - v[2] * w[:, 0])
+               + u[2] * (v[0] * w[:, 1] - v[1] * w[:, 0]))
+        for p in np.nonzero(det <= 1e-6)[0]:
+            p = int(p)
             if p in (a, b, c):
                 continue
             if _above(Q[a], Q[b], Q[c], Q[p]) <= 0:
                 raise ValueError(f"lift not generic or hull wrong (d={d}, seed={seed})")
-        for (u, v) in ((a, b), (b, c), (a, c)):
-            edges.add((min(u, v), max(u, v)))
+        for (u_, v_) in ((a, b), (b, c), (a, c)):
+            edges.add((min(u_, v_), max(u_, v_)))
     if len(tris) != d * d:
         raise ValueError(f"{len(tris)} lower faces, expected {d * d}")
     E = sorted(edges)

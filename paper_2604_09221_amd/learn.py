@@ -45,9 +45,10 @@ def _bind():
     L.pw_mutate.argtypes = [vp, i64, i64, i32, i32, u64, vp, vp]
     L.pw_select.argtypes = [vp, vp, i64, f32, vp, i64, vp, vp]
     L.pw_random_masks.argtypes = [u64, u64, i64, i32, vp, vp]
+    L.pw_bin_floats.argtypes = [vp, i64, f32, f32, i32, vp, vp]
     for n in ("pw_mlp_gemm", "pw_mlp_encode", "pw_features", "pw_mlp_softmax_xent", "pw_mlp_colsum",
               "pw_mlp_adam", "pw_mlp_score", "pw_to_bf16", "pw_mutate", "pw_select",
-              "pw_random_masks"):
+              "pw_random_masks", "pw_bin_floats"):
         getattr(L, n).restype = i32
     _bound = True
     return L
@@ -220,6 +221,22 @@ def score(Y, rarity):
     return out
 
 
+def top_threshold(scores, k, lo, hi, bins=1024):
+    """Score above which about k candidates lie: a device histogram of the
+    scores, scanned from the top on the host (1024 counts)."""
+    import torch
+
+    cnt = torch.zeros(bins, dtype=torch.int32, device=scores.device)
+    pw.check(_bind().pw_bin_floats(_p(scores), scores.numel(), lo, hi, bins, _p(cnt), _s()))
+    c = cnt.cpu().numpy().view(np.uint32)
+    acc = 0
+    for b in range(bins - 1, -1, -1):
+        acc += int(c[b])
+        if acc >= k:
+            return lo + (hi - lo) * b / bins
+    return -np.inf
+
+
 def select(scores, cands, threshold, cap):
     import torch
 
@@ -296,6 +313,7 @@ def run_search(tri, d, budget, use_net=True, train_n=1 << 22, epochs=2, batch=40
     book.add(m, codes)
     net = None
     rarity = None
+    score_hi = 1.0
     if use_net:
         lab = features(codes)
         X = encode(m, train_n, nA)
@@ -311,22 +329,23 @@ def run_search(tri, d, budget, use_net=True, train_n=1 << 22, epochs=2, batch=40
             p /= p.sum()
             r[st[h]:st[h + 1]] = -np.log(p)
         rarity = torch.from_numpy(r).cuda()
+        score_hi = float(sum(r[st[h]:st[h + 1]].max() for h in range(6)))
     train_s = time.perf_counter() - t0
     rnd = 0
     while book.evals < budget:
         rnd += 1
         k = min(per_round, budget - book.evals)
         parents = torch.from_numpy(book.rarest(n_elite).view(np.int64)).cuda()
-        cand = mutate(parents, k * oversample, nA, 1 + rnd % 3, seed * 1000003 + rnd)
+        cand = mutate(parents, k * (oversample if use_net else 1), nA, 1 + rnd % 3, seed * 1000003 + rnd)
         if use_net:
             Y = net.forward(encode(cand, cand.shape[0], nA))
             sc = score(Y, rarity)
+            thr = top_threshold(sc, k, 0.0, score_hi)
+            sel = select(sc, cand, thr, k)
+            if sel.shape[0] == 0:
+                sel = cand[:k]
         else:
-            sc = random_masks(seed + 99, rnd * k * oversample, k * oversample, 32)[:, 0].to(torch.float32)
-        thr = float(torch.kthvalue(sc.cpu(), max(1, sc.numel() - k)).values) if sc.numel() > k else -np.inf
-        sel = select(sc, cand, thr, k)
-        if sel.shape[0] == 0:
-            sel = cand[:k]
+            sel = cand[:k]          # random ranking: the mutants are already in random order
         codes = tri.batch(sel if wide else sel[:, 0].contiguous())
         book.add(sel, codes)
         if log and rnd % 16 == 0:

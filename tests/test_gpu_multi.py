@@ -80,11 +80,21 @@ def test_multi_literal_lift_slots_and_edge_cases(pw):
         t = int(np.searchsorted(offsets, k, side="right") - 1)
         want = oracle.scheme_many(int(degs[t]), edges[t], allm[k:k + 1])
         assert np.array_equal(got[k:k + 1], want)
-    # empty slots are allowed
+    # empty slots are allowed ...
     off2 = offsets.copy()
     off2[3] = off2[2]
     off2[4] = off2[2]
+    codes2 = torch.zeros_like(codes)
+    pw.batch_multi(tris, mt, off2, codes=codes2)                 # slot 4 now owns [off2[4], off2[5])
+    got2 = codes2.cpu().numpy().view(np.uint64)
+    a, b = int(off2[4]), int(off2[5])
+    assert np.array_equal(got2[a:b], oracle.scheme_many(int(degs[4]), edges[4], allm[a:b], threads=8))
+    assert np.array_equal(got2[b:], got[b:])
+    assert np.array_equal(got2[:a], got[:a])
+    # ... decreasing offsets are not
+    off3 = offsets.copy()
+    off3[3] = off3[2] - 1
     with pytest.raises(pw.PatchworkError):
-        pw.batch_multi(tris, mt, off2, codes=codes)          # non-monotone offsets
-    empty = np.concatenate([[0], np.zeros(len(tris), dtype=np.int64)])
+        pw.batch_multi(tris, mt, off3, codes=codes)
+    empty = np.zeros(len(tris) + 1, dtype=np.int64)
     pw.batch_multi(tris, mt, empty, codes=codes)                 # nothing to do
