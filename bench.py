@@ -158,6 +158,7 @@ def bench_learned(args):
     d = 8
     torch.cuda.set_device(0)
     tri = pw.Triangulation(d, I.lift_triangulation(d, 8, noise=0.05))
+    tri.specialize()
     budget = 1 << args.budget_log2
     log = (lambda m: print(m, file=sys.stderr, flush=True))
     res = [Lr.run_uniform(tri, d, budget)]
@@ -180,11 +181,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=1 << 24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--config", choices=("d7", "multi", "learned"), default="d7")
+    ap.add_argument("--config", choices=("d7", "multi", "learned", "copyprobe"), default="d7")
     ap.add_argument("--slots", type=int, default=4096)
     ap.add_argument("--varied", action="store_true")
     ap.add_argument("--tune", action="store_true")
     ap.add_argument("--budget-log2", type=int, default=26)
+    ap.add_argument("--generic", action="store_true", help="time the generic (unspecialised) kernel")
+    ap.add_argument("--chunk-log2", type=int, default=32, help="masks per step (profiling runs use less)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -195,6 +198,17 @@ def main():
         return
     if args.config == "learned":
         print(json.dumps(bench_learned(args)), flush=True)
+        return
+    if args.config == "copyprobe":
+        # reference for HBM traffic counters: one device-to-device copy of
+        # exactly 1 GiB (a plain copy kernel reads and writes 1 GiB each)
+        import torch
+
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 1 << 30}), flush=True)
         return
 
     import numpy as np
@@ -207,12 +221,22 @@ def main():
     E = I.lift_triangulation(d, 7, noise=0.05)
     torch.cuda.set_device(0)
     tri = pw.Triangulation(d, E)
+    # kernels specialised to this triangulation (hipRTC); compile time is
+    # setup, outside the timed region
+    t_spec = time.perf_counter()
+    kernel = "pw_jit_enum (kernel specialised to the d=7 triangulation)"
+    if args.generic:
+        kernel = "pw::k_enum<7> (generic)"
+    else:
+        tri.specialize()
+    t_spec = time.perf_counter() - t_spec
     hist = pw.Histogram(1024)
     warm = pw.Histogram(1024)
     stream = torch.cuda.current_stream()
 
+    CHUNK = 1 << args.chunk_log2
     for w in range(args.warmup):
-        tri.enumerate_range((w % 8) * CHUNK, CHUNK, warm)
+        tri.enumerate_range((w * CHUNK) % TOTAL, CHUNK, warm)
     torch.cuda.synchronize()
 
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
@@ -256,6 +280,7 @@ def main():
             "masks_per_step": CHUNK,
             "full_sweep": masks_done == TOTAL,
             "distinct_schemes": len(h),
+            "specialize_seconds": t_spec,
         },
         "roofline": {
             "bound": "alu",
@@ -264,7 +289,7 @@ def main():
             "unit": "TOP/s",
             "frac": achieved * 1e12 / PEAK_INT_OPS,
             "traffic": None,
-            "kernel": "pw::k_enum<7>",
+            "kernel": kernel,
             "ops_per_mask": algorithmic_ops_per_mask(d),
             "avg_launch_ms": avg_launch_s * 1e3,
         },

@@ -106,6 +106,29 @@ pw_status pw_tri_info(pw_tri_t tri, int32_t *d, int32_t *n_points, int32_t *n_ve
 pw_status pw_tri_errors(pw_tri_t tri, uint32_t *flags);
 
 /*
+ * Build kernels specialised to this triangulation (d <= 9): the walk of
+ * Alg. 1 over its diamond (Sec. 2) is written out as straight-line code with
+ * the vertex, neighbour and antipodal-pair indices as literals, compiled with
+ * hipRTC for gfx950 and loaded on the current device.  Afterwards
+ * patchwork_scheme_batch / _histogram / _enumerate_range on this handle use
+ * them; results are identical to the generic kernels.  Takes seconds (a
+ * compile); idempotent.  Errors: PW_ERR_ARG (d > 9), PW_ERR_HIP (compile or
+ * load failed; the handle keeps using the generic kernels).
+ */
+pw_status pw_tri_specialize(pw_tri_t tri);
+
+/* The source text pw_tri_specialize compiles for the triangulation given
+ * by (d, edges_ij, n_edges) (validated as in pw_tri_create), into a host
+ * buffer of cap bytes, NUL-terminated and truncated to fit; *len receives
+ * the full length.  Needs no GPU. */
+pw_status pw_jit_source(int32_t d, const int16_t *edges_ij, int32_t n_edges, char *buf, int64_t cap,
+                        int64_t *len);
+
+/* Compile that source with hipRTC for gfx950 without loading it (needs no
+ * GPU); *code_bytes receives the code object size. */
+pw_status pw_jit_compile(int32_t d, const int16_t *edges_ij, int32_t n_edges, int64_t *code_bytes);
+
+/*
  * Codes of n sign masks (Alg. 1 for each pair (T, sigma_k)).
  *   d_masks  n masks of pw_mask_bytes(d) bytes each, contiguous.
  *   d_codes  n x 2 uint64 (lo, hi) written in input order.
@@ -149,8 +172,8 @@ pw_status patchwork_scheme_histogram(pw_tri_t tri, const void *d_masks, int64_t 
  * the three points (0,0), (1,0), (0,1) fixed it visits one representative of
  * each (Z/2)^3 class (Sec. 3, Table 1).  The witness of a code is the
  * smallest index first+k that produced it.  The free positions may form at
- * most 8 contiguous runs.  Errors: PW_ERR_RANGE if first+count exceeds
- * 2^(number of free bits), PW_ERR_ARG for more than 8 runs.
+ * most 4 contiguous runs.  Errors: PW_ERR_RANGE if first+count exceeds
+ * 2^(number of free bits), PW_ERR_ARG for more than 4 runs.
  */
 pw_status patchwork_scheme_enumerate_range(pw_tri_t tri, uint64_t first, uint64_t count,
                                            const uint64_t fixed_zero_bits[2], pw_hist_t hist,

@@ -1,0 +1,162 @@
+// jit.cpp -- kernels specialised to one triangulation, built at run time.
+//
+// For a sweep over billions of sign distributions of one triangulation
+// (Sec. 3) the triangulation is a constant.  pw_tri_specialize() writes the
+// evaluation of Alg. 1 for that triangulation as straight-line code -- one
+// block per diamond vertex with its earlier neighbours and its spanning-tree
+// parent as literals, one call per antipodal pair -- compiles it with hipRTC
+// for gfx950 and loads it.  The steps it calls (Eval<D>::edge, pair, vertex3,
+// finish) and the kernel bodies are the same device functions the generic
+// kernels use; only the walk over the program is unrolled, so every LDS
+// offset becomes an immediate and no scalar decoding or loop control is
+// left.
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "patchwork.h"
+#include "pw_host.h"
+#include "rtc_headers.inc"
+
+namespace pw {
+
+std::string jit_source(const HostProgram& P) {
+  std::ostringstream o;
+  const int d = P.d, nV = P.nV, nE = P.nE, nP = P.nP;
+  o << "// generated evaluator for one degree-" << d << " triangulation\n";
+  o << "#include \"pw_device.h\"\n\nnamespace pw {\n\nstruct JitEval {\n";
+  o << "  __device__ __forceinline__ u128 operator()(Cfg<" << d
+    << ">::Mask m, const Lane& L, uint32_t& errs) const {\n";
+  o << "    using E = Eval<" << d << ">;\n";
+  o << "    // phase 1: components of same-sign vertices\n";
+  for (int v = 0; v < nV; ++v) {
+    const uint32_t rec = P.words[v];
+    const int p = rec & 0x7F, g = (rec >> 7) & 1, n = (rec >> 8) & 0xFF, off = rec >> 16;
+    o << "    { const uint32_t sv = E::bit(m, " << p << ")" << (g ? " ^ 1u" : "") << "; int rv = " << v << ";";
+    for (int k = 0; k < n; ++k) o << " E::edge(L, sv, " << v << ", rv, " << P.words[nV + off + k] << ");";
+    o << " L.ent(" << v << ") = (uint16_t)((sv << kSignShift) | (uint32_t)rv); }\n";
+  }
+  o << "    // phase 2: antipodal pairs\n";
+  for (int t = 0; t < nP; ++t) {
+    const uint32_t pr = P.words[nV + nE + t];
+    o << "    E::pair(L, " << (pr & 0xFFFF) << ", " << (pr >> 16) << ");\n";
+  }
+  o << "    // phase 3: region ids and the region tree\n";
+  o << "    int nR = 0, root = -1;\n    uint32_t err = 0;\n";
+  for (int v = 0; v < nV; ++v) {
+    const int t = v > 0 ? (int)P.words[nV + (P.words[v] >> 16)] : -1;
+    o << "    E::vertex3(L, " << v << ", " << t << ", nR, root, err);\n";
+  }
+  o << "    return E::finish(L, nR, root, err, errs);\n  }\n};\n\n}  // namespace pw\n\n";
+  o << "extern \"C\" __global__ __launch_bounds__(256) void pw_jit_codes(const void* masks, int64_t n, "
+       "uint64_t* codes, uint32_t* errflag) {\n"
+       "  extern __shared__ uint32_t smem[];\n  pw::codes_body<"
+    << d << ">(pw::JitEval{}, masks, n, codes, errflag, smem);\n}\n";
+  o << "extern \"C\" __global__ __launch_bounds__(256) void pw_jit_hist(const void* masks, int64_t n, "
+       "uint64_t index_base, pw::HistDev h, uint32_t* errflag) {\n"
+       "  extern __shared__ uint32_t smem[];\n  pw::hist_body<"
+    << d << ">(pw::JitEval{}, masks, n, index_base, h, errflag, smem);\n}\n";
+  o << "extern \"C\" __global__ __launch_bounds__(256) void pw_jit_enum(uint64_t first, uint64_t count, "
+       "pw::Runs runs, pw::HistDev h, uint32_t* errflag) {\n"
+       "  extern __shared__ uint32_t smem[];\n  pw::enum_body<"
+    << d << ">(pw::JitEval{}, first, count, runs, h, errflag, smem);\n}\n";
+  return o.str();
+}
+
+namespace {
+
+const char* const kRtcNames[] = {kRtcHeaderName0, kRtcHeaderName1};
+const char* const kRtcTexts[] = {kRtcHeaderText0, kRtcHeaderText1};
+
+// hipRTC options: gfx950, no packed FP32 instructions (as for the library)
+const char* const kRtcOptions[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature",
+                                   "-Xclang", "-packed-fp32-ops"};
+
+pw_status compile(const std::string& src, std::vector<char>* code) {
+  hiprtcProgram prog;
+  if (hiprtcCreateProgram(&prog, src.c_str(), "pw_jit.hip", kRtcHeaderCount, kRtcTexts, kRtcNames) !=
+      HIPRTC_SUCCESS)
+    return set_err(PW_ERR_HIP, "hiprtcCreateProgram failed");
+  const hiprtcResult r = hiprtcCompileProgram(prog, (int)(sizeof kRtcOptions / sizeof *kRtcOptions), kRtcOptions);
+  if (r != HIPRTC_SUCCESS) {
+    size_t n = 0;
+    hiprtcGetProgramLogSize(prog, &n);
+    std::string log(n + 1, '\0');
+    hiprtcGetProgramLog(prog, &log[0]);
+    hiprtcDestroyProgram(&prog);
+    return set_err(PW_ERR_HIP, "hipRTC compile failed: %.400s", log.c_str());
+  }
+  size_t n = 0;
+  hiprtcGetCodeSize(prog, &n);
+  code->resize(n);
+  hiprtcGetCode(prog, code->data());
+  hiprtcDestroyProgram(&prog);
+  return PW_OK;
+}
+
+}  // namespace
+}  // namespace pw
+
+using namespace pw;
+
+extern "C" {
+
+pw_status pw_jit_source(int32_t d, const int16_t* edges_ij, int32_t n_edges, char* buf, int64_t cap, int64_t* len) {
+  if (!len) return set_err(PW_ERR_ARG, "null argument");
+  static thread_local HostProgram P;
+  char msg[256];
+  const int rc = build_program(d, edges_ij, n_edges, &P, msg, sizeof msg);
+  if (rc != 0) return set_err(rc, "%s", msg);
+  const std::string s = jit_source(P);
+  *len = (int64_t)s.size();
+  if (buf && cap > 0) {
+    const int64_t n = std::min<int64_t>(cap - 1, (int64_t)s.size());
+    std::memcpy(buf, s.data(), (size_t)n);
+    buf[n] = '\0';
+  }
+  return PW_OK;
+}
+
+pw_status pw_jit_compile(int32_t d, const int16_t* edges_ij, int32_t n_edges, int64_t* code_bytes) {
+  if (d > kJitMaxDegree) return set_err(PW_ERR_ARG, "specialised kernels exist for d <= %d", kJitMaxDegree);
+  static thread_local HostProgram P;
+  char msg[256];
+  const int brc = build_program(d, edges_ij, n_edges, &P, msg, sizeof msg);
+  if (brc != 0) return set_err(brc, "%s", msg);
+  std::vector<char> code;
+  const pw_status rc = compile(jit_source(P), &code);
+  if (rc == PW_OK && code_bytes) *code_bytes = (int64_t)code.size();
+  return rc;
+}
+
+pw_status pw_tri_specialize(pw_tri_t t) {
+  if (!t) return set_err(PW_ERR_ARG, "null handle");
+  if (t->prog.d > kJitMaxDegree) return set_err(PW_ERR_ARG, "specialised kernels exist for d <= %d", kJitMaxDegree);
+  if (t->jit_mod) return PW_OK;
+  std::vector<char> code;
+  const pw_status rc = compile(jit_source(t->prog), &code);
+  if (rc != PW_OK) return rc;
+  hipModule_t mod = nullptr;
+  PW_HIP(hipModuleLoadData(&mod, code.data()));
+  hipFunction_t fc = nullptr, fh = nullptr, fe = nullptr;
+  hipError_t e = hipModuleGetFunction(&fc, mod, "pw_jit_codes");
+  if (e == hipSuccess) e = hipModuleGetFunction(&fh, mod, "pw_jit_hist");
+  if (e == hipSuccess) e = hipModuleGetFunction(&fe, mod, "pw_jit_enum");
+  if (e != hipSuccess) {
+    (void)hipModuleUnload(mod);
+    return set_err(PW_ERR_HIP, "%s (code %d)", hipGetErrorString(e), (int)e);
+  }
+  t->jit_mod = mod;
+  t->jit_codes = fc;
+  t->jit_hist = fh;
+  t->jit_enum = fe;
+  return PW_OK;
+}
+
+}  // extern "C"

@@ -189,13 +189,24 @@ __global__ void k_softmax_xent(const float* __restrict__ Y, const int32_t* __res
   atomicAdd(loss, l / (float)n);
 }
 
-// out[j] = sum_k X[k][j]  (bias gradients), one thread per column
+// out[j] = sum_k X[k][j]  (bias gradients): block (x, y) sums rows
+// [256 y, 256 y + 256) of columns [256 x, 256 x + 256) and adds its partial
+// sums to out, which k_fill zeroed first.
+constexpr int kColRows = 256;
+
+__global__ void k_fill(float* __restrict__ x, int64_t n, float v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
 __global__ void k_colsum(const float* __restrict__ X, int64_t n, int cols, float* __restrict__ out) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= cols) return;
+  const int64_t r0 = (int64_t)blockIdx.y * kColRows;
+  const int64_t r1 = r0 + kColRows < n ? r0 + kColRows : n;
   float s = 0.f;
-  for (int64_t k = 0; k < n; ++k) s += X[k * cols + j];
-  out[j] = s;
+  for (int64_t k = r0; k < r1; ++k) s += X[k * cols + j];
+  atomicAdd(&out[j], s);
 }
 
 // Adam (Kingma & Ba, 2015) on fp32 master weights, refreshing the bf16 copy.
@@ -360,7 +371,10 @@ pw_status pw_mlp_softmax_xent(const float* Y, const int32_t* labels, int64_t n, 
 
 pw_status pw_mlp_colsum(const float* X, int64_t n, int32_t cols, float* out, hipStream_t s) {
   if (n < 0 || cols <= 0 || !X || !out) return set_err(PW_ERR_ARG, "bad colsum arguments");
-  hipLaunchKernelGGL(k_colsum, dim3(grid1d(cols, 64)), dim3(64), 0, s, X, n, cols, out);
+  hipLaunchKernelGGL(k_fill, dim3(grid1d(cols, 256)), dim3(256), 0, s, out, (int64_t)cols, 0.f);
+  if (n == 0) return PW_OK;
+  hipLaunchKernelGGL(k_colsum, dim3(grid1d(cols, 256), (unsigned)((n + kColRows - 1) / kColRows)), dim3(256), 0, s,
+                     X, n, cols, out);
   PW_HIP(hipGetLastError());
   return PW_OK;
 }

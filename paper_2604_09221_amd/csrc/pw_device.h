@@ -412,36 +412,27 @@ __device__ __forceinline__ typename Cfg<D>::Mask load_mask(const void* __restric
   }
 }
 
+constexpr int kMaxRuns = 4;
+
+// The free bit positions of an enumeration as at most kMaxRuns contiguous
+// runs: index bits [src, src+len) go to mask bits [dst, dst+len).
 struct Runs {
   int n;
-  uint8_t src[8], len[8], dst[8];
+  uint8_t src[kMaxRuns], len[kMaxRuns], dst[kMaxRuns];
 };
-
-// Runs unpacked into wave-uniform scalars once per kernel.
-struct RunRegs {
-  int n;
-  int src[8], dst[8];
-  uint64_t keep[8];
-};
-
-__device__ __forceinline__ RunRegs unpack_runs(const Runs& r) {
-  RunRegs q;
-  q.n = r.n;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    q.src[k] = r.src[k];
-    q.dst[k] = r.dst[k];
-    q.keep[k] = r.len[k] >= 64 ? ~0ull : ((1ull << r.len[k]) - 1);
-  }
-  return q;
-}
 
 template <typename Mask>
-__device__ __forceinline__ Mask deposit(uint64_t idx, const RunRegs& r) {
-  Mask m = 0;
+__device__ __forceinline__ Mask deposit(uint64_t idx, const Runs& r) {
+  const uint64_t keep0 = r.len[0] >= 64 ? ~0ull : ((1ull << r.len[0]) - 1);
+  Mask m = (Mask)((idx >> r.src[0]) & keep0) << r.dst[0];
+  if (r.n > 1) {  // uniform branch: only class-representative sweeps take it
 #pragma unroll
-  for (int k = 0; k < 8; ++k)
-    if (k < r.n) m |= (Mask)((idx >> r.src[k]) & r.keep[k]) << r.dst[k];
+    for (int k = 1; k < kMaxRuns; ++k)
+      if (k < r.n) {
+        const uint64_t keep = r.len[k] >= 64 ? ~0ull : ((1ull << r.len[k]) - 1);
+        m |= (Mask)((idx >> r.src[k]) & keep) << r.dst[k];
+      }
+  }
   return m;
 }
 
@@ -652,7 +643,6 @@ __device__ __forceinline__ void enum_body(const EV& ev, uint64_t first, uint64_t
   const Lane L = lane_memory(smem, C::LANE_WORDS);
   WaveTable tab;
   tab.clear();
-  const RunRegs rr = unpack_runs(runs);
   uint32_t errs = 0;
   const uint64_t waves_total = (uint64_t)gridDim.x * (blockDim.x >> 6);
   for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + wave) * 64; base < count;
@@ -660,7 +650,7 @@ __device__ __forceinline__ void enum_body(const EV& ev, uint64_t first, uint64_t
     const uint64_t k = base + lane;
     const bool valid = k < count;
     const uint64_t idx = first + k;
-    const typename C::Mask m = deposit<typename C::Mask>(idx, rr);
+    const typename C::Mask m = deposit<typename C::Mask>(idx, runs);
     const u128 code = ev(m, L, errs);
     tab.add_batch((uint64_t)code, (uint64_t)(code >> 64), valid, idx, lane, h);
   }

@@ -14,6 +14,9 @@ struct pw_tri {
   uint32_t* d_prog = nullptr;
   uint32_t* d_err = nullptr;
   int device = 0;
+  // kernels specialised to this triangulation (pw_tri_specialize), or null
+  hipModule_t jit_mod = nullptr;
+  hipFunction_t jit_codes = nullptr, jit_hist = nullptr, jit_enum = nullptr;
 };
 
 struct pw_hist {
@@ -33,6 +36,10 @@ __attribute__((format(printf, 2, 3))) pw_status set_err(pw_status code, const ch
 
 // Number of compute units of the current device (256 on MI355X).
 int cu_count();
+
+// Degrees for which pw_tri_specialize builds kernels (a block's LDS stays
+// within the default 64 KiB of a module launch).
+constexpr int kJitMaxDegree = 9;
 
 }  // namespace pw
 

@@ -15,7 +15,9 @@
 //   words [nV, nV+nE)               earlier-neighbour ids (one per word)
 //   words [nV+nE, nV+nE+nP)         antipodal pairs a | b << 16, a < b
 #pragma once
+#if !defined(__HIPCC_RTC__)
 #include <cstdint>
+#endif
 
 namespace pw {
 
@@ -35,6 +37,7 @@ constexpr uint32_t kErrRoot = 2u;      // no unique root
 constexpr uint32_t kErrTree = 4u;      // adjacency graph is not a tree
 constexpr uint32_t kErrSelfLoop = 8u;  // self-loop for even d
 
+#if !defined(__HIPCC_RTC__)
 struct HostProgram {
   int d = 0, nA = 0, nV = 0, nE = 0, nP = 0;
   std::uint32_t words[kVMax + kEMax + 2 * kDMax];
@@ -44,5 +47,6 @@ struct HostProgram {
 // Validates the edge list and fills `prog`.  Returns 0 or a negative
 // pw_status, with a message in `err`.
 int build_program(int d, const int16_t* edges_ij, int n_edges, HostProgram* prog, char* err, int errlen);
+#endif
 
 }  // namespace pw

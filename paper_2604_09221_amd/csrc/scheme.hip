@@ -100,6 +100,15 @@ pw_status launch_codes(const pw_tri* t, const void* masks, int64_t n, uint64_t* 
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_codes<D>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   });
+  if (t->jit_codes) {
+    const void* m_ = masks;
+    uint64_t* c_ = codes;
+    uint32_t* e_ = t->d_err;
+    void* args[] = {&m_, &n, &c_, &e_};
+    PW_HIP(hipModuleLaunchKernel(t->jit_codes, blocks_for<D>(threads, n), 1, 1, threads, 1, 1, (unsigned)lds, s, args,
+                                 nullptr));
+    return PW_OK;
+  }
   hipLaunchKernelGGL(k_codes<D>, dim3(blocks_for<D>(threads, n)), dim3(threads), lds, s, t->d_prog, masks, n,
                      codes, t->d_err);
   PW_HIP(hipGetLastError());
@@ -117,6 +126,15 @@ pw_status launch_hist(const pw_tri* t, const void* masks, int64_t n, uint64_t ba
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hist<D>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   });
+  if (t->jit_hist) {
+    const void* m_ = masks;
+    HistDev hd = h->dev();
+    uint32_t* e_ = t->d_err;
+    void* args[] = {&m_, &n, &base, &hd, &e_};
+    PW_HIP(hipModuleLaunchKernel(t->jit_hist, blocks_for<D>(threads, n), 1, 1, threads, 1, 1, (unsigned)lds, s, args,
+                                 nullptr));
+    return PW_OK;
+  }
   hipLaunchKernelGGL(k_hist<D>, dim3(blocks_for<D>(threads, n)), dim3(threads), lds, s, t->d_prog, masks, n, base,
                      h->dev(), t->d_err);
   PW_HIP(hipGetLastError());
@@ -135,6 +153,15 @@ pw_status launch_enum(const pw_tri* t, uint64_t first, uint64_t count, const Run
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   });
   const int64_t n = count > (uint64_t)INT64_MAX ? INT64_MAX : (int64_t)count;
+  if (t->jit_enum) {
+    Runs r_ = runs;
+    HistDev hd = h->dev();
+    uint32_t* e_ = t->d_err;
+    void* args[] = {&first, &count, &r_, &hd, &e_};
+    PW_HIP(hipModuleLaunchKernel(t->jit_enum, blocks_for<D>(threads, n), 1, 1, threads, 1, 1, (unsigned)lds, s, args,
+                                 nullptr));
+    return PW_OK;
+  }
   hipLaunchKernelGGL(k_enum<D>, dim3(blocks_for<D>(threads, n)), dim3(threads), lds, s, t->d_prog, first, count,
                      runs, h->dev(), t->d_err);
   PW_HIP(hipGetLastError());
@@ -200,6 +227,7 @@ pw_status pw_tri_create(int32_t d, const int16_t* edges_ij, int32_t n_edges, pw_
 
 pw_status pw_tri_destroy(pw_tri_t t) {
   if (!t) return PW_OK;
+  if (t->jit_mod) (void)hipModuleUnload(t->jit_mod);
   (void)hipFree(t->d_prog);
   (void)hipFree(t->d_err);
   delete t;
@@ -346,7 +374,7 @@ pw_status patchwork_scheme_enumerate_range(pw_tri_t t, uint64_t first, uint64_t 
     }
     int e = b;
     while (e < nA && !((fixed_zero_bits[e / 64] >> (e % 64)) & 1)) ++e;
-    if (runs.n == 8) return set_err(PW_ERR_ARG, "the free bits form more than 8 runs");
+    if (runs.n == kMaxRuns) return set_err(PW_ERR_ARG, "the free bits form more than %d runs", kMaxRuns);
     runs.src[runs.n] = (uint8_t)nfree;
     runs.len[runs.n] = (uint8_t)(e - b);
     runs.dst[runs.n] = (uint8_t)b;

@@ -248,31 +248,15 @@ def select(scores, cands, threshold, cap):
     return out[:k]
 
 
-class SchemeBook:
-    """Host record of the schemes seen: code -> [count, one witness mask]."""
+def rarest_witnesses(hist, archive, k):
+    """Masks of the k schemes seen least often (witness = index into the
+    device archive of judged masks)."""
+    import torch
 
-    def __init__(self):
-        self.book = {}
-        self.curve = []          # (evaluations, distinct)
-        self.evals = 0
-
-    def add(self, masks, codes):
-        m = masks.cpu().numpy().view(np.uint64)
-        c = codes.cpu().numpy().view(np.uint64)
-        keys, first, counts = np.unique(c, axis=0, return_index=True, return_counts=True)
-        for (lo, hi), f, n in zip(keys, first, counts):
-            k = (int(lo), int(hi))
-            e = self.book.get(k)
-            if e is None:
-                self.book[k] = [int(n), m[f].copy()]
-            else:
-                e[0] += int(n)
-        self.evals += len(c)
-        self.curve.append((self.evals, len(self.book)))
-
-    def rarest(self, k):
-        items = sorted(self.book.values(), key=lambda e: e[0])[:k]
-        return np.stack([e[1] for e in items])
+    h = hist.read()
+    ranked = sorted(h.items(), key=lambda kv: kv[1][0])[:k]
+    idx = torch.tensor([w for _, (_, w) in ranked], dtype=torch.int64, device=archive.device)
+    return archive[idx], len(h)
 
 
 def run_uniform(tri, d, budget, chunk=1 << 22, seed=1):
@@ -295,32 +279,41 @@ def run_uniform(tri, d, budget, chunk=1 << 22, seed=1):
     return {"method": "uniform", "evaluations": done, "distinct": len(hist.read()), "gpu_seconds": dt}
 
 
-def run_search(tri, d, budget, use_net=True, train_n=1 << 22, epochs=2, batch=4096, per_round=1 << 21,
-               oversample=4, n_elite=4096, seed=7, log=None):
+def run_search(tri, d, budget, use_net=True, train_n=1 << 22, epochs=1, batch=16384, per_round=1 << 21,
+               oversample=2, n_elite=4096, seed=7, log=None):
     """Mutation search from the rarest schemes seen, ranked by the network
     (use_net) or at random (the ablation).  Every proposal is judged by the
-    exact kernel; the training masks count against the budget too."""
+    exact kernel (histogram mode, witnesses = indices into a device archive
+    of the judged masks); the training masks count against the budget."""
     import torch
 
     nA = (d + 1) * (d + 2) // 2
     wide = pw.mask_bytes(d) == 16
-    book = SchemeBook()
+    archive = torch.empty((budget, 2), dtype=torch.int64, device="cuda")
+    hist = pw.Histogram(1 << 14)
+    curve = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+
+    def judge(masks, at):
+        archive[at:at + masks.shape[0]] = masks
+        tri.histogram(masks if wide else masks[:, 0].contiguous(), hist, index_base=at)
+        return at + masks.shape[0]
+
     # labelled data from uniform masks (judged, counted)
     m = random_masks(seed, 0, train_n, nA)
-    codes = tri.batch(m if wide else m[:, 0].contiguous())
-    book.add(m, codes)
+    used = judge(m, 0)
     net = None
     rarity = None
     score_hi = 1.0
     if use_net:
+        codes = tri.batch(m if wide else m[:, 0].contiguous())
         lab = features(codes)
         X = encode(m, train_n, nA)
         net = MLP(n_in=nA, seed=seed)
         for ep in range(epochs):
             for a in range(0, train_n - batch + 1, batch):
-                net.train_step(X[a:a + batch], lab[a:a + batch], lr=1e-3)
+                net.train_step(X[a:a + batch], lab[a:a + batch], lr=2e-3)
         labels = lab.cpu().numpy()
         r = np.zeros(OUT, dtype=np.float32)
         st = np.concatenate([[0], np.cumsum(HEADS)])
@@ -330,28 +323,30 @@ def run_search(tri, d, budget, use_net=True, train_n=1 << 22, epochs=2, batch=40
             r[st[h]:st[h + 1]] = -np.log(p)
         rarity = torch.from_numpy(r).cuda()
         score_hi = float(sum(r[st[h]:st[h + 1]].max() for h in range(6)))
+    torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     rnd = 0
-    while book.evals < budget:
+    while used < budget:
         rnd += 1
-        k = min(per_round, budget - book.evals)
-        parents = torch.from_numpy(book.rarest(n_elite).view(np.int64)).cuda()
+        k = min(per_round, budget - used)
+        parents, distinct = rarest_witnesses(hist, archive, n_elite)
+        curve.append((used, distinct))
         cand = mutate(parents, k * (oversample if use_net else 1), nA, 1 + rnd % 3, seed * 1000003 + rnd)
         if use_net:
             Y = net.forward(encode(cand, cand.shape[0], nA))
             sc = score(Y, rarity)
-            thr = top_threshold(sc, k, 0.0, score_hi)
-            sel = select(sc, cand, thr, k)
+            sel = select(sc, cand, top_threshold(sc, k, 0.0, score_hi), k)
             if sel.shape[0] == 0:
                 sel = cand[:k]
         else:
             sel = cand[:k]          # random ranking: the mutants are already in random order
-        codes = tri.batch(sel if wide else sel[:, 0].contiguous())
-        book.add(sel, codes)
+        used = judge(sel, used)
         if log and rnd % 16 == 0:
-            log(f"round {rnd}: {book.evals} evaluations, {len(book.book)} schemes")
+            log(f"round {rnd}: {used} evaluations, {distinct} schemes")
+    final = len(hist.read())
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return {"method": "learned" if use_net else "ablation (random ranking)", "evaluations": book.evals,
-            "distinct": len(book.book), "gpu_seconds": dt, "train_seconds": train_s, "rounds": rnd,
-            "curve": book.curve[:: max(1, len(book.curve) // 32)]}
+    curve.append((used, final))
+    return {"method": "learned" if use_net else "ablation (random ranking)", "evaluations": used,
+            "distinct": final, "gpu_seconds": dt, "train_seconds": train_s, "rounds": rnd,
+            "curve": curve[:: max(1, len(curve) // 32)] + ([curve[-1]] if len(curve) > 32 else [])}

@@ -66,11 +66,16 @@ def lib():
     L.pw_hist_destroy.argtypes = [vp]
     L.patchwork_scheme_histogram.argtypes = [vp, vp, i64, u64, vp, vp]
     L.patchwork_scheme_enumerate_range.argtypes = [vp, u64, u64, u64p, vp, vp]
+    L.pw_tri_specialize.argtypes = [vp]
+    i16p = ctypes.POINTER(ctypes.c_int16)
+    L.pw_jit_source.argtypes = [i32, i16p, i32, ctypes.c_char_p, i64, ctypes.POINTER(ctypes.c_int64)]
+    L.pw_jit_compile.argtypes = [i32, i16p, i32, ctypes.POINTER(ctypes.c_int64)]
     L.patchwork_scheme_batch_multi.argtypes = [ctypes.POINTER(vp), i32, vp, ctypes.POINTER(ctypes.c_int64),
                                                ctypes.POINTER(vp), vp, ctypes.POINTER(MultiConfig), vp]
     for name in ("pw_tri_create", "pw_tri_destroy", "pw_tri_info", "pw_tri_errors", "patchwork_scheme_batch",
                  "pw_hist_create", "pw_hist_reset", "pw_hist_read", "pw_hist_destroy",
-                 "patchwork_scheme_histogram", "patchwork_scheme_enumerate_range", "patchwork_scheme_batch_multi"):
+                 "patchwork_scheme_histogram", "patchwork_scheme_enumerate_range", "patchwork_scheme_batch_multi",
+                 "pw_tri_specialize", "pw_jit_source", "pw_jit_compile"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -151,6 +156,11 @@ class Triangulation:
         return dict(zip(("d", "n_points", "n_vertices", "n_diamond_edges", "n_antipodal_pairs"),
                         (x.value for x in v)))
 
+    def specialize(self):
+        """Build and load kernels specialised to this triangulation."""
+        check(lib().pw_tri_specialize(self.handle))
+        return self
+
     def errors(self) -> int:
         f = ctypes.c_uint32()
         check(lib().pw_tri_errors(self.handle, ctypes.byref(f)))
@@ -175,6 +185,29 @@ class Triangulation:
         fz = (ctypes.c_uint64 * 2)(fixed_zero_bits & 0xFFFFFFFFFFFFFFFF, fixed_zero_bits >> 64)
         check(lib().patchwork_scheme_enumerate_range(self.handle, int(first), int(count), fz, hist.handle,
                                                      _stream(stream)))
+
+
+def _edges16(edges):
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int16).reshape(-1, 4))
+    return e, e.ctypes.data_as(ctypes.POINTER(ctypes.c_int16))
+
+
+def jit_source(d: int, edges) -> str:
+    """Source of the kernels specialised to one triangulation."""
+    e, p = _edges16(edges)
+    n = ctypes.c_int64()
+    check(lib().pw_jit_source(d, p, len(e), None, 0, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value + 1)
+    check(lib().pw_jit_source(d, p, len(e), buf, n.value + 1, ctypes.byref(n)))
+    return buf.value.decode()
+
+
+def jit_compile(d: int, edges) -> int:
+    """Compile (not load) the specialised kernels; code object bytes."""
+    e, p = _edges16(edges)
+    n = ctypes.c_int64()
+    check(lib().pw_jit_compile(d, p, len(e), ctypes.byref(n)))
+    return n.value
 
 
 class Histogram:

@@ -89,3 +89,16 @@ def test_null_arguments_rejected():
     assert L.pw_hist_create(100, ctypes.byref(ctypes.c_void_p())) == pw.PW_ERR_ARG   # not a power of two
     assert L.pw_hist_read(None, None, None, None, 0, None) == pw.PW_ERR_ARG
     assert L.pw_last_error()
+
+
+def test_specialized_source_compiles_for_gfx950():
+    """The generated per-triangulation source compiles with hipRTC (no GPU
+    needed) and names the literal program of the triangulation."""
+    d = 3
+    E = I.standard_triangulation(d)
+    src = pw.jit_source(d, E)
+    assert "struct JitEval" in src and src.count("E::vertex3(") == 2 * d * d + 2 * d + 1
+    assert src.count("E::pair(") == 2 * d
+    assert pw.jit_compile(d, E) > 0
+    with pytest.raises(pw.PatchworkError):
+        pw.jit_compile(10, I.standard_triangulation(10))       # above the specialised range

@@ -38,17 +38,17 @@ def test_network_ranking_beats_random_ranking():
     for h in range(6):
         p = np.bincount(labels[:, h], minlength=Lr.HEADS[h]).astype(np.float64) + 0.5
         rar[st[h]:st[h + 1]] = -np.log(p / p.sum())
-    book = Lr.SchemeBook()
-    book.add(m, codes)
-    seen = set(book.book)
-    parents = torch.from_numpy(book.rarest(2048).view(np.int64)).cuda()
+    hist = pw.Histogram(1 << 12)
+    tri.histogram(m[:, 0].contiguous(), hist)
+    seen = set(hist.read())
+    parents, _ = Lr.rarest_witnesses(hist, m, 2048)
     cand = Lr.mutate(parents, 1 << 16, nA, 2, 12345)
     sc = Lr.score(net.forward(Lr.encode(cand, cand.shape[0], nA)), torch.from_numpy(rar).cuda()).cpu().numpy()
     true_codes = tri.batch(cand[:, 0].contiguous())
     tl = Lr.features(true_codes).cpu().numpy()
     true_rarity = sum(rar[st[h] + tl[:, h]] for h in range(6))
     c = true_codes.cpu().numpy().view(np.uint64)
-    novel = np.array([(int(a), int(b)) not in seen for a, b in c])
+    novel = np.array([(int(a) | (int(b) << 64)) not in seen for a, b in c])
     k = len(sc) // 10
     top = np.argsort(-sc)[:k]
     rnd = np.random.default_rng(0).choice(len(sc), k, replace=False)

@@ -240,3 +240,29 @@ def test_edge_cases(pw):
     want = oracle.scheme_many(d, E, masks, threads=THREADS)
     assert reps.read() == oracle_hist(want)
     assert tri.errors() == 0
+
+
+# ------------------------------------------------- specialised kernels (hipRTC)
+
+def test_specialized_kernels_match_oracle(pw):
+    """Kernels generated for one triangulation: codes, histograms and
+    witnesses bit-exact against the oracle (and hence the generic path)."""
+    cases = [(4, I.lift_triangulation(4, 2, noise=1.0), 1 << 14),
+             (7, I.standard_triangulation(7), 1 << 18),
+             (8, fig2_edges("rank016"), 1 << 16)]
+    for d, E, n in cases:
+        tri = pw.Triangulation(d, E).specialize()
+        masks = I.random_masks(d, d, n + 7)
+        out = tri.batch(pw.mask_tensor(masks, d))
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy().view(np.uint64), oracle.scheme_many(d, E, masks, threads=THREADS))
+        hist = pw.Histogram(1024)
+        tri.enumerate_range(1000, n, hist)
+        emasks = enum_masks(1000, n, nA=I.n_points(d))
+        want = oracle.scheme_many(d, E, emasks, threads=THREADS)
+        assert hist.read() == oracle_hist(want, index_of=np.arange(1000, 1000 + n, dtype=np.uint64))
+        h2 = pw.Histogram(1024)
+        tri.histogram(pw.mask_tensor(masks, d), h2, index_base=5)
+        assert h2.read() == oracle_hist(oracle.scheme_many(d, E, masks, threads=THREADS),
+                                        index_of=np.arange(5, 5 + len(masks), dtype=np.uint64))
+        assert tri.errors() == 0
