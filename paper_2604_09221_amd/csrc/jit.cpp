@@ -38,9 +38,10 @@ std::string jit_source(const HostProgram& P) {
   for (int v = 0; v < nV; ++v) {
     const uint32_t rec = P.words[v];
     const int p = rec & 0x7F, g = (rec >> 7) & 1, n = (rec >> 8) & 0xFF, off = rec >> 16;
-    o << "    { const uint32_t sv = E::bit(m, " << p << ")" << (g ? " ^ 1u" : "") << "; int rv = " << v << ";";
+    o << "    { const uint32_t sv = E::bit(m, " << p << ")" << (g ? " ^ 1u" : "") << "; uint32_t rv = off_of(" << v
+      << ");";
     for (int k = 0; k < n; ++k) o << " E::edge(L, sv, " << v << ", rv, " << P.words[nV + off + k] << ");";
-    o << " L.ent(" << v << ") = (uint16_t)((sv << kSignShift) | (uint32_t)rv); }\n";
+    o << " L.ent(" << v << ") = (uint16_t)(rv | sv); }\n";
   }
   o << "    // phase 2: antipodal pairs\n";
   for (int t = 0; t < nP; ++t) {

@@ -61,9 +61,39 @@ struct GemmArgs {
   int accumulate;  // C32 += result
 };
 
+// Staging of one 64 x 32 tile of A ([m][k] in LDS) and of B ([n][k] in
+// LDS).  A_K / B_K: the operand is contiguous along k (a_k == 1 / b_k == 1),
+// so each thread moves 8 consecutive bf16 with one 16-byte load and one
+// 16-byte LDS store; A_M / B_N: contiguous along m / n, 16-byte loads
+// scattered into the k-contiguous LDS tile; otherwise element by element.
+struct u16x8 {
+  uint16_t v[8];
+};
+
+template <int MODE>  // 0 generic, 1 contiguous along k, 2 contiguous along the other index
+__device__ __forceinline__ void stage(uint16_t (*T)[TBK + 8], const uint16_t* __restrict__ X, int64_t s_row,
+                                      int64_t s_k, int r0, int k0, int tid) {
+  if (MODE == 1) {
+    const int r = tid >> 2, c = (tid & 3) * 8;  // 64 rows x 4 chunks of 8
+    *reinterpret_cast<u16x8*>(&T[r][c]) =
+        *reinterpret_cast<const u16x8*>(&X[(int64_t)(r0 + r) * s_row + (int64_t)(k0 + c)]);
+  } else if (MODE == 2) {
+    const int c = tid >> 3, r = (tid & 7) * 8;  // 32 k x 8 chunks of 8 rows
+    const u16x8 w = *reinterpret_cast<const u16x8*>(&X[(int64_t)(k0 + c) * s_k + (int64_t)(r0 + r)]);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) T[r + q][c] = w.v[q];
+  } else {
+    for (int e = tid; e < TBM * TBK; e += 256) {
+      const int r = e / TBK, c = e % TBK;
+      T[r][c] = X[(int64_t)(r0 + r) * s_row + (int64_t)(k0 + c) * s_k];
+    }
+  }
+}
+
+template <int AM, int BM_>
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
-  __shared__ uint16_t As[TBM][TBK + 4];  // [m][k]
-  __shared__ uint16_t Bs[TBN][TBK + 4];  // [n][k] (transposed for k-contiguous fragments)
+  __shared__ __attribute__((aligned(16))) uint16_t As[TBM][TBK + 8];  // [m][k]
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[TBN][TBK + 8];  // [n][k]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.y * TBM, n0 = blockIdx.x * TBN;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -71,12 +101,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = float4_t{0.f, 0.f, 0.f, 0.f};
   for (int k0 = 0; k0 < g.K; k0 += TBK) {
-    // stage A and B tiles: 64 x 32 elements each, 8 per thread
-    for (int e = tid; e < TBM * TBK; e += 256) {
-      const int r = e / TBK, c = e % TBK;
-      As[r][c] = g.A[(int64_t)(m0 + r) * g.a_m + (int64_t)(k0 + c) * g.a_k];
-      Bs[r][c] = g.B[(int64_t)(k0 + c) * g.b_k + (int64_t)(n0 + r) * g.b_n];
-    }
+    stage<AM>(As, g.A, g.a_m, g.a_k, m0, k0, tid);
+    stage<BM_>(Bs, g.B, g.b_n, g.b_k, n0, k0, tid);
     __syncthreads();
     for (int ks = 0; ks < TBK; ks += 16) {
       const int kk = ks + 4 * (lane >> 4);
@@ -337,7 +363,22 @@ pw_status pw_mlp_gemm(const uint16_t* A, int64_t a_m, int64_t a_k, const uint16_
     return set_err(PW_ERR_ARG, "gemm sizes must be positive multiples of 64 (M, N) and 32 (K): %d %d %d", M, N, K);
   if (accumulate && !C32) return set_err(PW_ERR_ARG, "accumulate needs the fp32 output");
   GemmArgs g{A, a_m, a_k, B, b_k, b_n, M, N, K, bias, gate, g_m, relu, C32, C16, c_m, accumulate};
-  hipLaunchKernelGGL(k_gemm_bf16, dim3(N / TBN, M / TBM), dim3(256), 0, s, g);
+  // 16-byte staging needs 8-element alignment of the base and the strides
+  auto al = [](const void* p, int64_t s1) { return ((uintptr_t)p % 16 == 0) && (s1 % 8 == 0); };
+  const int am = (a_k == 1 && al(A, a_m)) ? 1 : ((a_m == 1 && al(A, a_k)) ? 2 : 0);
+  const int bm = (b_k == 1 && al(B, b_n)) ? 1 : ((b_n == 1 && al(B, b_k)) ? 2 : 0);
+  const dim3 grid(N / TBN, M / TBM);
+  switch (am * 3 + bm) {
+    case 0: hipLaunchKernelGGL((k_gemm_bf16<0, 0>), grid, dim3(256), 0, s, g); break;
+    case 1: hipLaunchKernelGGL((k_gemm_bf16<0, 1>), grid, dim3(256), 0, s, g); break;
+    case 2: hipLaunchKernelGGL((k_gemm_bf16<0, 2>), grid, dim3(256), 0, s, g); break;
+    case 3: hipLaunchKernelGGL((k_gemm_bf16<1, 0>), grid, dim3(256), 0, s, g); break;
+    case 4: hipLaunchKernelGGL((k_gemm_bf16<1, 1>), grid, dim3(256), 0, s, g); break;
+    case 5: hipLaunchKernelGGL((k_gemm_bf16<1, 2>), grid, dim3(256), 0, s, g); break;
+    case 6: hipLaunchKernelGGL((k_gemm_bf16<2, 0>), grid, dim3(256), 0, s, g); break;
+    case 7: hipLaunchKernelGGL((k_gemm_bf16<2, 1>), grid, dim3(256), 0, s, g); break;
+    default: hipLaunchKernelGGL((k_gemm_bf16<2, 2>), grid, dim3(256), 0, s, g); break;
+  }
   PW_HIP(hipGetLastError());
   return PW_OK;
 }

@@ -73,8 +73,8 @@ __global__ __launch_bounds__(256) void k_multi(const TriDesc* __restrict__ tris,
                                                unsigned long long base, const uint64_t* __restrict__ masks,
                                                uint64_t* __restrict__ codes, int lane_words) {
   extern __shared__ uint32_t smem[];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const Lane L{smem + wave * lane_words * 64 + lane};
+  const int lane = threadIdx.x & 63;
+  const Lane L = lane_memory(smem, lane_words);
   while (true) {
     unsigned long long tk = 0;
     if (lane == 0) tk = atomicAdd(ticket, 1ull);

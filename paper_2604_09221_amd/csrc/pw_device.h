@@ -3,15 +3,17 @@
 // mask (Alg. 1 of "Fast Isotopy Computation for T-Curves", Sec. 2), the
 // in-kernel mask generator and the two-level code histogram.
 //
-// LDS layout: each wave owns LANE_WORDS * 64 dwords; word k of lane l sits
-// at index k * 64 + l, so every lane always hits its own bank whatever the
-// per-lane index (conflict-free for uniform and divergent accesses alike).
+// LDS layout: each wave owns LANE_WORDS * 64 dwords.  Word k of lane l sits
+// at dword k * 64 + l (every lane in its own bank whatever the index) and
+// vertex entry v (u16) at byte v * 128 + 2 l (its own bank for a uniform v,
+// at most two lanes per bank for divergent parent pointers).
 //
 // Per mask (thread) the phases are:
 //   1 components  (Alg. 1 "compute connected components of same-sign
 //     vertices"): vertices in program order; each earlier neighbour with
-//     the same sign is unioned.  Entry of v (u16): bits 0..8 parent,
-//     bit 9 parity to parent, bit 10 odd-cycle flag (roots), bit 15 sign.
+//     the same sign is unioned.  Entry of v (u16): parent << 7 (the byte
+//     offset of the parent's entry), odd-cycle flag (roots), parity to the
+//     parent, sign.
 //     Links always go from the larger root to the smaller one, so every
 //     parent index is smaller than its child's.
 //   2 regions (Alg. 1 "coarsen into regions by identifying antipodal
@@ -98,21 +100,31 @@ struct Cfg {
 
 // ------------------------------------------------------------ lane memory
 
+// Vertex entries (u16) sit at byte v * 128 + 2 * lane of the wave's area
+// and hold  parent << 7 | odd-cycle flag << 2 | parity << 1 | sign.  The
+// parent field is therefore the byte offset of the parent's entry, so
+// following a parent pointer costs one AND and one add.  Word k of a lane
+// (region data, reused entry space) sits at byte k * 256 + 4 * lane.  For
+// uniform v every lane hits its own bank; for divergent parents at most two
+// lanes share a bank.
 struct Lane {
   uint32_t* w;  // word 0 of this lane; word k at w[k * 64]
+  char* e;      // entry 0 of this lane; entry v at e + v * 128
   __device__ __forceinline__ uint32_t& word(int k) const { return w[k * 64]; }
-  __device__ __forceinline__ uint16_t& ent(int v) const {
-    return reinterpret_cast<uint16_t*>(w + (v >> 1) * 64)[v & 1];
-  }
+  __device__ __forceinline__ uint16_t& ent(int v) const { return *reinterpret_cast<uint16_t*>(e + v * 128); }
+  __device__ __forceinline__ uint16_t& at(uint32_t off) const { return *reinterpret_cast<uint16_t*>(e + off); }
   __device__ __forceinline__ uint8_t& byte(int k, int b) const {
     return reinterpret_cast<uint8_t*>(w + k * 64)[b];
   }
 };
 
-constexpr uint32_t kParent = 0x1FFu;
-constexpr uint32_t kParity = 1u << 9;
-constexpr uint32_t kOdd = 1u << 10;
-constexpr int kSignShift = 15;
+constexpr uint32_t kIdx = 0xFF80u;  // parent (or region id) << 7
+constexpr int kIdxShift = 7;
+constexpr uint32_t kSign = 1u;
+constexpr uint32_t kParity = 2u;
+constexpr uint32_t kOdd = 4u;
+
+__device__ __forceinline__ uint32_t off_of(int v) { return (uint32_t)v << kIdxShift; }
 
 template <typename T>
 __device__ __forceinline__ int clz_t(T x);
@@ -183,46 +195,47 @@ struct Eval {
 
   __device__ static __forceinline__ uint32_t bit(Mask m, int p) { return (uint32_t)(m >> p) & 1u; }
 
-  // root of u (walk only), starting from its entry eu
-  __device__ static __forceinline__ int find(const Lane& L, int u, uint32_t eu, uint32_t& er) {
-    int r = (int)(eu & kParent);
+  // root of u (walk only), starting from its entry eu; returns the root's
+  // entry offset, er = the root's entry
+  __device__ static __forceinline__ uint32_t find(const Lane& L, int u, uint32_t eu, uint32_t& er) {
+    uint32_t r = eu & kIdx;
     er = eu;
-    if (r != u) {
-      er = L.ent(r);
-      while ((int)(er & kParent) != r) {
-        r = (int)(er & kParent);
-        er = L.ent(r);
+    if (r != off_of(u)) {
+      er = L.at(r);
+      while ((er & kIdx) != r) {
+        r = er & kIdx;
+        er = L.at(r);
       }
     }
     return r;
   }
 
-  // root and parity of u relative to its root
-  __device__ static __forceinline__ int find_parity(const Lane& L, int u, uint32_t& er, uint32_t& par) {
-    int r = u;
+  // root offset and parity of u relative to its root
+  __device__ static __forceinline__ uint32_t find_parity(const Lane& L, int u, uint32_t& er, uint32_t& par) {
+    uint32_t r = off_of(u);
     er = L.ent(u);
     par = 0;
-    while ((int)(er & kParent) != r) {
+    while ((er & kIdx) != r) {
       par ^= (er & kParity) ? 1u : 0u;
-      r = (int)(er & kParent);
-      er = L.ent(r);
+      r = er & kIdx;
+      er = L.at(r);
     }
     return r;
   }
 
-  // Phase 1 step: v's earlier neighbour u; sv = sign of v, rv = v's root so
-  // far (v itself until v is linked).
-  __device__ static __forceinline__ void edge(const Lane& L, uint32_t sv, int v, int& rv, int u) {
+  // Phase 1 step: v's earlier neighbour u; sv = sign of v, rv = offset of
+  // v's root so far (v's own until v is linked).
+  __device__ static __forceinline__ void edge(const Lane& L, uint32_t sv, int v, uint32_t& rv, int u) {
     const uint32_t eu = L.ent(u);
-    if ((eu >> kSignShift) == sv) {
+    if ((eu & kSign) == sv) {
       uint32_t er;
-      const int r = find(L, u, eu, er);
-      if (r != (int)(eu & kParent)) L.ent(u) = (uint16_t)((eu & ~kParent) | (uint32_t)r);
-      if (rv == v) {
+      const uint32_t r = find(L, u, eu, er);
+      if (r != (eu & kIdx)) L.ent(u) = (uint16_t)((eu & ~kIdx) | r);
+      if (rv == off_of(v)) {
         rv = r;
       } else if (r != rv) {
-        const int lo = r < rv ? r : rv, hi = r < rv ? rv : r;
-        L.ent(hi) = (uint16_t)((sv << kSignShift) | (uint32_t)lo);
+        const uint32_t lo = r < rv ? r : rv, hi = r < rv ? rv : r;
+        L.at(hi) = (uint16_t)(lo | sv);
         rv = lo;
       }
     }
@@ -231,17 +244,17 @@ struct Eval {
   // Phase 2 step: one antipodal pair (a, b).
   __device__ static __forceinline__ void pair(const Lane& L, int a, int b) {
     uint32_t ea, eb, pa, pb;
-    const int ra = find_parity(L, a, ea, pa);
-    const int rb = find_parity(L, b, eb, pb);
+    const uint32_t ra = find_parity(L, a, ea, pa);
+    const uint32_t rb = find_parity(L, b, eb, pb);
     if (ra == rb) {
-      if (C::EVEN && pa == pb) L.ent(ra) = (uint16_t)(ea | kOdd);
+      if (C::EVEN && pa == pb) L.at(ra) = (uint16_t)(ea | kOdd);
     } else {
       const bool a_lo = ra < rb;
-      const int lo = a_lo ? ra : rb, hi = a_lo ? rb : ra;
+      const uint32_t lo = a_lo ? ra : rb, hi = a_lo ? rb : ra;
       const uint32_t elo = a_lo ? ea : eb, ehi = a_lo ? eb : ea;
       const uint32_t par = C::EVEN ? ((pa ^ pb ^ 1u) ? kParity : 0u) : 0u;
-      L.ent(hi) = (uint16_t)((ehi & (1u << kSignShift)) | par | (uint32_t)lo);
-      if (ehi & kOdd) L.ent(lo) = (uint16_t)(elo | kOdd);
+      L.at(hi) = (uint16_t)((ehi & kSign) | par | lo);
+      if (ehi & kOdd) L.at(lo) = (uint16_t)(elo | kOdd);
     }
   }
 
@@ -254,12 +267,13 @@ struct Eval {
   // region of t(first vertex of B)" is exactly the region adjacency tree,
   // rooted at the region of vertex 0.  For odd d a crossed tree edge inside
   // one region crosses the pseudo-line: that region is the root (Alg. 1).
+  // The entry of v becomes region id << 7 | sign.
   __device__ static __forceinline__ void vertex3(const Lane& L, int v, int t, int& nR, int& root, uint32_t& err) {
     const uint32_t ev = L.ent(v);
-    const uint32_t sv = ev >> kSignShift;
-    const int p = (int)(ev & kParent);
+    const uint32_t sv = ev & kSign;
+    const uint32_t p = ev & kIdx;
     int cid;
-    if (p == v) {
+    if (p == off_of(v)) {
       cid = nR < C::RMAX ? nR : C::RMAX - 1;
       err |= nR < C::RMAX ? 0u : kErrRegions;
       ++nR;
@@ -267,19 +281,19 @@ struct Eval {
         if (root >= 0) err |= kErrRoot;
         root = cid;
       }
-      const int pc = t >= 0 ? (int)(L.ent(t) & kParent) : 0xFF;
+      const int pc = t >= 0 ? (int)(L.ent(t) >> kIdxShift) : 0xFF;
       L.byte(C::PAR_BASE + (cid >> 2), cid & 3) = (uint8_t)pc;
     } else {
-      cid = (int)(L.ent(p) & kParent);
+      cid = (int)(L.at(p) >> kIdxShift);
       if (!C::EVEN) {
         const uint32_t et = L.ent(t);
-        if ((et >> kSignShift) != sv && (int)(et & kParent) == cid) {
+        if ((et & kSign) != sv && (int)(et >> kIdxShift) == cid) {
           if (root >= 0 && root != cid) err |= kErrRoot;
           root = cid;
         }
       }
     }
-    L.ent(v) = (uint16_t)((sv << kSignShift) | (uint32_t)cid);
+    L.ent(v) = (uint16_t)(off_of(cid) | sv);
   }
 
   // Returns the scheme code (0 on a failed consistency check, with the
@@ -293,9 +307,9 @@ struct Eval {
       const uint32_t sv = bit(m, rec & 0x7F) ^ ((rec >> 7) & 1u);
       const int nn = (rec >> 8) & 0xFF;
       const int off = rec >> 16;
-      int rv = v;
+      uint32_t rv = off_of(v);
       for (int k = 0; k < nn; ++k) edge(L, sv, v, rv, (int)nbr[off + k]);
-      L.ent(v) = (uint16_t)((sv << kSignShift) | (uint32_t)rv);
+      L.ent(v) = (uint16_t)(rv | sv);
     }
     // phase 2: regions (antipodal identification)
     for (int t = 0; t < C::NP; ++t) pair(L, pairs[t] & 0xFFFF, pairs[t] >> 16);
@@ -306,7 +320,7 @@ struct Eval {
     return finish(L, nR, root, err, errs);
   }
 
-  __device__ static u128 finish(const Lane& L, int nR, int root, uint32_t err, uint32_t& errs) {
+  __device__ __forceinline__ static u128 finish(const Lane& L, int nR, int root, uint32_t err, uint32_t& errs) {
     if (root < 0) err |= kErrRoot;
     if (err) {
       errs |= err;
@@ -586,7 +600,8 @@ struct RtEval {
 
 __device__ __forceinline__ Lane lane_memory(uint32_t* smem, int lane_words) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  return Lane{smem + wave * lane_words * 64 + lane};
+  uint32_t* base = smem + wave * lane_words * 64;
+  return Lane{base + lane, reinterpret_cast<char*>(base) + 2 * lane};
 }
 
 // codes of n masks, one per thread, grid-stride

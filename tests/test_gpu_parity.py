@@ -257,10 +257,11 @@ def test_specialized_kernels_match_oracle(pw):
         torch.cuda.synchronize()
         assert np.array_equal(out.cpu().numpy().view(np.uint64), oracle.scheme_many(d, E, masks, threads=THREADS))
         hist = pw.Histogram(1024)
-        tri.enumerate_range(1000, n, hist)
-        emasks = enum_masks(1000, n, nA=I.n_points(d))
+        first = min(1000, (1 << (I.n_points(d) - 1)) - n)
+        tri.enumerate_range(first, n, hist)
+        emasks = enum_masks(first, n, nA=I.n_points(d))
         want = oracle.scheme_many(d, E, emasks, threads=THREADS)
-        assert hist.read() == oracle_hist(want, index_of=np.arange(1000, 1000 + n, dtype=np.uint64))
+        assert hist.read() == oracle_hist(want, index_of=np.arange(first, first + n, dtype=np.uint64))
         h2 = pw.Histogram(1024)
         tri.histogram(pw.mask_tensor(masks, d), h2, index_base=5)
         assert h2.read() == oracle_hist(oracle.scheme_many(d, E, masks, threads=THREADS),
