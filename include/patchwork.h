@@ -208,6 +208,113 @@ pw_status patchwork_scheme_batch_multi(const pw_tri_t *tris, int32_t n_tris, con
                                        const int64_t *offsets, const pw_hist_t *hists, uint64_t *d_codes,
                                        const pw_multi_config *cfg, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Learned proposal of sign distributions.
+ *
+ * Not a step of Alg. 1: the paper finds rare schemes by searching over
+ * triangulations and curated pools of witnesses (Sec. 3).  These calls build
+ * a proposal generator for that search: a multilayer perceptron
+ * (|A| -> 512 -> 512 -> 64, ReLU) trained on masks labelled by the exact
+ * kernels above, used to rank mutated witnesses; every proposal it keeps is
+ * then judged by patchwork_scheme_batch / _histogram.  All buffers are
+ * device memory owned by the caller; every call is asynchronous on `stream`
+ * and returns PW_ERR_ARG (nothing launched) on bad sizes or null buffers.
+ * bfloat16 values are uint16_t bit patterns (upper half of an IEEE binary32,
+ * rounded to nearest even).  Masks here are always two uint64 per mask.
+ * ---------------------------------------------------------------------- */
+
+/*
+ * C = A B (+ bias[n]) (ReLU) (* [gate > 0]) on gfx950 BF16 matrix cores with
+ * FP32 accumulation.  Element (m, k) of A is A[m * a_m + k * a_k], element
+ * (k, n) of B is B[k * b_k + n * b_n] (so one call serves X W, dY W^T and
+ * X^T dY); gate (M x N, row stride g_m) and bias (N floats) may be NULL.
+ * Output row stride c_m; C32 (fp32) and/or C16 (bf16), at least one;
+ * accumulate != 0 adds into C32.  M and N must be multiples of 64, K of 32.
+ */
+pw_status pw_mlp_gemm(const uint16_t *A, int64_t a_m, int64_t a_k, const uint16_t *B, int64_t b_k, int64_t b_n,
+                      int32_t M, int32_t N, int32_t K, const float *bias, const uint16_t *gate, int64_t g_m,
+                      int32_t relu, float *C32, uint16_t *C16, int64_t c_m, int32_t accumulate,
+                      hipStream_t stream);
+
+/*
+ * Network input: X[k][j] = +1 for sign '+' (bit j of mask k clear), -1 for
+ * '-', j < n_bits (bits in the point order of eq. (signs)); 0 in the padding
+ * columns n_bits <= j < width.  X is n x width bf16.
+ */
+pw_status pw_mlp_encode(const uint64_t *masks, int64_t n, int32_t n_bits, int32_t width, uint16_t *X,
+                        hipStream_t stream);
+
+/*
+ * Six feature classes of each scheme code (the code format of
+ * patchwork_scheme_batch, Sec. 2): number of ovals clamped to 22; deepest
+ * nesting clamped to 4; number of ovals at depth 1, 2, 3, 4 in the buckets
+ * 0,1,2,3,4,5-6,7-9,10-14,15+.  labels is n x 6 int32.
+ */
+pw_status pw_features(const uint64_t *codes, int64_t n, int32_t *labels, hipStream_t stream);
+
+/*
+ * Softmax cross-entropy of the six heads of Y (n x 64 fp32; heads are the
+ * column ranges [0,23) [23,28) [28,37) [37,46) [46,55) [55,64)) against
+ * labels (n x 6), averaged over n: adds the loss to *loss and writes
+ * dY = (softmax - onehot) / n as fp32 (dY32) and/or bf16 (dY16), each
+ * may be NULL.
+ */
+pw_status pw_mlp_softmax_xent(const float *Y, const int32_t *labels, int64_t n, float *dY32, uint16_t *dY16,
+                              float *loss, hipStream_t stream);
+
+/* out[j] = sum over rows k < n of X[k * cols + j] (bias gradients). */
+pw_status pw_mlp_colsum(const float *X, int64_t n, int32_t cols, float *out, hipStream_t stream);
+
+/*
+ * One Adam step (Kingma & Ba 2015, bias-corrected, step >= 1) on n fp32
+ * weights w with gradient g and moments m, v; refreshes the bf16 copy w16
+ * when it is not NULL.
+ */
+pw_status pw_mlp_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float beta1, float beta2,
+                      float eps, int32_t step, uint16_t *w16, hipStream_t stream);
+
+/* y[i] = x[i] rounded to bf16 (nearest even). */
+pw_status pw_to_bf16(const float *x, int64_t n, uint16_t *y, hipStream_t stream);
+
+/*
+ * Novelty score of each row of Y (n x 64 logits): the sum over the six heads
+ * of sum_j softmax(Y)_j * rarity[j] (rarity: 64 floats, e.g. -log of the
+ * class frequencies seen so far).
+ */
+pw_status pw_mlp_score(const float *Y, const float *rarity, int64_t n, float *score, hipStream_t stream);
+
+/*
+ * Mutants: out[k] = parents[k mod n_parents] with `flips` bit positions in
+ * [1, n_bits) toggled, each drawn from the SplitMix64 finaliser applied to a
+ * key of (seed, k, flip index); bit 0 (sigma(0,0) = '+') is never touched.
+ */
+pw_status pw_mutate(const uint64_t *parents, int64_t n_parents, int64_t n, int32_t n_bits, int32_t flips,
+                    uint64_t seed, uint64_t *out, hipStream_t stream);
+
+/*
+ * Uniform masks: word w of mask k is the SplitMix64 output number
+ * 2 (offset + k) + w of the stream seeded with `seed`; bits >= n_bits and
+ * bit 0 cleared.
+ */
+pw_status pw_random_masks(uint64_t seed, uint64_t offset, int64_t n, int32_t n_bits, uint64_t *out,
+                          hipStream_t stream);
+
+/*
+ * counts[b] += number of x[k] in [lo + b w, lo + (b+1) w), w = (hi - lo) /
+ * bins; values outside [lo, hi) count in the end bins.  Used to find a
+ * score threshold for the top fraction of candidates.
+ */
+pw_status pw_bin_floats(const float *x, int64_t n, float lo, float hi, int32_t bins, uint32_t *counts,
+                        hipStream_t stream);
+
+/*
+ * Copies the candidates with score > threshold into out, in no particular
+ * order, up to cap of them; *count (device, zeroed by the caller) receives
+ * the number that passed, which may exceed cap.
+ */
+pw_status pw_select(const float *score, const uint64_t *cand, int64_t n, float threshold, uint64_t *out,
+                    int64_t cap, unsigned long long *count, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif
