@@ -38,10 +38,10 @@ std::string jit_source(const HostProgram& P) {
   for (int v = 0; v < nV; ++v) {
     const uint32_t rec = P.words[v];
     const int p = rec & 0x7F, g = (rec >> 7) & 1, n = (rec >> 8) & 0xFF, off = rec >> 16;
-    o << "    { const uint32_t sv = E::bit(m, " << p << ")" << (g ? " ^ 1u" : "") << "; uint32_t rv = off_of(" << v
+    o << "    { const uint32_t sv = E::bit(m, " << p << ")" << (g ? " ^ 1u" : "") << "; uint32_t rv = E::self(" << v
       << ");";
     for (int k = 0; k < n; ++k) o << " E::edge(L, sv, " << v << ", rv, " << P.words[nV + off + k] << ");";
-    o << " L.ent(" << v << ") = (uint16_t)(rv | sv); }\n";
+    o << " E::close(L, " << v << ", rv, sv); }\n";
   }
   o << "    // phase 2: antipodal pairs\n";
   for (int t = 0; t < nP; ++t) {
@@ -55,15 +55,15 @@ std::string jit_source(const HostProgram& P) {
     o << "    E::vertex3(L, " << v << ", " << t << ", nR, root, err);\n";
   }
   o << "    return E::finish(L, nR, root, err, errs);\n  }\n};\n\n}  // namespace pw\n\n";
-  o << "extern \"C\" __global__ __launch_bounds__(256) void pw_jit_codes(const void* masks, int64_t n, "
+  o << "extern \"C\" __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pw::Cfg<" << d << ">::WAVES_PER_EU))) void pw_jit_codes(const void* masks, int64_t n, "
        "uint64_t* codes, uint32_t* errflag) {\n"
        "  extern __shared__ uint32_t smem[];\n  pw::codes_body<"
     << d << ">(pw::JitEval{}, masks, n, codes, errflag, smem);\n}\n";
-  o << "extern \"C\" __global__ __launch_bounds__(256) void pw_jit_hist(const void* masks, int64_t n, "
+  o << "extern \"C\" __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pw::Cfg<" << d << ">::WAVES_PER_EU))) void pw_jit_hist(const void* masks, int64_t n, "
        "uint64_t index_base, pw::HistDev h, uint32_t* errflag) {\n"
        "  extern __shared__ uint32_t smem[];\n  pw::hist_body<"
     << d << ">(pw::JitEval{}, masks, n, index_base, h, errflag, smem);\n}\n";
-  o << "extern \"C\" __global__ __launch_bounds__(256) void pw_jit_enum(uint64_t first, uint64_t count, "
+  o << "extern \"C\" __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pw::Cfg<" << d << ">::WAVES_PER_EU))) void pw_jit_enum(uint64_t first, uint64_t count, "
        "pw::Runs runs, pw::HistDev h, uint32_t* errflag) {\n"
        "  extern __shared__ uint32_t smem[];\n  pw::enum_body<"
     << d << ">(pw::JitEval{}, first, count, runs, h, errflag, smem);\n}\n";

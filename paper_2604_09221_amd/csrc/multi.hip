@@ -41,8 +41,9 @@ struct Item {
 
 template <int D>
 __device__ __forceinline__ void run_item(const TriDesc& t, const Item& w, const uint64_t* __restrict__ masks,
-                                         uint64_t* __restrict__ codes, const Lane& L, int lane) {
+                                         uint64_t* __restrict__ codes, uint32_t* smem, int lane_words, int lane) {
   using C = Cfg<D>;
+  const Lane L = lane_memory<D>(smem, lane_words);
   uint32_t errs = 0;
   WaveTable tab;
   tab.clear();
@@ -74,7 +75,6 @@ __global__ __launch_bounds__(256) void k_multi(const TriDesc* __restrict__ tris,
                                                uint64_t* __restrict__ codes, int lane_words) {
   extern __shared__ uint32_t smem[];
   const int lane = threadIdx.x & 63;
-  const Lane L = lane_memory(smem, lane_words);
   while (true) {
     unsigned long long tk = 0;
     if (lane == 0) tk = atomicAdd(ticket, 1ull);
@@ -85,18 +85,18 @@ __global__ __launch_bounds__(256) void k_multi(const TriDesc* __restrict__ tris,
     const Item w = items[it];
     const TriDesc t = tris[w.tri];
     switch (t.d) {
-      case 1: run_item<1>(t, w, masks, codes, L, lane); break;
-      case 2: run_item<2>(t, w, masks, codes, L, lane); break;
-      case 3: run_item<3>(t, w, masks, codes, L, lane); break;
-      case 4: run_item<4>(t, w, masks, codes, L, lane); break;
-      case 5: run_item<5>(t, w, masks, codes, L, lane); break;
-      case 6: run_item<6>(t, w, masks, codes, L, lane); break;
-      case 7: run_item<7>(t, w, masks, codes, L, lane); break;
-      case 8: run_item<8>(t, w, masks, codes, L, lane); break;
-      case 9: run_item<9>(t, w, masks, codes, L, lane); break;
-      case 10: run_item<10>(t, w, masks, codes, L, lane); break;
-      case 11: run_item<11>(t, w, masks, codes, L, lane); break;
-      case 12: run_item<12>(t, w, masks, codes, L, lane); break;
+      case 1: run_item<1>(t, w, masks, codes, smem, lane_words, lane); break;
+      case 2: run_item<2>(t, w, masks, codes, smem, lane_words, lane); break;
+      case 3: run_item<3>(t, w, masks, codes, smem, lane_words, lane); break;
+      case 4: run_item<4>(t, w, masks, codes, smem, lane_words, lane); break;
+      case 5: run_item<5>(t, w, masks, codes, smem, lane_words, lane); break;
+      case 6: run_item<6>(t, w, masks, codes, smem, lane_words, lane); break;
+      case 7: run_item<7>(t, w, masks, codes, smem, lane_words, lane); break;
+      case 8: run_item<8>(t, w, masks, codes, smem, lane_words, lane); break;
+      case 9: run_item<9>(t, w, masks, codes, smem, lane_words, lane); break;
+      case 10: run_item<10>(t, w, masks, codes, smem, lane_words, lane); break;
+      case 11: run_item<11>(t, w, masks, codes, smem, lane_words, lane); break;
+      case 12: run_item<12>(t, w, masks, codes, smem, lane_words, lane); break;
       default: break;
     }
   }

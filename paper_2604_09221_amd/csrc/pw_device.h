@@ -49,6 +49,13 @@ typedef __hip_internal::int64_t int64_t;
 
 #include "pw_internal.h"
 
+// an empty asm statement the optimiser cannot see through: pins a value to
+// a VGPR at that point of the program (a CPU build of this header may
+// define it away)
+#ifndef PW_OPAQUE
+#define PW_OPAQUE(x) asm volatile("" : "+v"(x))
+#endif
+
 namespace pw {
 
 typedef unsigned __int128 u128;
@@ -76,58 +83,71 @@ struct Cfg {
   using Adj = typename cond<(RMAX <= 32), uint32_t, uint64_t>::type;
   using Code = typename cond<(D <= 9), uint64_t, u128>::type;
   static constexpr int ADJ_W = sizeof(Adj) / 4;
-  static constexpr int CODE_W = sizeof(Code) / 4;
+  // vertex entries: u8 (parent index << 1 | sign) where odd d needs no
+  // parity and 7 bits index every vertex (d <= 7); u16 otherwise
+  static constexpr bool NARROW = !EVEN && NV <= 128;
+  using Ent = typename cond<NARROW, uint8_t, uint16_t>::type;
+  static constexpr int EB = NARROW ? 1 : 2;
+  static constexpr int ESTRIDE = 64 * EB;  // bytes between entries v and v + 1 of a lane
+  // a stored region code has 2 * (subtree size) <= 2 * harnack(D) bits
+  static constexpr int CODE_W = 2 * harnack(D) <= 32 ? 1 : (int)(sizeof(Code) / 4);
   // per-lane LDS words:
-  //   [0, E_WORDS)            u16 vertex entries (phases 1-3)
+  //   [0, E_WORDS)            vertex entries (phases 1-3)
   //   [PAR_BASE, +PAR_WORDS)  u8 parent region of every region (phases 3-4)
   // after phase 3 the entry words hold, per region: child mask (ADJ_W
-  // words), breadth-first order (byte 0 of one word) and code (CODE_W).
-  static constexpr int E_WORDS = (NV + 1) / 2;
+  // words) and code (CODE_W words).
+  static constexpr int E_WORDS = (NV * EB + 3) / 4;
   static constexpr int CHILD_BASE = 0;
-  static constexpr int ORD_BASE = RMAX * ADJ_W;
-  static constexpr int CODE_BASE = ORD_BASE + RMAX;
+  static constexpr int CODE_BASE = RMAX * ADJ_W;
   static constexpr int TAIL_WORDS = CODE_BASE + RMAX * CODE_W;
   static constexpr int LOW_WORDS = E_WORDS > TAIL_WORDS ? E_WORDS : TAIL_WORDS;
   static constexpr int PAR_BASE = LOW_WORDS;
-  static constexpr int PAR_WORDS = (RMAX + 3) / 4;
+  static constexpr int PAR_WORDS = (RMAX + 4) / 4;  // RMAX bytes + a spare slot
   static constexpr int LANE_WORDS = LOW_WORDS + PAR_WORDS;
   static constexpr int WAVE_BYTES = LANE_WORDS * 4 * 64;
   // waves per block: as many waves per CU as the 160 KiB of LDS allows,
   // in blocks of at most 4 waves
   static constexpr int WAVES_PER_CU = (160 * 1024) / WAVE_BYTES;
   static constexpr int WAVES = WAVES_PER_CU >= 16 ? 4 : (WAVES_PER_CU >= 4 ? 2 : 1);
+  // resident waves per SIMD when the LDS is full: the register budget the
+  // kernels are compiled for (more registers would lower the occupancy
+  // below what the LDS allows)
+  static constexpr int RESIDENT = (WAVES_PER_CU / WAVES) * WAVES;
+  static constexpr int WAVES_PER_EU = RESIDENT >= 32 ? 8 : (RESIDENT >= 4 ? (RESIDENT + 3) / 4 : 1);
 };
 
 // ------------------------------------------------------------ lane memory
 
-// Vertex entries (u16) sit at byte v * 128 + 2 * lane of the wave's area
-// and hold  parent << 7 | odd-cycle flag << 2 | parity << 1 | sign.  The
-// parent field is therefore the byte offset of the parent's entry, so
-// following a parent pointer costs one AND and one add.  Word k of a lane
-// (region data, reused entry space) sits at byte k * 256 + 4 * lane.  For
-// uniform v every lane hits its own bank; for divergent parents at most two
-// lanes share a bank.
+// Vertex entries sit at byte v * ESTRIDE + EB * lane of the wave's area
+// (EB = 1 or 2 bytes per entry).  A u16 entry holds
+// parent << 7 | odd-cycle flag << 2 | parity << 1 | sign, so its parent
+// field is the byte offset of the parent's entry; a u8 entry holds
+// parent << 1 | sign.  Following a parent pointer costs two ALU operations
+// either way.  Word k of a lane (region data, reused entry space) sits at
+// byte k * 256 + 4 * lane.  For uniform v every lane hits its own bank; for
+// divergent parents a few lanes may share one.  Entry bytes of one lane
+// overlap words of others: phase 4 writes words only after every lane of
+// the wave has finished phase 3, which the wave's lockstep execution and
+// program order guarantee.
 struct Lane {
   uint32_t* w;  // word 0 of this lane; word k at w[k * 64]
-  char* e;      // entry 0 of this lane; entry v at e + v * 128
+  char* e;      // entry 0 of this lane
   __device__ __forceinline__ uint32_t& word(int k) const { return w[k * 64]; }
-  __device__ __forceinline__ uint16_t& ent(int v) const { return *reinterpret_cast<uint16_t*>(e + v * 128); }
-  __device__ __forceinline__ uint16_t& at(uint32_t off) const { return *reinterpret_cast<uint16_t*>(e + off); }
   __device__ __forceinline__ uint8_t& byte(int k, int b) const {
     return reinterpret_cast<uint8_t*>(w + k * 64)[b];
   }
 };
 
-constexpr uint32_t kIdx = 0xFF80u;  // parent (or region id) << 7
-constexpr int kIdxShift = 7;
 constexpr uint32_t kSign = 1u;
-constexpr uint32_t kParity = 2u;
-constexpr uint32_t kOdd = 4u;
-
-__device__ __forceinline__ uint32_t off_of(int v) { return (uint32_t)v << kIdxShift; }
+constexpr uint32_t kParity = 2u;  // u16 entries only
+constexpr uint32_t kOdd = 4u;     // u16 entries only
 
 template <typename T>
 __device__ __forceinline__ int clz_t(T x);
+template <>
+__device__ __forceinline__ int clz_t<uint32_t>(uint32_t x) {
+  return __clz((int)x);
+}
 template <>
 __device__ __forceinline__ int clz_t<uint64_t>(uint64_t x) {
   return __clzll((long long)x);
@@ -148,42 +168,6 @@ __device__ __forceinline__ int popc_t(T x) {
   return __popcll((unsigned long long)x);
 }
 
-template <typename Code>
-__device__ __forceinline__ Code load_code(const Lane& L, int base, int x) {
-  if constexpr (sizeof(Code) == 8) {
-    return (uint64_t)L.word(base + 2 * x) | ((uint64_t)L.word(base + 2 * x + 1) << 32);
-  } else {
-    u128 r = 0;
-    for (int k = 3; k >= 0; --k) r = (r << 32) | L.word(base + 4 * x + k);
-    return r;
-  }
-}
-
-template <typename Code>
-__device__ __forceinline__ void store_code(const Lane& L, int base, int x, Code c) {
-  constexpr int W = sizeof(Code) / 4;
-  for (int k = 0; k < W; ++k) L.word(base + W * x + k) = (uint32_t)(c >> (32 * k));
-}
-
-template <typename Adj>
-__device__ __forceinline__ Adj load_adj(const Lane& L, int base, int x) {
-  if constexpr (sizeof(Adj) == 4) {
-    return L.word(base + x);
-  } else {
-    return (uint64_t)L.word(base + 2 * x) | ((uint64_t)L.word(base + 2 * x + 1) << 32);
-  }
-}
-
-template <typename Adj>
-__device__ __forceinline__ void store_adj(const Lane& L, int base, int x, Adj a) {
-  if constexpr (sizeof(Adj) == 4) {
-    L.word(base + x) = a;
-  } else {
-    L.word(base + 2 * x) = (uint32_t)a;
-    L.word(base + 2 * x + 1) = (uint32_t)(a >> 32);
-  }
-}
-
 // ------------------------------------------------------------- one mask
 
 template <int D>
@@ -192,53 +176,94 @@ struct Eval {
   using Mask = typename C::Mask;
   using Adj = typename C::Adj;
   using Code = typename C::Code;
+  using Ent = typename C::Ent;
+  static constexpr int kShift = C::NARROW ? 1 : 7;  // index field of an entry
 
   __device__ static __forceinline__ uint32_t bit(Mask m, int p) { return (uint32_t)(m >> p) & 1u; }
 
-  // root of u (walk only), starting from its entry eu; returns the root's
-  // entry offset, er = the root's entry
-  __device__ static __forceinline__ uint32_t find(const Lane& L, int u, uint32_t eu, uint32_t& er) {
-    uint32_t r = eu & kIdx;
-    er = eu;
-    if (r != off_of(u)) {
-      er = L.at(r);
-      while ((er & kIdx) != r) {
-        r = er & kIdx;
-        er = L.at(r);
-      }
-    }
-    return r;
+  // ---- entries
+  __device__ static __forceinline__ Ent& ent(const Lane& L, int v) {
+    return *reinterpret_cast<Ent*>(L.e + v * C::ESTRIDE);
+  }
+  __device__ static __forceinline__ Ent& at(const Lane& L, uint32_t off) { return *reinterpret_cast<Ent*>(L.e + off); }
+  // byte offset of vertex v's entry (relative to entry 0)
+  __device__ static __forceinline__ uint32_t self(int v) { return (uint32_t)(v * C::ESTRIDE); }
+  // parent offset stored in an entry, and the field that stores an offset
+  __device__ static __forceinline__ uint32_t off(uint32_t e) {
+    return C::NARROW ? (e & 0xFEu) << 5 : (e & 0xFF80u);
+  }
+  __device__ static __forceinline__ uint32_t enc(uint32_t o) { return C::NARROW ? o >> 5 : o; }
+  // end of phase 1 for v: its root so far and its sign
+  __device__ static __forceinline__ void close(const Lane& L, int v, uint32_t rv, uint32_t sv) {
+    ent(L, v) = (Ent)(enc(rv) | sv);
   }
 
-  // root offset and parity of u relative to its root
+  // ---- region data (phases 3-4)
+  __device__ static __forceinline__ int par(const Lane& L, int x) { return L.byte(C::PAR_BASE + (x >> 2), x & 3); }
+  __device__ static __forceinline__ void set_par(const Lane& L, int x, int p) {
+    L.byte(C::PAR_BASE + (x >> 2), x & 3) = (uint8_t)p;
+  }
+  __device__ static __forceinline__ Adj load_adj(const Lane& L, int x) {
+    if constexpr (C::ADJ_W == 1) {
+      return L.word(C::CHILD_BASE + x);
+    } else {
+      return (uint64_t)L.word(C::CHILD_BASE + 2 * x) | ((uint64_t)L.word(C::CHILD_BASE + 2 * x + 1) << 32);
+    }
+  }
+  __device__ static __forceinline__ void store_adj(const Lane& L, int x, Adj a) {
+    if constexpr (C::ADJ_W == 1) {
+      L.word(C::CHILD_BASE + x) = a;
+    } else {
+      L.word(C::CHILD_BASE + 2 * x) = (uint32_t)a;
+      L.word(C::CHILD_BASE + 2 * x + 1) = (uint32_t)(a >> 32);
+    }
+  }
+  __device__ static __forceinline__ Code load_code(const Lane& L, int x) {
+    constexpr int W = C::CODE_W;
+    Code r = 0;
+    for (int k = W - 1; k >= 0; --k) r = (Code)(r << 32) | (Code)L.word(C::CODE_BASE + W * x + k);
+    return r;
+  }
+  __device__ static __forceinline__ void store_code(const Lane& L, int x, Code c) {
+    constexpr int W = C::CODE_W;
+    for (int k = 0; k < W; ++k) L.word(C::CODE_BASE + W * x + k) = (uint32_t)(c >> (32 * k));
+  }
+
+  // root offset of u and u's parity relative to it (parity: even d only)
   __device__ static __forceinline__ uint32_t find_parity(const Lane& L, int u, uint32_t& er, uint32_t& par) {
-    uint32_t r = off_of(u);
-    er = L.ent(u);
+    uint32_t r = self(u);
+    er = ent(L, u);
     par = 0;
-    while ((er & kIdx) != r) {
-      par ^= (er & kParity) ? 1u : 0u;
-      r = er & kIdx;
-      er = L.at(r);
+    while (off(er) != r) {
+      if (C::EVEN) par ^= (er & kParity) ? 1u : 0u;
+      r = off(er);
+      er = at(L, r);
     }
     return r;
   }
 
   // Phase 1 step: v's earlier neighbour u; sv = sign of v, rv = offset of
-  // v's root so far (v's own until v is linked).
+  // v's root so far (v's own until v is linked).  Written without branches
+  // apart from the walk to the root: every lane finds u's root (and points
+  // u's entry straight at it), and a lane whose signs differ, or whose
+  // union is void, stores into v's own entry instead -- that entry is
+  // scratch until phase 1 writes it once v is done, and no walk reaches v
+  // before that (every root found is an earlier vertex).
   __device__ static __forceinline__ void edge(const Lane& L, uint32_t sv, int v, uint32_t& rv, int u) {
-    const uint32_t eu = L.ent(u);
-    if ((eu & kSign) == sv) {
-      uint32_t er;
-      const uint32_t r = find(L, u, eu, er);
-      if (r != (eu & kIdx)) L.ent(u) = (uint16_t)((eu & ~kIdx) | r);
-      if (rv == off_of(v)) {
-        rv = r;
-      } else if (r != rv) {
-        const uint32_t lo = r < rv ? r : rv, hi = r < rv ? rv : r;
-        L.at(hi) = (uint16_t)(lo | sv);
-        rv = lo;
-      }
+    const uint32_t eu = ent(L, u);
+    uint32_t r = off(eu);
+    uint32_t er = at(L, r);
+    while (off(er) != r) {
+      r = off(er);
+      er = at(L, r);
     }
+    ent(L, u) = (Ent)(enc(r) | (eu & kSign));
+    const bool same = (eu & kSign) == sv;
+    const uint32_t lo = r < rv ? r : rv, hi = r < rv ? rv : r;
+    // same sign: the larger root hangs below the smaller one (a no-op
+    // rewrite when r == rv; v's own entry when v is still its own root)
+    at(L, same ? hi : self(v)) = (Ent)(enc(lo) | sv);
+    rv = same ? lo : rv;
   }
 
   // Phase 2 step: one antipodal pair (a, b).
@@ -247,14 +272,14 @@ struct Eval {
     const uint32_t ra = find_parity(L, a, ea, pa);
     const uint32_t rb = find_parity(L, b, eb, pb);
     if (ra == rb) {
-      if (C::EVEN && pa == pb) L.at(ra) = (uint16_t)(ea | kOdd);
+      if (C::EVEN && pa == pb) at(L, ra) = (Ent)(ea | kOdd);
     } else {
       const bool a_lo = ra < rb;
       const uint32_t lo = a_lo ? ra : rb, hi = a_lo ? rb : ra;
       const uint32_t elo = a_lo ? ea : eb, ehi = a_lo ? eb : ea;
       const uint32_t par = C::EVEN ? ((pa ^ pb ^ 1u) ? kParity : 0u) : 0u;
-      L.at(hi) = (uint16_t)((ehi & kSign) | par | lo);
-      if (ehi & kOdd) L.at(lo) = (uint16_t)(elo | kOdd);
+      at(L, hi) = (Ent)((ehi & kSign) | par | enc(lo));
+      if (C::EVEN && (ehi & kOdd)) at(L, lo) = (Ent)(elo | kOdd);
     }
   }
 
@@ -267,33 +292,35 @@ struct Eval {
   // region of t(first vertex of B)" is exactly the region adjacency tree,
   // rooted at the region of vertex 0.  For odd d a crossed tree edge inside
   // one region crosses the pseudo-line: that region is the root (Alg. 1).
-  // The entry of v becomes region id << 7 | sign.
+  // The entry of v becomes region id << kShift | sign.  Branch-free: a
+  // vertex that is not a root stores its (unused) parent-region byte into
+  // the spare slot RMAX of the parent table.
   __device__ static __forceinline__ void vertex3(const Lane& L, int v, int t, int& nR, int& root, uint32_t& err) {
-    const uint32_t ev = L.ent(v);
+    const uint32_t ev = ent(L, v);
     const uint32_t sv = ev & kSign;
-    const uint32_t p = ev & kIdx;
-    int cid;
-    if (p == off_of(v)) {
-      cid = nR < C::RMAX ? nR : C::RMAX - 1;
-      err |= nR < C::RMAX ? 0u : kErrRegions;
-      ++nR;
-      if (C::EVEN && (ev & kOdd)) {
-        if (root >= 0) err |= kErrRoot;
-        root = cid;
-      }
-      const int pc = t >= 0 ? (int)(L.ent(t) >> kIdxShift) : 0xFF;
-      L.byte(C::PAR_BASE + (cid >> 2), cid & 3) = (uint8_t)pc;
+    const uint32_t p = off(ev);
+    const bool is_root = p == self(v);
+    const uint32_t ep = at(L, p);  // p < v is relabelled already; a root reads its own entry
+    const uint32_t et = ent(L, t < 0 ? 0 : t);
+    // ids past the Harnack bound share the spare slot RMAX; finish()
+    // rejects such a mask (nR > RMAX) before reading any region data
+    const int cid = is_root ? (nR < C::RMAX ? nR : C::RMAX) : (int)(ep >> kShift);
+    nR += is_root ? 1 : 0;
+    // keep the running count a plain running count (re-associating the
+    // chain of increments would hold every vertex's flag in a register)
+    PW_OPAQUE(nR);
+    if (C::EVEN) {
+      const bool mark = is_root && (ev & kOdd);
+      err |= (mark && root >= 0) ? kErrRoot : 0u;
+      root = mark ? cid : root;
     } else {
-      cid = (int)(L.at(p) >> kIdxShift);
-      if (!C::EVEN) {
-        const uint32_t et = L.ent(t);
-        if ((et & kSign) != sv && (int)(et >> kIdxShift) == cid) {
-          if (root >= 0 && root != cid) err |= kErrRoot;
-          root = cid;
-        }
-      }
+      const bool loop_here = t >= 0 && !is_root && (et & kSign) != sv && (int)(et >> kShift) == cid;
+      err |= (loop_here && root >= 0 && root != cid) ? kErrRoot : 0u;
+      root = loop_here ? cid : root;
     }
-    L.ent(v) = (uint16_t)(off_of(cid) | sv);
+    const uint32_t pc = t >= 0 ? (et >> kShift) : 0xFFu;
+    set_par(L, is_root ? cid : C::RMAX, (int)pc);
+    ent(L, v) = (Ent)(((uint32_t)cid << kShift) | sv);
   }
 
   // Returns the scheme code (0 on a failed consistency check, with the
@@ -306,10 +333,10 @@ struct Eval {
       const uint32_t rec = prog[v];
       const uint32_t sv = bit(m, rec & 0x7F) ^ ((rec >> 7) & 1u);
       const int nn = (rec >> 8) & 0xFF;
-      const int off = rec >> 16;
-      uint32_t rv = off_of(v);
-      for (int k = 0; k < nn; ++k) edge(L, sv, v, rv, (int)nbr[off + k]);
-      L.ent(v) = (uint16_t)(rv | sv);
+      const int o = rec >> 16;
+      uint32_t rv = self(v);
+      for (int k = 0; k < nn; ++k) edge(L, sv, v, rv, (int)nbr[o + k]);
+      close(L, v, rv, sv);
     }
     // phase 2: regions (antipodal identification)
     for (int t = 0; t < C::NP; ++t) pair(L, pairs[t] & 0xFFFF, pairs[t] >> 16);
@@ -320,53 +347,60 @@ struct Eval {
     return finish(L, nR, root, err, errs);
   }
 
+  __device__ static __forceinline__ Adj one(int x) { return (Adj)1 << x; }
+
+  // Phase 4: re-root the region tree at `root` and build the canonical
+  // code (AHU) from the leaves up.
   __device__ __forceinline__ static u128 finish(const Lane& L, int nR, int root, uint32_t err, uint32_t& errs) {
     if (root < 0) err |= kErrRoot;
+    if (nR > C::RMAX) err |= kErrRegions;
     if (err) {
       errs |= err;
       return 0;
     }
-
-    // ---- phase 4: re-root the region tree at `root`, breadth-first order,
-    // then AHU codes from the leaves up
+    // Every region's parent has a smaller id (region 0 is the top).
+    // Re-rooting reverses the parent pointers on the path from `root` to
+    // region 0 and leaves every other subtree as it was.
+    Adj path = 0;
     {
       int x = root, prev = 0xFF;
-      while (x != 0xFF) {
-        const int nx = L.byte(C::PAR_BASE + (x >> 2), x & 3);
-        L.byte(C::PAR_BASE + (x >> 2), x & 3) = (uint8_t)prev;
+      for (int it = 0; x != 0xFF && it < C::RMAX; ++it) {
+        const int nx = par(L, x);
+        set_par(L, x, prev);
+        path |= one(x);
         prev = x;
         x = nx;
       }
-    }
-    for (int x = 0; x < nR; ++x) store_adj<Adj>(L, C::CHILD_BASE, x, (Adj)0);
-    for (int x = 0; x < nR; ++x) {
-      const int px = L.byte(C::PAR_BASE + (x >> 2), x & 3);
-      if (px != 0xFF) store_adj<Adj>(L, C::CHILD_BASE, px, load_adj<Adj>(L, C::CHILD_BASE, px) | ((Adj)1 << x));
-    }
-    L.byte(C::ORD_BASE + 0, 0) = (uint8_t)root;
-    int tail = 1;
-    for (int head = 0; head < tail && head < C::RMAX; ++head) {
-      const int x = L.byte(C::ORD_BASE + head, 0);
-      Adj nb = load_adj<Adj>(L, C::CHILD_BASE, x);
-      while (nb) {
-        const int y = ctz_t(nb);
-        nb &= nb - 1;
-        if (tail < C::RMAX) L.byte(C::ORD_BASE + tail, 0) = (uint8_t)y;
-        ++tail;
+      if (x != 0xFF) {
+        errs |= kErrTree;
+        return 0;
       }
     }
-    if (tail != nR) {
-      errs |= kErrTree;
-      return 0;
+    for (int x = 0; x < nR; ++x) store_adj(L, x, (Adj)0);
+    for (int x = 0; x < nR; ++x) {
+      const int px = par(L, x);
+      if (px != 0xFF) store_adj(L, px, load_adj(L, px) | one(x));
     }
+    // Bottom-up order: the regions off the path by decreasing id (all their
+    // children have larger ids), then the path from region 0 up to the root
+    // (the children of a path region are off the path or the path region
+    // done just before it).
+    constexpr int AB = 8 * (int)sizeof(Adj);
+    Adj todo = (nR >= AB ? ~(Adj)0 : (one(nR) - 1)) & ~path;
     Adj leaves = 0;
-    Code word = 0;
-    int wlen = 0;
-    for (int i = nR - 1; i >= 0; --i) {
-      const int x = L.byte(C::ORD_BASE + i, 0);
-      const Adj kids = load_adj<Adj>(L, C::CHILD_BASE, x);
-      if (kids == 0) {
-        leaves |= (Adj)1 << x;
+    int last = 0xFF;  // the path region done last
+    for (int it = 0; it <= C::RMAX; ++it) {
+      int y;
+      if (todo) {
+        y = AB - 1 - clz_t(todo);
+        todo &= ~one(y);
+      } else {
+        y = last == 0xFF ? 0 : par(L, last);
+        last = y;
+      }
+      const Adj kids = load_adj(L, y);
+      if (kids == 0 && y != root) {
+        leaves |= one(y);
         continue;
       }
       Adj rest = kids & ~leaves;
@@ -378,17 +412,17 @@ struct Eval {
         Code bkey = 0, bcode = 0;
         Adj t = rest;
         while (t) {
-          const int y = ctz_t(t);
+          const int z = ctz_t(t);
           t &= t - 1;
-          const Code cy = load_code<Code>(L, C::CODE_BASE, y);
-          const Code ky = cy << clz_t(cy);
-          if (best < 0 || ky > bkey) {
-            best = y;
-            bkey = ky;
-            bcode = cy;
+          const Code cz = load_code(L, z);
+          const Code kz = cz << clz_t(cz);
+          if (best < 0 || kz > bkey) {
+            best = z;
+            bkey = kz;
+            bcode = cz;
           }
         }
-        rest &= ~((Adj)1 << best);
+        rest &= ~one(best);
         const int lb = (int)(8 * sizeof(Code)) - clz_t(bcode);
         acc = (acc << lb) | bcode;
         len += lb;
@@ -398,16 +432,15 @@ struct Eval {
         acc = (acc << (2 * nleaf)) | (pat >> (8 * (int)sizeof(Code) - 2 * nleaf));
         len += 2 * nleaf;
       }
-      if (i > 0) {
-        store_code<Code>(L, C::CODE_BASE, x, ((Code)1 << (len + 1)) | (acc << 1));
-      } else {
-        word = acc;
-        wlen = len;
+      if (y == root) {
+        u128 code = ((u128)1 << len) | (u128)acc;
+        if (!C::EVEN) code |= (u128)1 << 127;
+        return code;
       }
+      store_code(L, y, ((Code)1 << (len + 1)) | (acc << 1));
     }
-    u128 code = ((u128)1 << wlen) | (u128)word;
-    if (!C::EVEN) code |= (u128)1 << 127;
-    return code;
+    errs |= kErrTree;
+    return 0;
   }
 };
 
@@ -598,10 +631,12 @@ struct RtEval {
   }
 };
 
+// this lane's view of its wave's area (lane_words words per lane)
+template <int D>
 __device__ __forceinline__ Lane lane_memory(uint32_t* smem, int lane_words) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t* base = smem + wave * lane_words * 64;
-  return Lane{base + lane, reinterpret_cast<char*>(base) + 2 * lane};
+  return Lane{base + lane, reinterpret_cast<char*>(base) + Cfg<D>::EB * lane};
 }
 
 // codes of n masks, one per thread, grid-stride
@@ -610,7 +645,7 @@ __device__ __forceinline__ void codes_body(const EV& ev, const void* __restrict_
                                            uint64_t* __restrict__ codes, uint32_t* __restrict__ errflag,
                                            uint32_t* smem) {
   using C = Cfg<D>;
-  const Lane L = lane_memory(smem, C::LANE_WORDS);
+  const Lane L = lane_memory<D>(smem, C::LANE_WORDS);
   uint32_t errs = 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
@@ -633,7 +668,7 @@ __device__ __forceinline__ void hist_body(const EV& ev, const void* __restrict__
                                           uint32_t* smem) {
   using C = Cfg<D>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const Lane L = lane_memory(smem, C::LANE_WORDS);
+  const Lane L = lane_memory<D>(smem, C::LANE_WORDS);
   WaveTable tab;
   tab.clear();
   uint32_t errs = 0;
@@ -655,7 +690,7 @@ __device__ __forceinline__ void enum_body(const EV& ev, uint64_t first, uint64_t
                                           const HistDev& h, uint32_t* __restrict__ errflag, uint32_t* smem) {
   using C = Cfg<D>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const Lane L = lane_memory(smem, C::LANE_WORDS);
+  const Lane L = lane_memory<D>(smem, C::LANE_WORDS);
   WaveTable tab;
   tab.clear();
   uint32_t errs = 0;

@@ -24,7 +24,7 @@ namespace pw {
 // bodies are shared with the kernels generated for one triangulation.
 
 template <int D>
-__global__ __launch_bounds__(256) void k_codes(const uint32_t* __restrict__ prog, const void* __restrict__ masks,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Cfg<D>::WAVES_PER_EU))) void k_codes(const uint32_t* __restrict__ prog, const void* __restrict__ masks,
                                                int64_t n, uint64_t* __restrict__ codes,
                                                uint32_t* __restrict__ errflag) {
   extern __shared__ uint32_t smem[];
@@ -32,7 +32,7 @@ __global__ __launch_bounds__(256) void k_codes(const uint32_t* __restrict__ prog
 }
 
 template <int D>
-__global__ __launch_bounds__(256) void k_hist(const uint32_t* __restrict__ prog, const void* __restrict__ masks,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Cfg<D>::WAVES_PER_EU))) void k_hist(const uint32_t* __restrict__ prog, const void* __restrict__ masks,
                                               int64_t n, uint64_t index_base, HistDev h,
                                               uint32_t* __restrict__ errflag) {
   extern __shared__ uint32_t smem[];
@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256) void k_hist(const uint32_t* __restrict__ prog,
 }
 
 template <int D>
-__global__ __launch_bounds__(256) void k_enum(const uint32_t* __restrict__ prog, uint64_t first, uint64_t count,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Cfg<D>::WAVES_PER_EU))) void k_enum(const uint32_t* __restrict__ prog, uint64_t first, uint64_t count,
                                               Runs runs, HistDev h, uint32_t* __restrict__ errflag) {
   extern __shared__ uint32_t smem[];
   enum_body<D>(RtEval<D>{prog}, first, count, runs, h, errflag, smem);
