@@ -10,6 +10,7 @@
 // layout (the upper 16 bits of a float are a bfloat16).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -18,7 +19,6 @@
 
 namespace pw {
 
-typedef short short4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
@@ -32,18 +32,26 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
 // --------------------------------------------------------------------- GEMM
 //
 // C[M x N] = A[M x K] * B[K x N] with arbitrary element strides (so the
-// same kernel serves X W, dY W^T and X^T dY).  Tile 64 x 64 per block of
-// four waves, each wave owning a 32 x 32 sub-tile = 2 x 2 MFMA 16x16 tiles;
-// K advances 32 at a time through LDS.
+// same kernel serves X W, dY W^T and X^T dY).  A block of four waves owns a
+// BM x BN tile (BM, BN in {64, 128}); each wave a (BM/2) x (BN/2) quarter
+// made of 16 x 16 MFMA tiles.  K advances TBK = 32 at a time through LDS,
+// the next slab being fetched into registers while the current one is
+// multiplied.  Tall-K products with few output tiles (the weight gradients
+// X^T dY, K = batch) split K over blockIdx.z and add their partial tiles
+// into C32 with FP32 atomics.
 //
-// MFMA 16x16x16 operand layout (wave of 64 lanes, l = lane):
-//   A: lane l holds A[l % 16][4 (l / 16) + 0..3]
-//   B: lane l holds B[4 (l / 16) + 0..3][l % 16]
+// gfx950 MFMA v_mfma_f32_16x16x32_bf16 operand layout (l = lane):
+//   A: lane l holds A[l % 16][8 (l / 16) + 0..7]
+//   B: lane l holds B[8 (l / 16) + 0..7][l % 16]
 //   C: lane l holds C[4 (l / 16) + 0..3][l % 16]
-// Epilogue per element: + bias[n], ReLU, times [gate > 0], stored as fp32
-// and/or bf16.
+// Both tiles sit in LDS k-contiguous ([m][k] and [n][k]), so each operand
+// fragment is one 16-byte LDS read.  Epilogue per element: + bias[n],
+// ReLU, times [gate > 0], stored as fp32 and/or bf16.
 
-constexpr int TBM = 64, TBN = 64, TBK = 32;
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+constexpr int TBK = 32;
+constexpr int LDK = TBK + 8;  // padded LDS row: 80 bytes
 
 struct GemmArgs {
   const uint16_t* A;
@@ -51,6 +59,7 @@ struct GemmArgs {
   const uint16_t* B;
   int64_t b_k, b_n;
   int M, N, K;
+  int k_split;           // K range of one blockIdx.z (multiple of TBK)
   const float* bias;     // N or null
   const uint16_t* gate;  // M x N (ld g_m) or null: multiply by [gate > 0]
   int64_t g_m;
@@ -59,73 +68,117 @@ struct GemmArgs {
   uint16_t* C16;  // or null
   int64_t c_m;
   int accumulate;  // C32 += result
+  int atomic;      // partial tiles of a split K: C32 += result atomically
 };
 
-// Staging of one 64 x 32 tile of A ([m][k] in LDS) and of B ([n][k] in
-// LDS).  A_K / B_K: the operand is contiguous along k (a_k == 1 / b_k == 1),
-// so each thread moves 8 consecutive bf16 with one 16-byte load and one
-// 16-byte LDS store; A_M / B_N: contiguous along m / n, 16-byte loads
-// scattered into the k-contiguous LDS tile; otherwise element by element.
-struct u16x8 {
-  uint16_t v[8];
-};
+// One ROWS x TBK slab of an operand X (element (r, k) at X[r s_row + k s_k])
+// moves HBM -> registers -> LDS tile T[ROWS][LDK] in 16-byte chunks.
+// MODE 1: contiguous along k (s_k == 1): a chunk is 8 consecutive k of one
+// row.  MODE 2: contiguous along r (s_row == 1): a chunk is 8 consecutive
+// rows of one k, scattered into 8 LDS rows.  MODE 0: element by element.
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));  // 8 bf16
 
-template <int MODE>  // 0 generic, 1 contiguous along k, 2 contiguous along the other index
-__device__ __forceinline__ void stage(uint16_t (*T)[TBK + 8], const uint16_t* __restrict__ X, int64_t s_row,
-                                      int64_t s_k, int r0, int k0, int tid) {
-  if (MODE == 1) {
-    const int r = tid >> 2, c = (tid & 3) * 8;  // 64 rows x 4 chunks of 8
-    *reinterpret_cast<u16x8*>(&T[r][c]) =
-        *reinterpret_cast<const u16x8*>(&X[(int64_t)(r0 + r) * s_row + (int64_t)(k0 + c)]);
-  } else if (MODE == 2) {
-    const int c = tid >> 3, r = (tid & 7) * 8;  // 32 k x 8 chunks of 8 rows
-    const u16x8 w = *reinterpret_cast<const u16x8*>(&X[(int64_t)(k0 + c) * s_k + (int64_t)(r0 + r)]);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) T[r + q][c] = w.v[q];
-  } else {
-    for (int e = tid; e < TBM * TBK; e += 256) {
-      const int r = e / TBK, c = e % TBK;
-      T[r][c] = X[(int64_t)(r0 + r) * s_row + (int64_t)(k0 + c) * s_k];
-    }
-  }
+__device__ __forceinline__ uint16_t half_of(const u32x4_t& q, int e) {
+  return (uint16_t)(q[e >> 1] >> (16 * (e & 1)));
 }
 
-template <int AM, int BM_>
-__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[TBM][TBK + 8];  // [m][k]
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[TBN][TBK + 8];  // [n][k]
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m0 = blockIdx.y * TBM, n0 = blockIdx.x * TBN;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  float4_t acc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) acc[a][b] = float4_t{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < g.K; k0 += TBK) {
-    stage<AM>(As, g.A, g.a_m, g.a_k, m0, k0, tid);
-    stage<BM_>(Bs, g.B, g.b_n, g.b_k, n0, k0, tid);
-    __syncthreads();
-    for (int ks = 0; ks < TBK; ks += 16) {
-      const int kk = ks + 4 * (lane >> 4);
-      short4_t af[2], bf[2];
-      for (int a = 0; a < 2; ++a) {
-        const uint16_t* p = &As[wm + 16 * a + (lane & 15)][kk];
-        af[a] = short4_t{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
+template <int ROWS, int MODE>
+struct Slab {
+  static constexpr int CHUNKS = ROWS * TBK / 8 / 256;  // per thread
+  u32x4_t q[CHUNKS];
+
+  __device__ __forceinline__ void load(const uint16_t* __restrict__ X, int64_t s_row, int64_t s_k, int r0, int k0,
+                                       int tid) {
+#pragma unroll
+    for (int c = 0; c < CHUNKS; ++c) {
+      const int id = tid + 256 * c;
+      if (MODE == 2) {
+        const int k = id / (ROWS / 8), r = (id % (ROWS / 8)) * 8;
+        q[c] = *reinterpret_cast<const u32x4_t*>(&X[(int64_t)(k0 + k) * s_k + (int64_t)(r0 + r)]);
+      } else {
+        const int r = id >> 2, k = (id & 3) * 8;
+        if (MODE == 1) {
+          q[c] = *reinterpret_cast<const u32x4_t*>(&X[(int64_t)(r0 + r) * s_row + (int64_t)(k0 + k)]);
+        } else {
+          const uint16_t* x = &X[(int64_t)(r0 + r) * s_row + (int64_t)k0 * s_k];
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            q[c][e] = (uint32_t)x[(k + 2 * e) * s_k] | ((uint32_t)x[(k + 2 * e + 1) * s_k] << 16);
+        }
       }
-      for (int b = 0; b < 2; ++b) {
-        const uint16_t* p = &Bs[wn + 16 * b + (lane & 15)][kk];
-        bf[b] = short4_t{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
-      }
-      for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[a], bf[b], acc[a][b], 0, 0, 0);
     }
+  }
+
+  __device__ __forceinline__ void store(uint16_t (*T)[LDK], int tid) const {
+#pragma unroll
+    for (int c = 0; c < CHUNKS; ++c) {
+      const int id = tid + 256 * c;
+      if (MODE == 2) {
+        const int k = id / (ROWS / 8), r = (id % (ROWS / 8)) * 8;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) T[r + e][k] = half_of(q[c], e);
+      } else {
+        const int r = id >> 2, k = (id & 3) * 8;
+        *reinterpret_cast<u32x4_t*>(&T[r][k]) = q[c];
+      }
+    }
+  }
+};
+
+template <int BM, int BN, int AM, int BM_>
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
+  constexpr int FM = BM / 32, FN = BN / 32;  // 16 x 16 tiles per wave along m and n
+  __shared__ __attribute__((aligned(16))) uint16_t As[BM][LDK];  // [m][k]
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][LDK];  // [n][k]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+  const int kb = blockIdx.z * g.k_split;
+  const int ke = kb + g.k_split < g.K ? kb + g.k_split : g.K;
+  float4_t acc[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) acc[a][b] = float4_t{0.f, 0.f, 0.f, 0.f};
+  Slab<BM, AM> sa;
+  Slab<BN, BM_> sb;
+  if (kb < ke) {
+    sa.load(g.A, g.a_m, g.a_k, m0, kb, tid);
+    sb.load(g.B, g.b_n, g.b_k, n0, kb, tid);
+  }
+  for (int k0 = kb; k0 < ke; k0 += TBK) {
+    sa.store(As, tid);
+    sb.store(Bs, tid);
+    __syncthreads();
+    if (k0 + TBK < ke) {  // next slab in flight during the products
+      sa.load(g.A, g.a_m, g.a_k, m0, k0 + TBK, tid);
+      sb.load(g.B, g.b_n, g.b_k, n0, k0 + TBK, tid);
+    }
+    const int kk = 8 * (lane >> 4);
+    bf16x8_t af[FM], bfr[FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a) af[a] = *reinterpret_cast<const bf16x8_t*>(&As[wm + 16 * a + (lane & 15)][kk]);
+#pragma unroll
+    for (int b = 0; b < FN; ++b) bfr[b] = *reinterpret_cast<const bf16x8_t*>(&Bs[wn + 16 * b + (lane & 15)][kk]);
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
     __syncthreads();
   }
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b)
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + wm + 16 * a + 4 * (lane >> 4) + r;
         const int n = n0 + wn + 16 * b + (lane & 15);
         float v = acc[a][b][r];
+        if (g.atomic) {
+          unsafeAtomicAdd(&g.C32[(int64_t)m * g.c_m + n], v);
+          continue;
+        }
         if (g.bias) v += g.bias[n];
         if (g.relu) v = v > 0.f ? v : 0.f;
         if (g.gate && !(bf16_to_f32(g.gate[(int64_t)m * g.g_m + n]) > 0.f)) v = 0.f;
@@ -223,6 +276,12 @@ constexpr int kColRows = 256;
 __global__ void k_fill(float* __restrict__ x, int64_t n, float v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = v;
+}
+
+// C[m][n] = 0 for an M x N matrix with row stride ld
+__global__ void k_fill2d(float* __restrict__ C, int M, int N, int64_t ld) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < (int64_t)M * N) C[(i / N) * ld + i % N] = 0.f;
 }
 
 __global__ void k_colsum(const float* __restrict__ X, int64_t n, int cols, float* __restrict__ out) {
@@ -359,26 +418,55 @@ pw_status pw_mlp_gemm(const uint16_t* A, int64_t a_m, int64_t a_k, const uint16_
                       int32_t M, int32_t N, int32_t K, const float* bias, const uint16_t* gate, int64_t g_m,
                       int32_t relu, float* C32, uint16_t* C16, int64_t c_m, int32_t accumulate, hipStream_t s) {
   if (!A || !B || (!C32 && !C16)) return set_err(PW_ERR_ARG, "null operand");
-  if (M <= 0 || N <= 0 || K <= 0 || M % TBM || N % TBN || K % TBK)
+  if (M <= 0 || N <= 0 || K <= 0 || M % 64 || N % 64 || K % TBK)
     return set_err(PW_ERR_ARG, "gemm sizes must be positive multiples of 64 (M, N) and 32 (K): %d %d %d", M, N, K);
   if (accumulate && !C32) return set_err(PW_ERR_ARG, "accumulate needs the fp32 output");
-  GemmArgs g{A, a_m, a_k, B, b_k, b_n, M, N, K, bias, gate, g_m, relu, C32, C16, c_m, accumulate};
+  GemmArgs g{A, a_m, a_k, B, b_k, b_n, M, N, K, K, bias, gate, g_m, relu, C32, C16, c_m, accumulate, 0};
   // 16-byte staging needs 8-element alignment of the base and the strides
   auto al = [](const void* p, int64_t s1) { return ((uintptr_t)p % 16 == 0) && (s1 % 8 == 0); };
   const int am = (a_k == 1 && al(A, a_m)) ? 1 : ((a_m == 1 && al(A, a_k)) ? 2 : 0);
   const int bm = (b_k == 1 && al(B, b_n)) ? 1 : ((b_n == 1 && al(B, b_k)) ? 2 : 0);
-  const dim3 grid(N / TBN, M / TBM);
-  switch (am * 3 + bm) {
-    case 0: hipLaunchKernelGGL((k_gemm_bf16<0, 0>), grid, dim3(256), 0, s, g); break;
-    case 1: hipLaunchKernelGGL((k_gemm_bf16<0, 1>), grid, dim3(256), 0, s, g); break;
-    case 2: hipLaunchKernelGGL((k_gemm_bf16<0, 2>), grid, dim3(256), 0, s, g); break;
-    case 3: hipLaunchKernelGGL((k_gemm_bf16<1, 0>), grid, dim3(256), 0, s, g); break;
-    case 4: hipLaunchKernelGGL((k_gemm_bf16<1, 1>), grid, dim3(256), 0, s, g); break;
-    case 5: hipLaunchKernelGGL((k_gemm_bf16<1, 2>), grid, dim3(256), 0, s, g); break;
-    case 6: hipLaunchKernelGGL((k_gemm_bf16<2, 0>), grid, dim3(256), 0, s, g); break;
-    case 7: hipLaunchKernelGGL((k_gemm_bf16<2, 1>), grid, dim3(256), 0, s, g); break;
-    default: hipLaunchKernelGGL((k_gemm_bf16<2, 2>), grid, dim3(256), 0, s, g); break;
+  const int tm = M % 128 == 0 ? 128 : 64, tn = N % 128 == 0 ? 128 : 64;
+  const int tiles = (M / tm) * (N / tn);
+  // split K when the output has too few tiles to fill 256 CUs and there is
+  // no element-wise epilogue (partial sums are added atomically)
+  int splits = 1;
+  const int ksteps = K / TBK;
+  if (C32 && !C16 && !bias && !gate && !relu && tiles < 512 && ksteps >= 8) {
+    splits = std::min(ksteps / 4, (1024 + tiles - 1) / tiles);
+    const int per = (ksteps + splits - 1) / splits;
+    g.k_split = per * TBK;
+    splits = (ksteps + per - 1) / per;
   }
+  if (splits > 1) {
+    g.atomic = 1;
+    if (!accumulate) {
+      hipLaunchKernelGGL(k_fill2d, dim3(grid1d((int64_t)M * N, 256)), dim3(256), 0, s, C32, M, N, c_m);
+    }
+  }
+  const dim3 grid(N / tn, M / tm, splits);
+#define PW_GEMM_CASES(BM_, BN_)                                                                   \
+  switch (am * 3 + bm) {                                                                          \
+    case 0: hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, 0, 0>), grid, dim3(256), 0, s, g); break; \
+    case 1: hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, 0, 1>), grid, dim3(256), 0, s, g); break; \
+    case 2: hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, 0, 2>), grid, dim3(256), 0, s, g); break; \
+    case 3: hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, 1, 0>), grid, dim3(256), 0, s, g); break; \
+    case 4: hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, 1, 1>), grid, dim3(256), 0, s, g); break; \
+    case 5: hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, 1, 2>), grid, dim3(256), 0, s, g); break; \
+    case 6: hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, 2, 0>), grid, dim3(256), 0, s, g); break; \
+    case 7: hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, 2, 1>), grid, dim3(256), 0, s, g); break; \
+    default: hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, 2, 2>), grid, dim3(256), 0, s, g); break; \
+  }
+  if (tm == 128 && tn == 128) {
+    PW_GEMM_CASES(128, 128)
+  } else if (tm == 128) {
+    PW_GEMM_CASES(128, 64)
+  } else if (tn == 128) {
+    PW_GEMM_CASES(64, 128)
+  } else {
+    PW_GEMM_CASES(64, 64)
+  }
+#undef PW_GEMM_CASES
   PW_HIP(hipGetLastError());
   return PW_OK;
 }

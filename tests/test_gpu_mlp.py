@@ -69,6 +69,46 @@ def test_gemm_variants(L, M, N, K, variant):
     assert np.all(np.abs(from16(C16) - want) <= bound + np.abs(want) * 2.0 ** -8)
 
 
+@pytest.mark.parametrize("M,N,K,variant,accumulate", [
+    (512, 512, 4096, "TN", False),   # weight-gradient shape: K split over blocks, atomic partial sums
+    (64, 512, 2048, "TN", True),     # split K on top of an existing C32
+    (512, 64, 1024, "TT", False),    # both operands transposed, split K
+    (192, 320, 96, "NN", False),     # 64-wide tiles on both axes, ragged against 128
+    (128, 192, 64, "GG", True),      # unaligned strides: element-wise staging
+])
+def test_gemm_plain_fp32(L, M, N, K, variant, accumulate):
+    """C32 (+)= A B without epilogue: the path that splits K."""
+    rng = np.random.default_rng(7 * M + N + K)
+    A = R.bf16(rng.normal(size=(M, K)))
+    B = R.bf16(rng.normal(size=(K, N)))
+    C0 = rng.normal(size=(M, N)).astype(np.float32)
+    if variant == "NN":
+        At, a_m, a_k = bits16(A), K, 1
+        Bt, b_k, b_n = bits16(B), N, 1
+    elif variant == "TN":
+        At, a_m, a_k = bits16(A.T.copy()), 1, M
+        Bt, b_k, b_n = bits16(B), N, 1
+    elif variant == "TT":
+        At, a_m, a_k = bits16(A.T.copy()), 1, M
+        Bt, b_k, b_n = bits16(B.T.copy()), 1, K
+    else:                          # rows padded by 3 elements: no 16-byte alignment
+        Ap = np.zeros((M, K + 3)); Ap[:, :K] = A
+        Bp = np.zeros((K, N + 3)); Bp[:, :N] = B
+        At, a_m, a_k = bits16(Ap), K + 3, 1
+        Bt, b_k, b_n = bits16(Bp), N + 3, 1
+    C32 = torch.from_numpy(C0.copy()).cuda()
+    L.gemm(At, a_m, a_k, Bt, b_k, b_n, M, N, K, C32=C32, accumulate=accumulate)
+    torch.cuda.synchronize()
+    want = A @ B + (C0.astype(np.float64) if accumulate else 0.0)
+    # every partial sum and every atomic addition rounds once in FP32: at
+    # most K + (number of splits <= K / 128) roundings, each relative to a
+    # value bounded by sum |a||b| (+ |C0|)
+    mag = np.abs(A) @ np.abs(B) + (np.abs(C0) if accumulate else 0.0)
+    bound = mag * (K + K / 128 + 1) * 2.0 ** -24 + 1e-30
+    got = C32.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - want) <= bound)
+
+
 def test_encode_and_features_exact(L):
     d = 8
     E = I.standard_triangulation(d)
