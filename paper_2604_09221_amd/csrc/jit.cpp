@@ -34,14 +34,23 @@ std::string jit_source(const HostProgram& P) {
   o << "  __device__ __forceinline__ u128 operator()(Cfg<" << d
     << ">::Mask m, const Lane& L, uint32_t& errs) const {\n";
   o << "    using E = Eval<" << d << ">;\n";
+  // sign of vertex v: bit p of the mask, flipped by the reflection parity g
+  auto sign = [&](int v) {
+    const uint32_t rec = P.words[v];
+    const int p = rec & 0x7F, g = (rec >> 7) & 1;
+    std::string x = "E::bit(m, " + std::to_string(p) + ")";
+    return g ? "(" + x + " ^ 1u)" : x;
+  };
   o << "    // phase 1: components of same-sign vertices\n";
   for (int v = 0; v < nV; ++v) {
     const uint32_t rec = P.words[v];
-    const int p = rec & 0x7F, g = (rec >> 7) & 1, n = (rec >> 8) & 0xFF, off = rec >> 16;
-    o << "    { const uint32_t sv = E::bit(m, " << p << ")" << (g ? " ^ 1u" : "") << "; uint32_t rv = E::self(" << v
-      << ");";
-    for (int k = 0; k < n; ++k) o << " E::edge(L, sv, " << v << ", rv, " << P.words[nV + off + k] << ");";
-    o << " E::close(L, " << v << ", rv, sv); }\n";
+    const int n = (rec >> 8) & 0xFF, off = rec >> 16;
+    o << "    { const uint32_t sv = " << sign(v) << "; uint32_t rv = " << v << "u;";
+    for (int k = 0; k < n; ++k) {
+      const int u = (int)P.words[nV + off + k];
+      o << " E::edge(L, sv, " << sign(u) << ", " << v << ", rv, " << u << ");";
+    }
+    o << " E::close(L, " << v << ", rv); }\n";
   }
   o << "    // phase 2: antipodal pairs\n";
   for (int t = 0; t < nP; ++t) {
@@ -49,22 +58,23 @@ std::string jit_source(const HostProgram& P) {
     o << "    E::pair(L, " << (pr & 0xFFFF) << ", " << (pr >> 16) << ");\n";
   }
   o << "    // phase 3: region ids and the region tree\n";
-  o << "    int nR = 0, root = -1;\n    uint32_t err = 0;\n";
+  o << "    int nR = 0;\n    E::Adj roots = 0;\n";
   for (int v = 0; v < nV; ++v) {
     const int t = v > 0 ? (int)P.words[nV + (P.words[v] >> 16)] : -1;
-    o << "    E::vertex3(L, " << v << ", " << t << ", nR, root, err);\n";
+    o << "    E::vertex3(L, " << v << ", " << t << ", " << sign(v) << ", " << (t >= 0 ? sign(t) : std::string("0u"))
+      << ", nR, roots);\n";
   }
-  o << "    return E::finish(L, nR, root, err, errs);\n  }\n};\n\n}  // namespace pw\n\n";
+  o << "    return E::finish(L, nR, roots, errs);\n  }\n};\n\n}  // namespace pw\n\n";
   o << "extern \"C\" __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pw::Cfg<" << d << ">::WAVES_PER_EU))) void pw_jit_codes(const void* masks, int64_t n, "
        "uint64_t* codes, uint32_t* errflag) {\n"
        "  extern __shared__ uint32_t smem[];\n  pw::codes_body<"
     << d << ">(pw::JitEval{}, masks, n, codes, errflag, smem);\n}\n";
   o << "extern \"C\" __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pw::Cfg<" << d << ">::WAVES_PER_EU))) void pw_jit_hist(const void* masks, int64_t n, "
-       "uint64_t index_base, pw::HistDev h, uint32_t* errflag) {\n"
+       "uint64_t index_base, const pw::HistDev* h, uint32_t* errflag) {\n"
        "  extern __shared__ uint32_t smem[];\n  pw::hist_body<"
     << d << ">(pw::JitEval{}, masks, n, index_base, h, errflag, smem);\n}\n";
   o << "extern \"C\" __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pw::Cfg<" << d << ">::WAVES_PER_EU))) void pw_jit_enum(uint64_t first, uint64_t count, "
-       "pw::Runs runs, pw::HistDev h, uint32_t* errflag) {\n"
+       "pw::Runs runs, const pw::HistDev* h, uint32_t* errflag) {\n"
        "  extern __shared__ uint32_t smem[];\n  pw::enum_body<"
     << d << ">(pw::JitEval{}, first, count, runs, h, errflag, smem);\n}\n";
   return o.str();

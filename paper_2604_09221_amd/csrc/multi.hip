@@ -27,7 +27,7 @@ namespace pw {
 struct TriDesc {
   const uint32_t* prog;
   uint32_t* err;
-  HistDev hist;
+  const HistDev* hist;
   int32_t d;
   int32_t use_hist;
 };
@@ -163,7 +163,7 @@ extern "C" pw_status patchwork_scheme_batch_multi(const pw_tri_t* tris, int32_t 
     const int d = tris[t]->prog.d;
     desc[t].prog = tris[t]->d_prog;
     desc[t].err = tris[t]->d_err;
-    desc[t].hist = hists ? hists[t]->dev() : HistDev{};
+    desc[t].hist = hists ? hists[t]->d_dev : nullptr;
     desc[t].d = d;
     desc[t].use_hist = hists ? 1 : 0;
     max_words = std::max(max_words, lane_words_for(d));

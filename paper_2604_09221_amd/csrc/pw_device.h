@@ -83,8 +83,9 @@ struct Cfg {
   using Adj = typename cond<(RMAX <= 32), uint32_t, uint64_t>::type;
   using Code = typename cond<(D <= 9), uint64_t, u128>::type;
   static constexpr int ADJ_W = sizeof(Adj) / 4;
-  // vertex entries: u8 (parent index << 1 | sign) where odd d needs no
-  // parity and 7 bits index every vertex (d <= 7); u16 otherwise
+  // vertex entries: u8 (parent index) where odd d needs no parity flags
+  // and 7 bits index every vertex (d <= 7); u16 otherwise (parent index in
+  // bits 0-8, parity to the parent bit 9, odd-cycle flag bit 10)
   static constexpr bool NARROW = !EVEN && NV <= 128;
   using Ent = typename cond<NARROW, uint8_t, uint16_t>::type;
   static constexpr int EB = NARROW ? 1 : 2;
@@ -93,7 +94,8 @@ struct Cfg {
   static constexpr int CODE_W = 2 * harnack(D) <= 32 ? 1 : (int)(sizeof(Code) / 4);
   // per-lane LDS words:
   //   [0, E_WORDS)            vertex entries (phases 1-3)
-  //   [PAR_BASE, +PAR_WORDS)  u8 parent region of every region (phases 3-4)
+  //   [PAR_BASE, +PAR_WORDS)  parent region of every region, one byte row
+  //                           of the wave per region (phases 3-4)
   // after phase 3 the entry words hold, per region: child mask (ADJ_W
   // words) and code (CODE_W words).
   static constexpr int E_WORDS = (NV * EB + 3) / 4;
@@ -102,7 +104,7 @@ struct Cfg {
   static constexpr int TAIL_WORDS = CODE_BASE + RMAX * CODE_W;
   static constexpr int LOW_WORDS = E_WORDS > TAIL_WORDS ? E_WORDS : TAIL_WORDS;
   static constexpr int PAR_BASE = LOW_WORDS;
-  static constexpr int PAR_WORDS = (RMAX + 4) / 4;  // RMAX bytes + a spare slot
+  static constexpr int PAR_WORDS = (RMAX + 4) / 4;  // RMAX byte rows + a spare row
   static constexpr int LANE_WORDS = LOW_WORDS + PAR_WORDS;
   static constexpr int WAVE_BYTES = LANE_WORDS * 4 * 64;
   // waves per block: as many waves per CU as the 160 KiB of LDS allows,
@@ -119,28 +121,25 @@ struct Cfg {
 // ------------------------------------------------------------ lane memory
 
 // Vertex entries sit at byte v * ESTRIDE + EB * lane of the wave's area
-// (EB = 1 or 2 bytes per entry).  A u16 entry holds
-// parent << 7 | odd-cycle flag << 2 | parity << 1 | sign, so its parent
-// field is the byte offset of the parent's entry; a u8 entry holds
-// parent << 1 | sign.  Following a parent pointer costs two ALU operations
-// either way.  Word k of a lane (region data, reused entry space) sits at
-// byte k * 256 + 4 * lane.  For uniform v every lane hits its own bank; for
-// divergent parents a few lanes may share one.  Entry bytes of one lane
-// overlap words of others: phase 4 writes words only after every lane of
-// the wave has finished phase 3, which the wave's lockstep execution and
-// program order guarantee.
+// (EB = 1 or 2 bytes per entry) and hold the index of the vertex's
+// union-find parent (phases 1-2; for even d also the parity to the parent
+// and, at a root, the odd-cycle flag), then its region id (phase 3).  Signs
+// are not stored: the sign of a vertex is a fixed bit of the mask.  Word k
+// of a lane (region data, reused entry space) sits at byte k * 256 + 4 *
+// lane, and byte row x (the parent table) at byte x * 64 + lane.  For uniform v every lane hits its own bank; for divergent parents
+// a few lanes may share one.  Entry bytes of one lane overlap words of
+// others: phase 4 writes words only after every lane of the wave has
+// finished phase 3, which the wave's lockstep execution and program order
+// guarantee.
 struct Lane {
   uint32_t* w;  // word 0 of this lane; word k at w[k * 64]
   char* e;      // entry 0 of this lane
+  char* b;      // byte 0 of this lane in byte rows: byte row x at b[x * 64]
   __device__ __forceinline__ uint32_t& word(int k) const { return w[k * 64]; }
-  __device__ __forceinline__ uint8_t& byte(int k, int b) const {
-    return reinterpret_cast<uint8_t*>(w + k * 64)[b];
-  }
 };
 
-constexpr uint32_t kSign = 1u;
-constexpr uint32_t kParity = 2u;  // u16 entries only
-constexpr uint32_t kOdd = 4u;     // u16 entries only
+constexpr uint32_t kParity = 0x200u;  // u16 entries only
+constexpr uint32_t kOdd = 0x400u;     // u16 entries only
 
 template <typename T>
 __device__ __forceinline__ int clz_t(T x);
@@ -177,7 +176,11 @@ struct Eval {
   using Adj = typename C::Adj;
   using Code = typename C::Code;
   using Ent = typename C::Ent;
-  static constexpr int kShift = C::NARROW ? 1 : 7;  // index field of an entry
+  static constexpr uint32_t kIdx = C::NARROW ? 0x7Fu : 0x1FFu;  // index field of an entry
+  __device__ static __forceinline__ Adj one(int x) { return (Adj)1 << x; }
+
+  // parent index in an entry (u8 entries hold nothing else)
+  __device__ static __forceinline__ uint32_t idx(uint32_t e) { return C::NARROW ? e : (e & kIdx); }
 
   __device__ static __forceinline__ uint32_t bit(Mask m, int p) { return (uint32_t)(m >> p) & 1u; }
 
@@ -185,24 +188,15 @@ struct Eval {
   __device__ static __forceinline__ Ent& ent(const Lane& L, int v) {
     return *reinterpret_cast<Ent*>(L.e + v * C::ESTRIDE);
   }
-  __device__ static __forceinline__ Ent& at(const Lane& L, uint32_t off) { return *reinterpret_cast<Ent*>(L.e + off); }
-  // byte offset of vertex v's entry (relative to entry 0)
-  __device__ static __forceinline__ uint32_t self(int v) { return (uint32_t)(v * C::ESTRIDE); }
-  // parent offset stored in an entry, and the field that stores an offset
-  __device__ static __forceinline__ uint32_t off(uint32_t e) {
-    return C::NARROW ? (e & 0xFEu) << 5 : (e & 0xFF80u);
-  }
-  __device__ static __forceinline__ uint32_t enc(uint32_t o) { return C::NARROW ? o >> 5 : o; }
-  // end of phase 1 for v: its root so far and its sign
-  __device__ static __forceinline__ void close(const Lane& L, int v, uint32_t rv, uint32_t sv) {
-    ent(L, v) = (Ent)(enc(rv) | sv);
-  }
+  // end of phase 1 for v: its root so far
+  __device__ static __forceinline__ void close(const Lane& L, int v, uint32_t rv) { ent(L, v) = (Ent)rv; }
 
   // ---- region data (phases 3-4)
-  __device__ static __forceinline__ int par(const Lane& L, int x) { return L.byte(C::PAR_BASE + (x >> 2), x & 3); }
-  __device__ static __forceinline__ void set_par(const Lane& L, int x, int p) {
-    L.byte(C::PAR_BASE + (x >> 2), x & 3) = (uint8_t)p;
+  __device__ static __forceinline__ uint8_t& par_ref(const Lane& L, int x) {
+    return *reinterpret_cast<uint8_t*>(L.b + C::PAR_BASE * 256 + x * 64);
   }
+  __device__ static __forceinline__ int par(const Lane& L, int x) { return par_ref(L, x); }
+  __device__ static __forceinline__ void set_par(const Lane& L, int x, int p) { par_ref(L, x) = (uint8_t)p; }
   __device__ static __forceinline__ Adj load_adj(const Lane& L, int x) {
     if constexpr (C::ADJ_W == 1) {
       return L.word(C::CHILD_BASE + x);
@@ -229,40 +223,41 @@ struct Eval {
     for (int k = 0; k < W; ++k) L.word(C::CODE_BASE + W * x + k) = (uint32_t)(c >> (32 * k));
   }
 
-  // root offset of u and u's parity relative to it (parity: even d only)
+  // root of u and u's parity relative to it (parity: even d only)
   __device__ static __forceinline__ uint32_t find_parity(const Lane& L, int u, uint32_t& er, uint32_t& par) {
-    uint32_t r = self(u);
+    uint32_t r = (uint32_t)u;
     er = ent(L, u);
     par = 0;
-    while (off(er) != r) {
+    while (idx(er) != r) {
       if (C::EVEN) par ^= (er & kParity) ? 1u : 0u;
-      r = off(er);
-      er = at(L, r);
+      r = idx(er);
+      er = ent(L, (int)r);
     }
     return r;
   }
 
-  // Phase 1 step: v's earlier neighbour u; sv = sign of v, rv = offset of
-  // v's root so far (v's own until v is linked).  Written without branches
-  // apart from the walk to the root: every lane finds u's root (and points
-  // u's entry straight at it), and a lane whose signs differ, or whose
-  // union is void, stores into v's own entry instead -- that entry is
-  // scratch until phase 1 writes it once v is done, and no walk reaches v
-  // before that (every root found is an earlier vertex).
-  __device__ static __forceinline__ void edge(const Lane& L, uint32_t sv, int v, uint32_t& rv, int u) {
-    const uint32_t eu = ent(L, u);
-    uint32_t r = off(eu);
-    uint32_t er = at(L, r);
-    while (off(er) != r) {
-      r = off(er);
-      er = at(L, r);
+  // Phase 1 step: v's earlier neighbour u; sv, su = signs of v and u, rv =
+  // v's root so far (v itself until v is linked).  During phase 1 an entry
+  // is a bare parent index.  Written without branches apart from the walk
+  // to the root: every lane finds u's root (and points u straight at it),
+  // and a lane whose signs differ stores into v's own entry instead -- that
+  // entry is scratch until close() writes it, and no walk reaches v before
+  // that (every root found is an earlier vertex).
+  __device__ static __forceinline__ void edge(const Lane& L, uint32_t sv, uint32_t su, int v, uint32_t& rv, int u) {
+    uint32_t r = ent(L, u);
+    uint32_t er = ent(L, (int)r);
+    while (er != r) {
+      r = er;
+      er = ent(L, (int)r);
     }
-    ent(L, u) = (Ent)(enc(r) | (eu & kSign));
-    const bool same = (eu & kSign) == sv;
+    ent(L, u) = (Ent)r;
+    const bool same = su == sv;
     const uint32_t lo = r < rv ? r : rv, hi = r < rv ? rv : r;
     // same sign: the larger root hangs below the smaller one (a no-op
     // rewrite when r == rv; v's own entry when v is still its own root)
-    at(L, same ? hi : self(v)) = (Ent)(enc(lo) | sv);
+    int w = same ? (int)hi : v;
+    PW_OPAQUE(w);  // select the index, then address it (one shift-add)
+    ent(L, w) = (Ent)lo;
     rv = same ? lo : rv;
   }
 
@@ -272,59 +267,60 @@ struct Eval {
     const uint32_t ra = find_parity(L, a, ea, pa);
     const uint32_t rb = find_parity(L, b, eb, pb);
     if (ra == rb) {
-      if (C::EVEN && pa == pb) at(L, ra) = (Ent)(ea | kOdd);
+      if (C::EVEN && pa == pb) ent(L, (int)ra) = (Ent)(ea | kOdd);
     } else {
       const bool a_lo = ra < rb;
       const uint32_t lo = a_lo ? ra : rb, hi = a_lo ? rb : ra;
       const uint32_t elo = a_lo ? ea : eb, ehi = a_lo ? eb : ea;
       const uint32_t par = C::EVEN ? ((pa ^ pb ^ 1u) ? kParity : 0u) : 0u;
-      at(L, hi) = (Ent)((ehi & kSign) | par | enc(lo));
-      if (C::EVEN && (ehi & kOdd)) at(L, lo) = (Ent)(elo | kOdd);
+      ent(L, (int)hi) = (Ent)(par | lo);
+      if (C::EVEN && (ehi & kOdd)) ent(L, (int)lo) = (Ent)(elo | kOdd);
     }
   }
 
-  // Phase 3 step for vertex v with spanning-tree parent t (t < 0 for v = 0).
-  // A union-find root is the first vertex of its region and gets the next
-  // id.  The tree edges t(v)-v form a spanning tree of T<>.  Each oval
-  // separates two regions that both contain vertices, so some tree edge
-  // crosses it; the tree edge into the first vertex of a region B comes
-  // from the region across one of B's boundary ovals, and "parent(B) =
-  // region of t(first vertex of B)" is exactly the region adjacency tree,
-  // rooted at the region of vertex 0.  For odd d a crossed tree edge inside
-  // one region crosses the pseudo-line: that region is the root (Alg. 1).
-  // The entry of v becomes region id << kShift | sign.  Branch-free: a
-  // vertex that is not a root stores its (unused) parent-region byte into
-  // the spare slot RMAX of the parent table.
-  __device__ static __forceinline__ void vertex3(const Lane& L, int v, int t, int& nR, int& root, uint32_t& err) {
+  // Phase 3 step for vertex v with spanning-tree parent t (t < 0 for v = 0);
+  // sv, st = signs of v and t.  A union-find root is the first vertex of its
+  // region and gets the next id.  The tree edges t(v)-v form a spanning
+  // tree of T<>.  Each oval separates two regions that both contain
+  // vertices, so some tree edge crosses it; the tree edge into the first
+  // vertex of a region B comes from the region across one of B's boundary
+  // ovals, and "parent(B) = region of t(first vertex of B)" is exactly the
+  // region adjacency tree, rooted at the region of vertex 0.  The root of
+  // Alg. 1 is collected in `roots` as a set of region ids: for odd d the
+  // regions containing a crossed tree edge (an edge crossing the
+  // pseudo-line inside one region), for even d the regions whose union-find
+  // root carries the odd-cycle flag; finish() requires exactly one.  The
+  // entry of v becomes its region id.  Branch-free: a vertex that is not a
+  // root stores its (unused) parent-region byte into the spare row RMAX of
+  // the parent table.
+  __device__ static __forceinline__ void vertex3(const Lane& L, int v, int t, uint32_t sv, uint32_t st, int& nR,
+                                                 Adj& roots) {
     const uint32_t ev = ent(L, v);
-    const uint32_t sv = ev & kSign;
-    const uint32_t p = off(ev);
-    const bool is_root = p == self(v);
-    const uint32_t ep = at(L, p);  // p < v is relabelled already; a root reads its own entry
+    const uint32_t p = idx(ev);
+    const bool is_root = p == (uint32_t)v;
+    const uint32_t ep = ent(L, (int)p);  // p < v holds its region id already; a root reads its own entry
     const uint32_t et = ent(L, t < 0 ? 0 : t);
     // ids past the Harnack bound share the spare slot RMAX; finish()
     // rejects such a mask (nR > RMAX) before reading any region data
-    const int cid = is_root ? (nR < C::RMAX ? nR : C::RMAX) : (int)(ep >> kShift);
+    const int cid = is_root ? (nR < C::RMAX ? nR : C::RMAX) : (int)ep;
     nR += is_root ? 1 : 0;
     // keep the running count a plain running count (re-associating the
     // chain of increments would hold every vertex's flag in a register)
     PW_OPAQUE(nR);
-    if (C::EVEN) {
-      const bool mark = is_root && (ev & kOdd);
-      err |= (mark && root >= 0) ? kErrRoot : 0u;
-      root = mark ? cid : root;
-    } else {
-      const bool loop_here = t >= 0 && !is_root && (et & kSign) != sv && (int)(et >> kShift) == cid;
-      err |= (loop_here && root >= 0 && root != cid) ? kErrRoot : 0u;
-      root = loop_here ? cid : root;
-    }
-    const uint32_t pc = t >= 0 ? (et >> kShift) : 0xFFu;
-    set_par(L, is_root ? cid : C::RMAX, (int)pc);
-    ent(L, v) = (Ent)(((uint32_t)cid << kShift) | sv);
+    const bool hit = C::EVEN ? (is_root && (ev & kOdd)) : (t >= 0 && st != sv && (int)et == cid);
+    roots |= hit ? one(cid & (8 * (int)sizeof(Adj) - 1)) : (Adj)0;
+    const uint32_t pc = t >= 0 ? et : 0xFFu;
+    int slot = is_root ? cid : C::RMAX;
+    PW_OPAQUE(slot);
+    set_par(L, slot, (int)pc);
+    ent(L, v) = (Ent)cid;
   }
 
-  // Returns the scheme code (0 on a failed consistency check, with the
-  // reason or-ed into errs), walking the program in device memory.
+  __device__ static __forceinline__ uint32_t sign_of(const uint32_t* __restrict__ prog, Mask m, int v) {
+    const uint32_t rec = prog[v];
+    return bit(m, rec & 0x7F) ^ ((rec >> 7) & 1u);
+  }
+
   __device__ static u128 run(const uint32_t* __restrict__ prog, Mask m, const Lane& L, uint32_t& errs) {
     const uint32_t* nbr = prog + C::NV;
     const uint32_t* pairs = prog + C::NV + C::NE;
@@ -334,26 +330,33 @@ struct Eval {
       const uint32_t sv = bit(m, rec & 0x7F) ^ ((rec >> 7) & 1u);
       const int nn = (rec >> 8) & 0xFF;
       const int o = rec >> 16;
-      uint32_t rv = self(v);
-      for (int k = 0; k < nn; ++k) edge(L, sv, v, rv, (int)nbr[o + k]);
-      close(L, v, rv, sv);
+      uint32_t rv = (uint32_t)v;
+      for (int k = 0; k < nn; ++k) {
+        const int u = (int)nbr[o + k];
+        edge(L, sv, sign_of(prog, m, u), v, rv, u);
+      }
+      close(L, v, rv);
     }
     // phase 2: regions (antipodal identification)
     for (int t = 0; t < C::NP; ++t) pair(L, pairs[t] & 0xFFFF, pairs[t] >> 16);
     // phase 3: region ids and the region tree
-    int nR = 0, root = -1;
-    uint32_t err = 0;
-    for (int v = 0; v < C::NV; ++v) vertex3(L, v, v > 0 ? (int)nbr[prog[v] >> 16] : -1, nR, root, err);
-    return finish(L, nR, root, err, errs);
+    int nR = 0;
+    Adj roots = 0;
+    for (int v = 0; v < C::NV; ++v) {
+      const int t = v > 0 ? (int)nbr[prog[v] >> 16] : -1;
+      vertex3(L, v, t, sign_of(prog, m, v), t >= 0 ? sign_of(prog, m, t) : 0u, nR, roots);
+    }
+    return finish(L, nR, roots, errs);
   }
 
-  __device__ static __forceinline__ Adj one(int x) { return (Adj)1 << x; }
 
   // Phase 4: re-root the region tree at `root` and build the canonical
   // code (AHU) from the leaves up.
-  __device__ __forceinline__ static u128 finish(const Lane& L, int nR, int root, uint32_t err, uint32_t& errs) {
-    if (root < 0) err |= kErrRoot;
+  __device__ __forceinline__ static u128 finish(const Lane& L, int nR, Adj roots, uint32_t& errs) {
+    uint32_t err = 0;
+    if (roots == 0 || (roots & (roots - 1))) err |= kErrRoot;  // exactly one root region
     if (nR > C::RMAX) err |= kErrRegions;
+    const int root = roots ? ctz_t(roots) : 0;
     if (err) {
       errs |= err;
       return 0;
@@ -462,23 +465,39 @@ __device__ __forceinline__ typename Cfg<D>::Mask load_mask(const void* __restric
 constexpr int kMaxRuns = 4;
 
 // The free bit positions of an enumeration as at most kMaxRuns contiguous
-// runs: index bits [src, src+len) go to mask bits [dst, dst+len).
+// runs: index bits [src, src+len) go to mask bits [dst, dst+len).  Byte k
+// of src / len / dst describes run k.
 struct Runs {
-  int n;
-  uint8_t src[kMaxRuns], len[kMaxRuns], dst[kMaxRuns];
+  uint32_t n, src, len, dst;
+  __host__ __device__ int src_of(int k) const { return (int)((src >> (8 * k)) & 0xFF); }
+  __host__ __device__ int len_of(int k) const { return (int)((len >> (8 * k)) & 0xFF); }
+  __host__ __device__ int dst_of(int k) const { return (int)((dst >> (8 * k)) & 0xFF); }
+  __host__ __device__ void set(int k, int s_, int l_, int d_) {
+    const uint32_t m = ~(0xFFu << (8 * k));
+    src = (src & m) | ((uint32_t)s_ << (8 * k));
+    len = (len & m) | ((uint32_t)l_ << (8 * k));
+    dst = (dst & m) | ((uint32_t)d_ << (8 * k));
+  }
 };
 
 template <typename Mask>
-__device__ __forceinline__ Mask deposit(uint64_t idx, const Runs& r) {
-  const uint64_t keep0 = r.len[0] >= 64 ? ~0ull : ((1ull << r.len[0]) - 1);
-  Mask m = (Mask)((idx >> r.src[0]) & keep0) << r.dst[0];
+__device__ __forceinline__ Mask deposit_run(uint64_t idx, int src, int len, int dst) {
+  const uint64_t keep = len >= 64 ? ~0ull : ((1ull << len) - 1);
+  return (Mask)((idx >> src) & keep) << dst;
+}
+
+// The run descriptors are passed through an empty asm statement once per
+// batch, so the values derived from them are recomputed (a few scalar
+// instructions) instead of being held in scalar registers across the
+// evaluation.
+template <typename Mask>
+__device__ __forceinline__ Mask deposit(uint64_t idx, Runs r) {
+  asm volatile("" : "+s"(r.n), "+s"(r.src), "+s"(r.len), "+s"(r.dst));
+  Mask m = deposit_run<Mask>(idx, r.src_of(0), r.len_of(0), r.dst_of(0));
   if (r.n > 1) {  // uniform branch: only class-representative sweeps take it
 #pragma unroll
     for (int k = 1; k < kMaxRuns; ++k)
-      if (k < r.n) {
-        const uint64_t keep = r.len[k] >= 64 ? ~0ull : ((1ull << r.len[k]) - 1);
-        m |= (Mask)((idx >> r.src[k]) & keep) << r.dst[k];
-      }
+      if (k < (int)r.n) m |= deposit_run<Mask>(idx, r.src_of(k), r.len_of(k), r.dst_of(k));
   }
   return m;
 }
@@ -493,6 +512,13 @@ struct HistDev {
   uint32_t* overflow;
   uint32_t cap_mask;
 };
+
+// the table descriptor, read from device memory where it is needed (it is
+// not kept in scalar registers across the evaluation)
+__device__ __forceinline__ HistDev load_hist(const HistDev* hd) {
+  asm volatile("" : "+s"(hd));
+  return *hd;
+}
 
 __device__ __forceinline__ uint32_t hash_code(uint64_t lo, uint64_t hi) {
   uint64_t z = lo ^ (hi * 0x9E3779B97F4A7C15ull) ^ 0x632BE59BD9B4E019ull;
@@ -572,14 +598,15 @@ struct WaveTable {
     s1.put(0, 0, 0, 0);
   }
 
-  __device__ __forceinline__ void flush(const HistDev& h) {
+  __device__ __forceinline__ void flush(const HistDev* hd) {
+    const HistDev h = load_hist(hd);
     if (!s0.empty()) global_insert(h, s0.lo, s0.hi, s0.cnt, s0.wit);
     if (!s1.empty()) global_insert(h, s1.lo, s1.hi, s1.cnt, s1.wit);
     clear();
   }
 
   __device__ __forceinline__ void add(uint64_t lo, uint64_t hi, uint64_t k, uint64_t w, int lane,
-                                      const HistDev& h) {
+                                      const HistDev* h) {
     const bool h0 = s0.holds(lo, hi), h1 = s1.holds(lo, hi);
     if (__ballot(h0 || h1)) {
       if (h0) s0.bump(k, w);
@@ -604,7 +631,7 @@ struct WaveTable {
   // hold consecutive indices, so the lowest lane of a match carries the
   // smallest witness.
   __device__ __forceinline__ void add_batch(uint64_t lo, uint64_t hi, bool valid, uint64_t widx, int lane,
-                                            const HistDev& h) {
+                                            const HistDev* h) {
     uint64_t act = __ballot(valid && (lo | hi) != 0);
     while (act) {
       const int L = __ffsll((unsigned long long)act) - 1;
@@ -636,7 +663,7 @@ template <int D>
 __device__ __forceinline__ Lane lane_memory(uint32_t* smem, int lane_words) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t* base = smem + wave * lane_words * 64;
-  return Lane{base + lane, reinterpret_cast<char*>(base) + Cfg<D>::EB * lane};
+  return Lane{base + lane, reinterpret_cast<char*>(base) + Cfg<D>::EB * lane, reinterpret_cast<char*>(base) + lane};
 }
 
 // codes of n masks, one per thread, grid-stride
@@ -664,7 +691,7 @@ __device__ __forceinline__ void codes_body(const EV& ev, const void* __restrict_
 // histogram of n masks; each wave takes batches of 64 consecutive masks
 template <int D, class EV>
 __device__ __forceinline__ void hist_body(const EV& ev, const void* __restrict__ masks, int64_t n,
-                                          uint64_t index_base, const HistDev& h, uint32_t* __restrict__ errflag,
+                                          uint64_t index_base, const HistDev* h, uint32_t* __restrict__ errflag,
                                           uint32_t* smem) {
   using C = Cfg<D>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -687,7 +714,7 @@ __device__ __forceinline__ void hist_body(const EV& ev, const void* __restrict__
 // histogram of the masks generated from indices first .. first+count-1
 template <int D, class EV>
 __device__ __forceinline__ void enum_body(const EV& ev, uint64_t first, uint64_t count, const Runs& runs,
-                                          const HistDev& h, uint32_t* __restrict__ errflag, uint32_t* smem) {
+                                          const HistDev* h, uint32_t* __restrict__ errflag, uint32_t* smem) {
   using C = Cfg<D>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const Lane L = lane_memory<D>(smem, C::LANE_WORDS);

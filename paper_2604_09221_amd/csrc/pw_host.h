@@ -26,6 +26,7 @@ struct pw_hist {
   uint64_t* cnt = nullptr;
   uint64_t* wit = nullptr;
   uint32_t* overflow = nullptr;
+  pw::HistDev* d_dev = nullptr;  // device copy of dev(), read by the kernels
   pw::HistDev dev() const { return pw::HistDev{state, key, cnt, wit, overflow, (uint32_t)(cap - 1)}; }
 };
 

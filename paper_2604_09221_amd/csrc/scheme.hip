@@ -33,7 +33,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Cfg<D>::WAV
 
 template <int D>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Cfg<D>::WAVES_PER_EU))) void k_hist(const uint32_t* __restrict__ prog, const void* __restrict__ masks,
-                                              int64_t n, uint64_t index_base, HistDev h,
+                                              int64_t n, uint64_t index_base, const HistDev* __restrict__ h,
                                               uint32_t* __restrict__ errflag) {
   extern __shared__ uint32_t smem[];
   hist_body<D>(RtEval<D>{prog}, masks, n, index_base, h, errflag, smem);
@@ -41,7 +41,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Cfg<D>::WAV
 
 template <int D>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Cfg<D>::WAVES_PER_EU))) void k_enum(const uint32_t* __restrict__ prog, uint64_t first, uint64_t count,
-                                              Runs runs, HistDev h, uint32_t* __restrict__ errflag) {
+                                              Runs runs, const HistDev* __restrict__ h, uint32_t* __restrict__ errflag) {
   extern __shared__ uint32_t smem[];
   enum_body<D>(RtEval<D>{prog}, first, count, runs, h, errflag, smem);
 }
@@ -128,7 +128,7 @@ pw_status launch_hist(const pw_tri* t, const void* masks, int64_t n, uint64_t ba
   });
   if (t->jit_hist) {
     const void* m_ = masks;
-    HistDev hd = h->dev();
+    const HistDev* hd = h->d_dev;
     uint32_t* e_ = t->d_err;
     void* args[] = {&m_, &n, &base, &hd, &e_};
     PW_HIP(hipModuleLaunchKernel(t->jit_hist, blocks_for<D>(threads, n), 1, 1, threads, 1, 1, (unsigned)lds, s, args,
@@ -136,7 +136,7 @@ pw_status launch_hist(const pw_tri* t, const void* masks, int64_t n, uint64_t ba
     return PW_OK;
   }
   hipLaunchKernelGGL(k_hist<D>, dim3(blocks_for<D>(threads, n)), dim3(threads), lds, s, t->d_prog, masks, n, base,
-                     h->dev(), t->d_err);
+                     h->d_dev, t->d_err);
   PW_HIP(hipGetLastError());
   return PW_OK;
 }
@@ -155,7 +155,7 @@ pw_status launch_enum(const pw_tri* t, uint64_t first, uint64_t count, const Run
   const int64_t n = count > (uint64_t)INT64_MAX ? INT64_MAX : (int64_t)count;
   if (t->jit_enum) {
     Runs r_ = runs;
-    HistDev hd = h->dev();
+    const HistDev* hd = h->d_dev;
     uint32_t* e_ = t->d_err;
     void* args[] = {&first, &count, &r_, &hd, &e_};
     PW_HIP(hipModuleLaunchKernel(t->jit_enum, blocks_for<D>(threads, n), 1, 1, threads, 1, 1, (unsigned)lds, s, args,
@@ -163,7 +163,7 @@ pw_status launch_enum(const pw_tri* t, uint64_t first, uint64_t count, const Run
     return PW_OK;
   }
   hipLaunchKernelGGL(k_enum<D>, dim3(blocks_for<D>(threads, n)), dim3(threads), lds, s, t->d_prog, first, count,
-                     runs, h->dev(), t->d_err);
+                     runs, h->d_dev, t->d_err);
   PW_HIP(hipGetLastError());
   return PW_OK;
 }
@@ -274,6 +274,11 @@ pw_status pw_hist_create(int32_t capacity, pw_hist_t* out) {
   if (e == hipSuccess) e = hipMalloc(&h->cnt, sizeof(uint64_t) * capacity);
   if (e == hipSuccess) e = hipMalloc(&h->wit, sizeof(uint64_t) * capacity);
   if (e == hipSuccess) e = hipMalloc(&h->overflow, sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc(&h->d_dev, sizeof(HistDev));
+  if (e == hipSuccess) {
+    const HistDev hd = h->dev();
+    e = hipMemcpy(h->d_dev, &hd, sizeof hd, hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess) e = hipMemset(h->state, 0, sizeof(uint32_t) * capacity);
   if (e == hipSuccess) e = hipMemset(h->overflow, 0, sizeof(uint32_t));
   if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -283,6 +288,7 @@ pw_status pw_hist_create(int32_t capacity, pw_hist_t* out) {
     (void)hipFree(h->cnt);
     (void)hipFree(h->wit);
     (void)hipFree(h->overflow);
+    (void)hipFree(h->d_dev);
     delete h;
     return set_err(PW_ERR_HIP, "%s (code %d)", hipGetErrorString(e), (int)e);
   }
@@ -304,6 +310,7 @@ pw_status pw_hist_destroy(pw_hist_t h) {
   (void)hipFree(h->cnt);
   (void)hipFree(h->wit);
   (void)hipFree(h->overflow);
+  (void)hipFree(h->d_dev);
   delete h;
   return PW_OK;
 }
@@ -375,20 +382,18 @@ pw_status patchwork_scheme_enumerate_range(pw_tri_t t, uint64_t first, uint64_t 
     int e = b;
     while (e < nA && !((fixed_zero_bits[e / 64] >> (e % 64)) & 1)) ++e;
     if (runs.n == kMaxRuns) return set_err(PW_ERR_ARG, "the free bits form more than %d runs", kMaxRuns);
-    runs.src[runs.n] = (uint8_t)nfree;
-    runs.len[runs.n] = (uint8_t)(e - b);
-    runs.dst[runs.n] = (uint8_t)b;
+    runs.set(runs.n, nfree, e - b, b);
     ++runs.n;
     nfree += e - b;
     b = e;
   }
   // only the low 64 index bits are addressable
   for (int k = 0; k < runs.n; ++k) {
-    if (runs.src[k] >= 64) {
+    if (runs.src_of(k) >= 64) {
       runs.n = k;
       break;
     }
-    if (runs.src[k] + runs.len[k] > 64) runs.len[k] = (uint8_t)(64 - runs.src[k]);
+    if (runs.src_of(k) + runs.len_of(k) > 64) runs.set(k, runs.src_of(k), 64 - runs.src_of(k), runs.dst_of(k));
   }
   if (count == 0) return PW_OK;
   if (nfree < 64) {
