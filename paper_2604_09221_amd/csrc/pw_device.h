@@ -55,6 +55,10 @@ typedef __hip_internal::int64_t int64_t;
 #ifndef PW_OPAQUE
 #define PW_OPAQUE(x) asm volatile("" : "+v"(x))
 #endif
+// the same for a wave-uniform value (kept in a scalar register)
+#ifndef PW_OPAQUE_S
+#define PW_OPAQUE_S(x) asm volatile("" : "+s"(x))
+#endif
 
 namespace pw {
 
@@ -492,7 +496,10 @@ __device__ __forceinline__ Mask deposit_run(uint64_t idx, int src, int len, int 
 // evaluation.
 template <typename Mask>
 __device__ __forceinline__ Mask deposit(uint64_t idx, Runs r) {
-  asm volatile("" : "+s"(r.n), "+s"(r.src), "+s"(r.len), "+s"(r.dst));
+  PW_OPAQUE_S(r.n);
+  PW_OPAQUE_S(r.src);
+  PW_OPAQUE_S(r.len);
+  PW_OPAQUE_S(r.dst);
   Mask m = deposit_run<Mask>(idx, r.src_of(0), r.len_of(0), r.dst_of(0));
   if (r.n > 1) {  // uniform branch: only class-representative sweeps take it
 #pragma unroll
@@ -516,7 +523,7 @@ struct HistDev {
 // the table descriptor, read from device memory where it is needed (it is
 // not kept in scalar registers across the evaluation)
 __device__ __forceinline__ HistDev load_hist(const HistDev* hd) {
-  asm volatile("" : "+s"(hd));
+  PW_OPAQUE_S(hd);
   return *hd;
 }
 

@@ -1,0 +1,101 @@
+"""The kernels' evaluation logic, compiled for the CPU, against the oracle.
+
+The per-triangulation evaluator that the library generates (the same source
+hipRTC compiles for gfx950) is compiled here with g++ together with the
+device header, through tests/host_shim.h, and run lane by lane over one
+wave's LDS area.  Every code must equal the oracle's, and a lane may only
+write its own bytes of the area (entries, words, parent-table rows).  No GPU
+is needed; wave-level parts (histogram, ballots) are not covered here."""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_09221_amd import inputs as I
+from paper_2604_09221_amd import patchwork as pw
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(os.path.dirname(HERE), "paper_2604_09221_amd", "csrc")
+
+MAIN = r'''
+Dim3E threadIdx{0, 0, 0}, blockIdx{0, 0, 0}, blockDim{64, 1, 1}, gridDim{1, 1, 1};
+#include <cstring>
+#include <vector>
+int main(int argc, char** argv) {
+  using C = pw::Cfg<DEG>;
+  const long n = atol(argv[1]);
+  std::vector<uint64_t> in(2 * n), out(2 * n);
+  if (fread(in.data(), 8, 2 * n, stdin) != (size_t)(2 * n)) return 3;
+  const size_t bytes = (size_t)C::LANE_WORDS * 64 * 4;
+  uint32_t* smem = (uint32_t*)malloc(bytes);
+  memset(smem, 0xAB, bytes);
+  std::vector<unsigned char> snap(bytes), own(bytes);
+  long foreign = 0;
+  for (long i = 0; i < n; ++i) {
+    const int lane = (int)(i % 64);
+    threadIdx.x = lane;
+    const pw::Lane L = pw::lane_memory<DEG>(smem, C::LANE_WORDS);
+    memset(own.data(), 0, bytes);
+    for (int k = 0; k < C::LOW_WORDS; ++k)
+      for (int b = 0; b < 4; ++b) own[k * 256 + 4 * lane + b] = 1;
+    for (int v = 0; v < C::NV; ++v)
+      for (int b = 0; b < C::EB; ++b) own[v * C::ESTRIDE + C::EB * lane + b] = 1;
+    for (int x = 0; x < 4 * C::PAR_WORDS; ++x) own[C::PAR_BASE * 256 + x * 64 + lane] = 1;
+    memcpy(snap.data(), smem, bytes);
+    typename C::Mask m = (typename C::Mask)in[2 * i];
+    if (sizeof(m) == 16) m |= (typename C::Mask)((pw::u128)in[2 * i + 1] << 64);
+    uint32_t errs = 0;
+    const pw::u128 code = pw::JitEval{}(m, L, errs);
+    out[2 * i] = errs ? 0 : (uint64_t)code;
+    out[2 * i + 1] = errs ? 0 : (uint64_t)(code >> 64);
+    const unsigned char* cur = (const unsigned char*)smem;
+    for (size_t b = 0; b < bytes; ++b)
+      if (!own[b] && cur[b] != snap[b]) {
+        ++foreign;
+        break;
+      }
+  }
+  fwrite(out.data(), 8, 2 * n, stdout);
+  free(smem);
+  return foreign ? 4 : 0;
+}
+'''
+
+
+def _compile(tmp_path, d, edges):
+    src = pw.jit_source(d, edges)
+    src = src[:src.index('extern "C"')]          # the evaluator; the kernels need a GPU
+    path = tmp_path / f"emu_d{d}.cpp"
+    path.write_text('#include "host_shim.h"\n' + src + MAIN.replace("DEG", str(d)))
+    exe = tmp_path / f"emu_d{d}"
+    subprocess.check_call(["g++", "-O1", "-std=c++17", "-w", "-fsanitize=address,undefined",
+                           "-fno-sanitize-recover=undefined", "-I", HERE, "-I", CSRC, "-o", str(exe), str(path)])
+    return exe
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+@pytest.mark.parametrize("d,noise,seed,n", [(4, None, 0, 3000), (5, 1.0, 2, 2000), (6, 1.0, 3, 2000),
+                                            (7, None, 0, 3000), (7, 1.0, 4, 2000), (9, None, 0, 600)])
+def test_evaluator_on_host_matches_oracle(tmp_path, d, noise, seed, n):
+    edges = I.standard_triangulation(d) if noise is None else I.lift_triangulation(d, seed, noise=noise)
+    exe = _compile(tmp_path, d, edges)
+    masks = np.ascontiguousarray(I.random_masks(d, seed + 11, n).astype(np.uint64))
+    # first rows: the Harnack distribution (the most regions), all '+', all
+    # '-' except sigma(0,0), and every single flip of the Harnack mask
+    nA = I.n_points(d)
+    h = I.harnack_mask(d)
+    special = [h, 0, ((1 << nA) - 1) & ~1] + [h ^ (1 << k) for k in range(1, nA)]
+    for i, x in enumerate(special[:n]):
+        masks[i, 0] = x & ((1 << 64) - 1)
+        masks[i, 1] = x >> 64
+    run = subprocess.run([str(exe), str(n)], input=masks.tobytes(), capture_output=True)
+    assert run.returncode != 4, "a lane wrote outside its own LDS bytes"
+    assert run.returncode == 0, run.stderr.decode()[-2000:]
+    got = np.frombuffer(run.stdout, dtype=np.uint64).reshape(n, 2)
+    want = oracle.scheme_many(d, edges, masks, threads=4)
+    assert np.array_equal(got, want)
