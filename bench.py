@@ -147,8 +147,9 @@ def bench_multi(args):
 
 def bench_learned(args):
     """d = 8 (seed-8 lift = the standard triangulation): distinct schemes
-    per GPU-second for uniform sampling, the learned proposal and its
-    ablation (random ranking), each judged by the exact kernel."""
+    per GPU-second for uniform sampling, the learned proposal (mutations of
+    rare witnesses guided by the network's input gradient) and its ablation
+    (the same search with uniform flips), each judged by the exact kernel."""
     import torch
 
     from paper_2604_09221_amd import inputs as I
@@ -162,8 +163,11 @@ def bench_learned(args):
     budget = 1 << args.budget_log2
     log = (lambda m: print(m, file=sys.stderr, flush=True))
     res = [Lr.run_uniform(tri, d, budget)]
-    res.append(Lr.run_search(tri, d, budget, use_net=True, train_n=min(1 << 24, budget // 4), log=log))
-    res.append(Lr.run_search(tri, d, budget, use_net=False, train_n=min(1 << 24, budget // 4), log=log))
+    per_round = max(1 << 20, budget >> 8)
+    res.append(Lr.run_search(tri, d, budget, use_net=True, train_n=min(1 << 24, budget // 4), per_round=per_round,
+                             log=log))
+    res.append(Lr.run_search(tri, d, budget, use_net=False, train_n=min(1 << 24, budget // 4), per_round=per_round,
+                             log=log))
     for r in res:
         r["distinct_per_gpu_second"] = r["distinct"] / r["gpu_seconds"]
     return {

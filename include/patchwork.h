@@ -262,8 +262,30 @@ pw_status pw_features(const uint64_t *codes, int64_t n, int32_t *labels, hipStre
 pw_status pw_mlp_softmax_xent(const float *Y, const int32_t *labels, int64_t n, float *dY32, uint16_t *dY16,
                               float *loss, hipStream_t stream);
 
-/* out[j] = sum over rows k < n of X[k * cols + j] (bias gradients). */
-pw_status pw_mlp_colsum(const float *X, int64_t n, int32_t cols, float *out, hipStream_t stream);
+/*
+ * out[j] = sum over rows k < n of X[k * cols + j] (bias gradients); with
+ * accumulate != 0 the sums are added to out instead (out must then hold
+ * valid values; the additions are atomic, in no fixed order).
+ */
+pw_status pw_mlp_colsum(const float *X, int64_t n, int32_t cols, float *out, int32_t accumulate,
+                        hipStream_t stream);
+
+/*
+ * counts[start_h + labels[k * 6 + h]] += 1 over rows k < n and the six heads
+ * (start_h = 0, 23, 28, 37, 46, 55; counts: 64 uint32, not zeroed here).
+ * Labels must be valid classes of pw_features.
+ */
+pw_status pw_label_counts(const int32_t *labels, int64_t n, uint32_t *counts, hipStream_t stream);
+
+/* x[i] = v for i < n. */
+pw_status pw_fill_f32(float *x, int64_t n, float v, hipStream_t stream);
+
+/*
+ * Gradient of the novelty score (pw_mlp_score) of each row of Y with respect
+ * to the logits, as bf16 (n x 64): for head h with p = softmax(Y_h) and
+ * s_h = sum_j p_j rarity_j, d s_h / d Y_j = p_j (rarity_j - s_h).
+ */
+pw_status pw_mlp_score_grad(const float *Y, const float *rarity, int64_t n, uint16_t *dY16, hipStream_t stream);
 
 /*
  * One Adam step (Kingma & Ba 2015, bias-corrected, step >= 1) on n fp32
@@ -290,6 +312,19 @@ pw_status pw_mlp_score(const float *Y, const float *rarity, int64_t n, float *sc
  */
 pw_status pw_mutate(const uint64_t *parents, int64_t n_parents, int64_t n, int32_t n_bits, int32_t flips,
                     uint64_t seed, uint64_t *out, hipStream_t stream);
+
+/*
+ * Guided mutants: out[k] = parents[p], p = k mod n_parents, with `flips` bit
+ * positions in [1, n_bits) toggled.  Each position j is drawn with
+ * probability proportional to exp(gain_j / (temp * max |gain|)), gain_j =
+ * -2 x_j dX[p * ldx + j] (x_j = +1 for '+', -1 for '-'; dX = gradient of
+ * the network's novelty score with respect to its input), except that a
+ * fraction `explore` of the draws is uniform.  Random numbers: the
+ * SplitMix64 finaliser applied to a key of (seed, k, flip index).
+ */
+pw_status pw_mutate_guided(const uint64_t *parents, const float *dX, int64_t ldx, int64_t n_parents, int64_t n,
+                           int32_t n_bits, int32_t flips, float temp, float explore, uint64_t seed, uint64_t *out,
+                           hipStream_t stream);
 
 /*
  * Uniform masks: word w of mask k is the SplitMix64 output number

@@ -41,16 +41,16 @@ std::string jit_source(const HostProgram& P) {
     std::string x = "E::bit(m, " + std::to_string(p) + ")";
     return g ? "(" + x + " ^ 1u)" : x;
   };
-  o << "    // phase 1: components of same-sign vertices\n";
+  o << "    // phase 1: components of same-sign vertices; r<u> = a root u had\n";
   for (int v = 0; v < nV; ++v) {
     const uint32_t rec = P.words[v];
     const int n = (rec >> 8) & 0xFF, off = rec >> 16;
-    o << "    { const uint32_t sv = " << sign(v) << "; uint32_t rv = " << v << "u;";
+    o << "    uint32_t r" << v << " = " << v << "u; { const uint32_t sv = " << sign(v) << ";";
     for (int k = 0; k < n; ++k) {
       const int u = (int)P.words[nV + off + k];
-      o << " E::edge(L, sv, " << sign(u) << ", " << v << ", rv, " << u << ");";
+      o << " E::edge_r(L, sv, " << sign(u) << ", " << v << ", r" << v << ", r" << u << ");";
     }
-    o << " E::close(L, " << v << ", rv); }\n";
+    o << " E::close(L, " << v << ", r" << v << "); }\n";
   }
   o << "    // phase 2: antipodal pairs\n";
   for (int t = 0; t < nP; ++t) {

@@ -333,6 +333,41 @@ __global__ void k_score(const float* __restrict__ Y, const float* __restrict__ r
   score[k] = s;
 }
 
+// counts[kHeadStart[h] + labels[k][h]] += 1 for every row k and head h
+__global__ void k_label_counts(const int32_t* __restrict__ labels, int64_t n, uint32_t* __restrict__ counts) {
+  __shared__ uint32_t c[64];
+  if (threadIdx.x < 64) c[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    for (int h = 0; h < 6; ++h) atomicAdd(&c[kHeadStart[h] + labels[6 * k + h]], 1u);
+  __syncthreads();
+  if (threadIdx.x < 64 && c[threadIdx.x]) atomicAdd(&counts[threadIdx.x], c[threadIdx.x]);
+}
+
+// Gradient of the novelty score with respect to the logits: for head h with
+// p = softmax(Y_h) and s_h = sum_j p_j rarity_j, d s_h / d Y_j =
+// p_j (rarity_j - s_h).  Written as bf16 (the operand of the backward
+// products).
+__global__ void k_score_grad(const float* __restrict__ Y, const float* __restrict__ rarity, int64_t n,
+                             uint16_t* __restrict__ dY16) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const float* y = Y + 64 * k;
+  for (int h = 0; h < 6; ++h) {
+    const int a = kHeadStart[h], e = kHeadStart[h + 1];
+    float mx = -INFINITY;
+    for (int j = a; j < e; ++j) mx = fmaxf(mx, y[j]);
+    float z = 0.f, acc = 0.f;
+    for (int j = a; j < e; ++j) {
+      const float p = expf(y[j] - mx);
+      z += p;
+      acc += p * rarity[j];
+    }
+    const float sh = acc / z;
+    for (int j = a; j < e; ++j) dY16[64 * k + j] = f32_to_bf16(expf(y[j] - mx) / z * (rarity[j] - sh));
+  }
+}
+
 // SplitMix64 finaliser as a counter-based generator: out(key) depends only
 // on key (Steele, Lea, Flood 2014).
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
@@ -353,6 +388,61 @@ __global__ void k_mutate(const uint64_t* __restrict__ parents, int64_t n_parents
   for (int f = 0; f < flips; ++f) {
     const uint64_t r = mix64(seed ^ mix64((uint64_t)k * 0x100000001B3ull + (uint64_t)f));
     const int b = 1 + (int)(r % (uint64_t)(n_bits - 1));
+    if (b < 64)
+      lo ^= 1ull << b;
+    else
+      hi ^= 1ull << (b - 64);
+  }
+  out[2 * k] = lo;
+  out[2 * k + 1] = hi;
+}
+
+// Guided mutants: candidate k = parent p = k % n_parents with `flips` bits
+// toggled, each drawn from [1, n_bits) with probability proportional to
+// exp(gain_j / (temp * max_j |gain_j|)) (a fraction `explore` of the draws
+// is uniform instead), where gain_j = -2 x_j dX[p][j] is the first-order
+// change of the network's novelty score when bit j of the parent flips
+// (x_j = +1 for '+', -1 for '-'; dX = d score / d input).
+__global__ void k_mutate_guided(const uint64_t* __restrict__ parents, const float* __restrict__ dX, int64_t ldx,
+                                int64_t n_parents, int64_t n, int n_bits, int flips, float temp, float explore,
+                                uint64_t seed, uint64_t* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int64_t p = k % n_parents;
+  const uint64_t lo0 = parents[2 * p], hi0 = parents[2 * p + 1];
+  const float* g = dX + p * ldx;
+  auto gain = [&](int j) {
+    const uint64_t b = j < 64 ? (lo0 >> j) & 1 : (hi0 >> (j - 64)) & 1;
+    return (b ? 2.f : -2.f) * g[j];
+  };
+  float gmax = -INFINITY, amax = 0.f;
+  for (int j = 1; j < n_bits; ++j) {
+    const float a = gain(j);
+    gmax = fmaxf(gmax, a);
+    amax = fmaxf(amax, fabsf(a));
+  }
+  const float inv = 1.f / (temp * amax + 1e-30f);
+  float z = 0.f;
+  for (int j = 1; j < n_bits; ++j) z += expf((gain(j) - gmax) * inv);
+  uint64_t lo = lo0, hi = hi0;
+  for (int f = 0; f < flips; ++f) {
+    const uint64_t r = mix64(seed ^ mix64((uint64_t)k * 0x100000001B3ull + (uint64_t)f));
+    const float u = (float)(r >> 40) * (1.f / 16777216.f);          // 24 bits
+    int b;
+    if ((float)((r >> 8) & 0xFFFF) * (1.f / 65536.f) < explore) {
+      b = 1 + (int)((r & 0xFF) % (uint64_t)(n_bits - 1));
+    } else {
+      const float target = u * z;
+      float acc = 0.f;
+      b = n_bits - 1;
+      for (int j = 1; j < n_bits; ++j) {
+        acc += expf((gain(j) - gmax) * inv);
+        if (acc > target) {
+          b = j;
+          break;
+        }
+      }
+    }
     if (b < 64)
       lo ^= 1ull << b;
     else
@@ -498,9 +588,9 @@ pw_status pw_mlp_softmax_xent(const float* Y, const int32_t* labels, int64_t n, 
   return PW_OK;
 }
 
-pw_status pw_mlp_colsum(const float* X, int64_t n, int32_t cols, float* out, hipStream_t s) {
+pw_status pw_mlp_colsum(const float* X, int64_t n, int32_t cols, float* out, int32_t accumulate, hipStream_t s) {
   if (n < 0 || cols <= 0 || !X || !out) return set_err(PW_ERR_ARG, "bad colsum arguments");
-  hipLaunchKernelGGL(k_fill, dim3(grid1d(cols, 256)), dim3(256), 0, s, out, (int64_t)cols, 0.f);
+  if (!accumulate) hipLaunchKernelGGL(k_fill, dim3(grid1d(cols, 256)), dim3(256), 0, s, out, (int64_t)cols, 0.f);
   if (n == 0) return PW_OK;
   hipLaunchKernelGGL(k_colsum, dim3(grid1d(cols, 256), (unsigned)((n + kColRows - 1) / kColRows)), dim3(256), 0, s,
                      X, n, cols, out);
@@ -514,6 +604,44 @@ pw_status pw_mlp_adam(float* w, const float* g, float* m, float* v, int64_t n, f
   const float bc1 = 1.f - std::pow(beta1, (float)step), bc2 = 1.f - std::pow(beta2, (float)step);
   hipLaunchKernelGGL(k_adam, dim3(grid1d(n, 256)), dim3(256), 0, s, w, g, m, v, n, lr, beta1, beta2, eps, bc1, bc2,
                      w16);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
+pw_status pw_label_counts(const int32_t* labels, int64_t n, uint32_t* counts, hipStream_t s) {
+  if (n < 0 || !labels || !counts) return set_err(PW_ERR_ARG, "bad label-count arguments");
+  if (n == 0) return PW_OK;
+  const int blocks = (int)std::min<int64_t>(grid1d(n, 256), 1024);
+  hipLaunchKernelGGL(k_label_counts, dim3(blocks), dim3(256), 0, s, labels, n, counts);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
+pw_status pw_fill_f32(float* x, int64_t n, float v, hipStream_t s) {
+  if (n < 0 || (n > 0 && !x)) return set_err(PW_ERR_ARG, "bad fill arguments");
+  if (n == 0) return PW_OK;
+  hipLaunchKernelGGL(k_fill, dim3(grid1d(n, 256)), dim3(256), 0, s, x, n, v);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
+pw_status pw_mlp_score_grad(const float* Y, const float* rarity, int64_t n, uint16_t* dY16, hipStream_t s) {
+  if (n < 0 || !Y || !rarity || !dY16) return set_err(PW_ERR_ARG, "bad score-gradient arguments");
+  if (n == 0) return PW_OK;
+  hipLaunchKernelGGL(k_score_grad, dim3(grid1d(n, 256)), dim3(256), 0, s, Y, rarity, n, dY16);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
+pw_status pw_mutate_guided(const uint64_t* parents, const float* dX, int64_t ldx, int64_t n_parents, int64_t n,
+                           int32_t n_bits, int32_t flips, float temp, float explore, uint64_t seed, uint64_t* out,
+                           hipStream_t s) {
+  if (n < 0 || n_parents <= 0 || n_bits < 2 || n_bits > 128 || ldx < n_bits || flips < 0 || !(temp > 0.f) ||
+      !parents || !dX || !out)
+    return set_err(PW_ERR_ARG, "bad guided-mutation arguments");
+  if (n == 0) return PW_OK;
+  hipLaunchKernelGGL(k_mutate_guided, dim3(grid1d(n, 256)), dim3(256), 0, s, parents, dX, ldx, n_parents, n, n_bits,
+                     flips, temp, explore, seed, out);
   PW_HIP(hipGetLastError());
   return PW_OK;
 }

@@ -110,6 +110,11 @@ struct Cfg {
   static constexpr int PAR_BASE = LOW_WORDS;
   static constexpr int PAR_WORDS = (RMAX + 4) / 4;  // RMAX byte rows + a spare row
   static constexpr int LANE_WORDS = LOW_WORDS + PAR_WORDS;
+  // kernels for one triangulation keep the parent table in a __shared__
+  // array of its own (PAR_ROWS byte rows per wave) and the rest in the
+  // dynamic area (DYN_WORDS per lane)
+  static constexpr int PAR_ROWS = RMAX + 1;
+  static constexpr int DYN_WORDS = LOW_WORDS;
   static constexpr int WAVE_BYTES = LANE_WORDS * 4 * 64;
   // waves per block: as many waves per CU as the 160 KiB of LDS allows,
   // in blocks of at most 4 waves
@@ -197,7 +202,7 @@ struct Eval {
 
   // ---- region data (phases 3-4)
   __device__ static __forceinline__ uint8_t& par_ref(const Lane& L, int x) {
-    return *reinterpret_cast<uint8_t*>(L.b + C::PAR_BASE * 256 + x * 64);
+    return *reinterpret_cast<uint8_t*>(L.b + x * 64);
   }
   __device__ static __forceinline__ int par(const Lane& L, int x) { return par_ref(L, x); }
   __device__ static __forceinline__ void set_par(const Lane& L, int x, int p) { par_ref(L, x) = (uint8_t)p; }
@@ -261,6 +266,28 @@ struct Eval {
     // rewrite when r == rv; v's own entry when v is still its own root)
     int w = same ? (int)hi : v;
     PW_OPAQUE(w);  // select the index, then address it (one shift-add)
+    ent(L, w) = (Ent)lo;
+    rv = same ? lo : rv;
+  }
+
+  // Phase 1 step of the specialised kernels: as edge(), but the walk starts
+  // from ru, a register holding a root u had at some earlier time (u's root
+  // when u was closed, refreshed by each later walk from u), so the first
+  // LDS read does not wait for another one.  ru is refreshed with u's
+  // current root; nothing is written back to u's entry.
+  __device__ static __forceinline__ void edge_r(const Lane& L, uint32_t sv, uint32_t su, int v, uint32_t& rv,
+                                                uint32_t& ru) {
+    uint32_t r = ru;
+    uint32_t er = ent(L, (int)r);
+    while (er != r) {
+      r = er;
+      er = ent(L, (int)r);
+    }
+    ru = r;
+    const bool same = su == sv;
+    const uint32_t lo = r < rv ? r : rv, hi = r < rv ? rv : r;
+    int w = same ? (int)hi : v;
+    PW_OPAQUE(w);
     ent(L, w) = (Ent)lo;
     rv = same ? lo : rv;
   }
@@ -665,12 +692,26 @@ struct RtEval {
   }
 };
 
-// this lane's view of its wave's area (lane_words words per lane)
+// this lane's view of its wave's area (lane_words words per lane, the
+// parent table at word PAR_BASE)
 template <int D>
 __device__ __forceinline__ Lane lane_memory(uint32_t* smem, int lane_words) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t* base = smem + wave * lane_words * 64;
-  return Lane{base + lane, reinterpret_cast<char*>(base) + Cfg<D>::EB * lane, reinterpret_cast<char*>(base) + lane};
+  char* cb = reinterpret_cast<char*>(base);
+  return Lane{base + lane, cb + Cfg<D>::EB * lane, cb + Cfg<D>::PAR_BASE * 256 + lane};
+}
+
+// the same with the parent table in its own __shared__ array (par: PAR_ROWS
+// rows of 64 bytes per wave): the compiler then knows that parent-table
+// stores do not alias entry loads and can issue those loads early
+template <int D>
+__device__ __forceinline__ Lane lane_memory_split(uint32_t* smem, uint8_t* par) {
+  using C = Cfg<D>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t* base = smem + wave * C::DYN_WORDS * 64;
+  return Lane{base + lane, reinterpret_cast<char*>(base) + C::EB * lane,
+              reinterpret_cast<char*>(par) + wave * C::PAR_ROWS * 64 + lane};
 }
 
 // codes of n masks, one per thread, grid-stride
@@ -679,7 +720,8 @@ __device__ __forceinline__ void codes_body(const EV& ev, const void* __restrict_
                                            uint64_t* __restrict__ codes, uint32_t* __restrict__ errflag,
                                            uint32_t* smem) {
   using C = Cfg<D>;
-  const Lane L = lane_memory<D>(smem, C::LANE_WORDS);
+  __shared__ uint8_t par_rows[C::WAVES * C::PAR_ROWS * 64];
+  const Lane L = lane_memory_split<D>(smem, par_rows);
   uint32_t errs = 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
@@ -702,7 +744,8 @@ __device__ __forceinline__ void hist_body(const EV& ev, const void* __restrict__
                                           uint32_t* smem) {
   using C = Cfg<D>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const Lane L = lane_memory<D>(smem, C::LANE_WORDS);
+  __shared__ uint8_t par_rows[C::WAVES * C::PAR_ROWS * 64];
+  const Lane L = lane_memory_split<D>(smem, par_rows);
   WaveTable tab;
   tab.clear();
   uint32_t errs = 0;
@@ -724,7 +767,8 @@ __device__ __forceinline__ void enum_body(const EV& ev, uint64_t first, uint64_t
                                           const HistDev* h, uint32_t* __restrict__ errflag, uint32_t* smem) {
   using C = Cfg<D>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const Lane L = lane_memory<D>(smem, C::LANE_WORDS);
+  __shared__ uint8_t par_rows[C::WAVES * C::PAR_ROWS * 64];
+  const Lane L = lane_memory_split<D>(smem, par_rows);
   WaveTable tab;
   tab.clear();
   uint32_t errs = 0;

@@ -94,7 +94,7 @@ template <int D>
 pw_status launch_codes(const pw_tri* t, const void* masks, int64_t n, uint64_t* codes, hipStream_t s) {
   using C = Cfg<D>;
   const int threads = 64 * C::WAVES;
-  const size_t lds = (size_t)C::LANE_WORDS * 4 * 64 * C::WAVES;
+  const size_t lds = (size_t)C::DYN_WORDS * 4 * 64 * C::WAVES;  // + the static parent table
   static std::once_flag once;
   std::call_once(once, [] {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_codes<D>),
@@ -120,7 +120,7 @@ pw_status launch_hist(const pw_tri* t, const void* masks, int64_t n, uint64_t ba
                       hipStream_t s) {
   using C = Cfg<D>;
   const int threads = 64 * C::WAVES;
-  const size_t lds = (size_t)C::LANE_WORDS * 4 * 64 * C::WAVES;
+  const size_t lds = (size_t)C::DYN_WORDS * 4 * 64 * C::WAVES;  // + the static parent table
   static std::once_flag once;
   std::call_once(once, [] {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hist<D>),
@@ -146,7 +146,7 @@ pw_status launch_enum(const pw_tri* t, uint64_t first, uint64_t count, const Run
                       hipStream_t s) {
   using C = Cfg<D>;
   const int threads = 64 * C::WAVES;
-  const size_t lds = (size_t)C::LANE_WORDS * 4 * 64 * C::WAVES;
+  const size_t lds = (size_t)C::DYN_WORDS * 4 * 64 * C::WAVES;  // + the static parent table
   static std::once_flag once;
   std::call_once(once, [] {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_enum<D>),

@@ -38,7 +38,11 @@ def _bind():
     L.pw_mlp_encode.argtypes = [vp, i64, i32, i32, vp, vp]
     L.pw_features.argtypes = [vp, i64, vp, vp]
     L.pw_mlp_softmax_xent.argtypes = [vp, vp, i64, vp, vp, vp, vp]
-    L.pw_mlp_colsum.argtypes = [vp, i64, i32, vp, vp]
+    L.pw_mlp_colsum.argtypes = [vp, i64, i32, vp, i32, vp]
+    L.pw_fill_f32.argtypes = [vp, i64, f32, vp]
+    L.pw_label_counts.argtypes = [vp, i64, vp, vp]
+    L.pw_mlp_score_grad.argtypes = [vp, vp, i64, vp, vp]
+    L.pw_mutate_guided.argtypes = [vp, vp, i64, i64, i64, i32, i32, f32, f32, u64, vp, vp]
     L.pw_mlp_adam.argtypes = [vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp, vp]
     L.pw_mlp_score.argtypes = [vp, vp, i64, vp, vp]
     L.pw_to_bf16.argtypes = [vp, i64, vp, vp]
@@ -48,7 +52,8 @@ def _bind():
     L.pw_bin_floats.argtypes = [vp, i64, f32, f32, i32, vp, vp]
     for n in ("pw_mlp_gemm", "pw_mlp_encode", "pw_features", "pw_mlp_softmax_xent", "pw_mlp_colsum",
               "pw_mlp_adam", "pw_mlp_score", "pw_to_bf16", "pw_mutate", "pw_select",
-              "pw_random_masks", "pw_bin_floats"):
+              "pw_random_masks", "pw_bin_floats", "pw_fill_f32", "pw_mlp_score_grad", "pw_mutate_guided",
+              "pw_label_counts"):
         getattr(L, n).restype = i32
     _bound = True
     return L
@@ -98,8 +103,28 @@ def to_bf16(t32):
     return out
 
 
+# parameter layout in one flat fp32 buffer (every offset a multiple of 64
+# elements, so every matrix view is 256-byte aligned)
+LAYOUT = (("W1", (WIDTH_IN, HIDDEN)), ("b1", (HIDDEN,)), ("W2", (HIDDEN, HIDDEN)), ("b2", (HIDDEN,)),
+          ("W3", (HIDDEN, OUT)), ("b3", (OUT,)))
+
+
+def _offsets():
+    off, o = {}, 0
+    for k, shp in LAYOUT:
+        n = int(np.prod(shp))
+        off[k] = (o, n, shp)
+        o += n
+    return off, o
+
+
 class MLP:
-    """Device parameters: fp32 masters, bf16 copies, Adam moments."""
+    """Device parameters in flat buffers: fp32 masters P, gradients G (plus
+    one slot for the loss), Adam moments M, V and the bf16 copy W16, each
+    with per-tensor views.  One training step is 14 kernel launches: zero G,
+    three forward products, the loss, three weight-gradient products, three
+    bias-gradient column sums, two input-gradient products and one Adam
+    update over all parameters."""
 
     def __init__(self, n_in=45, seed=0, device="cuda"):
         import torch
@@ -115,19 +140,44 @@ class MLP:
         W1[n_in:] = 0.0
         host = {"W1": W1, "b1": np.zeros(HIDDEN, np.float32), "W2": he(HIDDEN, (HIDDEN, HIDDEN)),
                 "b2": np.zeros(HIDDEN, np.float32), "W3": he(HIDDEN, (HIDDEN, OUT)), "b3": np.zeros(OUT, np.float32)}
-        self.P = {k: torch.from_numpy(v).to(device) for k, v in host.items()}
-        self.G = {k: torch.zeros_like(v) for k, v in self.P.items()}
-        self.M = {k: torch.zeros_like(v) for k, v in self.P.items()}
-        self.V = {k: torch.zeros_like(v) for k, v in self.P.items()}
-        self.W16 = {k: torch.empty(self.P[k].shape, dtype=torch.int16, device=device) for k in ("W1", "W2", "W3")}
+        self.off, self.n_par = _offsets()
+        flat = np.concatenate([host[k].reshape(-1) for k, _ in LAYOUT])
+        self.Pf = torch.from_numpy(flat).to(device)
+        self.Gf = torch.zeros(self.n_par + 64, dtype=torch.float32, device=device)   # + loss slot
+        self.Mf = torch.zeros_like(self.Pf)
+        self.Vf = torch.zeros_like(self.Pf)
+        self.W16f = torch.empty(self.n_par, dtype=torch.int16, device=device)
+        self.P = self._views(self.Pf)
+        self.G = self._views(self.Gf)
+        self.M = self._views(self.Mf)
+        self.V = self._views(self.Vf)
+        self.W16 = self._views(self.W16f)
+        self.loss = self.Gf[self.n_par:self.n_par + 1]
         self.step = 0
+        self._buf = {}
         self.sync16()
 
+    def _views(self, flat):
+        return {k: flat[o:o + n].view(shp) for k, (o, n, shp) in self.off.items()}
+
+    def _buffers(self, n, dev):
+        """Activation and gradient buffers for batches of n rows (reused)."""
+        import torch
+
+        b = self._buf.get(n)
+        if b is None:
+            e = lambda shp, dt: torch.empty(shp, dtype=dt, device=dev)
+            b = {"H1": e((n, HIDDEN), torch.int16), "H2": e((n, HIDDEN), torch.int16), "Y": e((n, OUT), torch.float32),
+                 "dY32": e((n, OUT), torch.float32), "dY16": e((n, OUT), torch.int16),
+                 "dH2_32": e((n, HIDDEN), torch.float32), "dH2_16": e((n, HIDDEN), torch.int16),
+                 "dH1_32": e((n, HIDDEN), torch.float32), "dH1_16": e((n, HIDDEN), torch.int16),
+                 "dX": e((n, WIDTH_IN), torch.float32)}
+            self._buf = {n: b}          # keep one batch size
+        return b
+
     def sync16(self):
-        """Refresh the bf16 weight copies from the fp32 masters."""
-        L = _bind()
-        for k in ("W1", "W2", "W3"):
-            pw.check(L.pw_to_bf16(_p(self.P[k]), self.P[k].numel(), _p(self.W16[k]), _s()))
+        """Refresh the bf16 copy from the fp32 masters."""
+        pw.check(_bind().pw_to_bf16(_p(self.Pf), self.n_par, _p(self.W16f), _s()))
 
     def load(self, host):
         """Set parameters from host float arrays (tests)."""
@@ -137,14 +187,20 @@ class MLP:
             self.P[k].copy_(torch.from_numpy(np.asarray(v, dtype=np.float32)))
         self.sync16()
 
-    def forward(self, X16, keep=False):
+    def forward(self, X16, keep=False, fresh=True):
+        """Logits of a batch (fresh buffers unless fresh=False, which reuses
+        this network's training buffers)."""
         import torch
 
         n = X16.shape[0]
         dev = X16.device
-        H1 = torch.empty((n, HIDDEN), dtype=torch.int16, device=dev)
-        H2 = torch.empty((n, HIDDEN), dtype=torch.int16, device=dev)
-        Y = torch.empty((n, OUT), dtype=torch.float32, device=dev)
+        if fresh:
+            H1 = torch.empty((n, HIDDEN), dtype=torch.int16, device=dev)
+            H2 = torch.empty((n, HIDDEN), dtype=torch.int16, device=dev)
+            Y = torch.empty((n, OUT), dtype=torch.float32, device=dev)
+        else:
+            b = self._buffers(n, dev)
+            H1, H2, Y = b["H1"], b["H2"], b["Y"]
         gemm(X16, WIDTH_IN, 1, self.W16["W1"], HIDDEN, 1, n, HIDDEN, WIDTH_IN, C16=H1, bias=self.P["b1"], relu=True)
         gemm(H1, HIDDEN, 1, self.W16["W2"], HIDDEN, 1, n, HIDDEN, HIDDEN, C16=H2, bias=self.P["b2"], relu=True)
         gemm(H2, HIDDEN, 1, self.W16["W3"], OUT, 1, n, OUT, HIDDEN, C32=Y, bias=self.P["b3"])
@@ -153,46 +209,55 @@ class MLP:
         return Y
 
     def backward(self, X16, H1, H2, Y, labels):
-        """Loss and parameter gradients (into self.G) for one batch."""
-        import torch
-
+        """Loss and parameter gradients (into G, zeroed first) for one batch;
+        returns the loss as a one-element device tensor."""
         L = _bind()
         n = X16.shape[0]
-        dev = X16.device
-        loss = torch.zeros(1, dtype=torch.float32, device=dev)
-        dY32 = torch.empty((n, OUT), dtype=torch.float32, device=dev)
-        dY16 = torch.empty((n, OUT), dtype=torch.int16, device=dev)
-        pw.check(L.pw_mlp_softmax_xent(_p(Y), _p(labels), n, _p(dY32), _p(dY16), _p(loss), _s()))
+        b = self._buffers(n, X16.device)
+        pw.check(L.pw_fill_f32(_p(self.Gf), self.Gf.numel(), 0.0, _s()))
+        pw.check(L.pw_mlp_softmax_xent(_p(Y), _p(labels), n, _p(b["dY32"]), _p(b["dY16"]), _p(self.loss), _s()))
         # layer 3
-        gemm(H2, 1, HIDDEN, dY16, OUT, 1, HIDDEN, OUT, n, C32=self.G["W3"])
-        pw.check(L.pw_mlp_colsum(_p(dY32), n, OUT, _p(self.G["b3"]), _s()))
-        dH2_32 = torch.empty((n, HIDDEN), dtype=torch.float32, device=dev)
-        dH2_16 = torch.empty((n, HIDDEN), dtype=torch.int16, device=dev)
-        gemm(dY16, OUT, 1, self.W16["W3"], 1, OUT, n, HIDDEN, OUT, C32=dH2_32, C16=dH2_16, gate=H2, g_m=HIDDEN)
-        # layer 2
-        gemm(H1, 1, HIDDEN, dH2_16, HIDDEN, 1, HIDDEN, HIDDEN, n, C32=self.G["W2"])
-        pw.check(L.pw_mlp_colsum(_p(dH2_32), n, HIDDEN, _p(self.G["b2"]), _s()))
-        dH1_32 = torch.empty((n, HIDDEN), dtype=torch.float32, device=dev)
-        dH1_16 = torch.empty((n, HIDDEN), dtype=torch.int16, device=dev)
-        gemm(dH2_16, HIDDEN, 1, self.W16["W2"], 1, HIDDEN, n, HIDDEN, HIDDEN, C32=dH1_32, C16=dH1_16, gate=H1,
+        gemm(H2, 1, HIDDEN, b["dY16"], OUT, 1, HIDDEN, OUT, n, C32=self.G["W3"], accumulate=True)
+        pw.check(L.pw_mlp_colsum(_p(b["dY32"]), n, OUT, _p(self.G["b3"]), 1, _s()))
+        gemm(b["dY16"], OUT, 1, self.W16["W3"], 1, OUT, n, HIDDEN, OUT, C32=b["dH2_32"], C16=b["dH2_16"], gate=H2,
              g_m=HIDDEN)
+        # layer 2
+        gemm(H1, 1, HIDDEN, b["dH2_16"], HIDDEN, 1, HIDDEN, HIDDEN, n, C32=self.G["W2"], accumulate=True)
+        pw.check(L.pw_mlp_colsum(_p(b["dH2_32"]), n, HIDDEN, _p(self.G["b2"]), 1, _s()))
+        gemm(b["dH2_16"], HIDDEN, 1, self.W16["W2"], 1, HIDDEN, n, HIDDEN, HIDDEN, C32=b["dH1_32"], C16=b["dH1_16"],
+             gate=H1, g_m=HIDDEN)
         # layer 1
-        gemm(X16, 1, WIDTH_IN, dH1_16, HIDDEN, 1, WIDTH_IN, HIDDEN, n, C32=self.G["W1"])
-        pw.check(L.pw_mlp_colsum(_p(dH1_32), n, HIDDEN, _p(self.G["b1"]), _s()))
-        return loss
+        gemm(X16, 1, WIDTH_IN, b["dH1_16"], HIDDEN, 1, WIDTH_IN, HIDDEN, n, C32=self.G["W1"], accumulate=True)
+        pw.check(L.pw_mlp_colsum(_p(b["dH1_32"]), n, HIDDEN, _p(self.G["b1"]), 1, _s()))
+        return self.loss
 
     def adam_step(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
-        L = _bind()
         self.step += 1
-        for k in self.P:
-            pw.check(L.pw_mlp_adam(_p(self.P[k]), _p(self.G[k]), _p(self.M[k]), _p(self.V[k]), self.P[k].numel(),
-                                   lr, b1, b2, eps, self.step, _p(self.W16.get(k)), _s()))
+        pw.check(_bind().pw_mlp_adam(_p(self.Pf), _p(self.Gf), _p(self.Mf), _p(self.Vf), self.n_par, lr, b1, b2, eps,
+                                     self.step, _p(self.W16f), _s()))
 
     def train_step(self, X16, labels, lr=1e-3):
-        Y, H1, H2 = self.forward(X16, keep=True)
+        Y, H1, H2 = self.forward(X16, keep=True, fresh=False)
         loss = self.backward(X16, H1, H2, Y, labels)
         self.adam_step(lr)
         return loss
+
+    def input_gradient(self, X16, rarity):
+        """d score / d input (n x 64 fp32) of the novelty score: the logit
+        gradient of the score, propagated back through both ReLU layers."""
+        L = _bind()
+        n0 = X16.shape[0]
+        n = (n0 + 63) // 64 * 64          # the products take multiples of 64 rows: repeat rows to pad
+        if n != n0:
+            X16 = X16.repeat(((n + n0 - 1) // n0, 1))[:n].contiguous()
+        Y, H1, H2 = self.forward(X16, keep=True, fresh=False)
+        b = self._buffers(n, X16.device)
+        pw.check(L.pw_mlp_score_grad(_p(Y), _p(rarity), n, _p(b["dY16"]), _s()))
+        gemm(b["dY16"], OUT, 1, self.W16["W3"], 1, OUT, n, HIDDEN, OUT, C16=b["dH2_16"], gate=H2, g_m=HIDDEN)
+        gemm(b["dH2_16"], HIDDEN, 1, self.W16["W2"], 1, HIDDEN, n, HIDDEN, HIDDEN, C16=b["dH1_16"], gate=H1,
+             g_m=HIDDEN)
+        gemm(b["dH1_16"], HIDDEN, 1, self.W16["W1"], 1, HIDDEN, n, WIDTH_IN, HIDDEN, C32=b["dX"])
+        return b["dX"][:n0]
 
 
 # ------------------------------------------------------------- search loop
@@ -248,6 +313,31 @@ def select(scores, cands, threshold, cap):
     return out[:k]
 
 
+def mutate_guided(parents, dX, n, n_bits, flips, seed, temp=0.25, explore=0.1):
+    import torch
+
+    out = torch.empty((n, 2), dtype=torch.int64, device=parents.device)
+    pw.check(_bind().pw_mutate_guided(_p(parents), _p(dX), dX.shape[1], parents.shape[0], n, n_bits, flips, temp,
+                                      explore, seed, _p(out), _s()))
+    return out
+
+
+def rarity_from_labels(lab):
+    """-log of the class frequencies of the six heads over a labelled set
+    (counted on the device; 64 numbers come back)."""
+    import torch
+
+    cnt = torch.zeros(OUT, dtype=torch.int32, device=lab.device)
+    pw.check(_bind().pw_label_counts(_p(lab), lab.shape[0], _p(cnt), _s()))
+    c = cnt.cpu().numpy().view(np.uint32).astype(np.float64) + 0.5
+    r = np.zeros(OUT, dtype=np.float32)
+    st = np.concatenate([[0], np.cumsum(HEADS)])
+    for h in range(6):
+        p = c[st[h]:st[h + 1]] / c[st[h]:st[h + 1]].sum()
+        r[st[h]:st[h + 1]] = -np.log(p)
+    return r
+
+
 def rarest_witnesses(hist, archive, k):
     """Masks of the k schemes seen least often (witness = index into the
     device archive of judged masks)."""
@@ -279,12 +369,18 @@ def run_uniform(tri, d, budget, chunk=1 << 22, seed=1):
     return {"method": "uniform", "evaluations": done, "distinct": len(hist.read()), "gpu_seconds": dt}
 
 
-def run_search(tri, d, budget, use_net=True, train_n=1 << 22, epochs=1, batch=16384, per_round=1 << 21,
-               oversample=2, n_elite=4096, seed=7, log=None):
-    """Mutation search from the rarest schemes seen, ranked by the network
-    (use_net) or at random (the ablation).  Every proposal is judged by the
-    exact kernel (histogram mode, witnesses = indices into a device archive
-    of the judged masks); the training masks count against the budget."""
+def run_search(tri, d, budget, use_net=True, train_n=1 << 24, epochs=1, batch=1 << 16, lr=3e-3, per_round=1 << 22,
+               n_elite=4096, temp=0.25, explore=0.1, seed=7, log=None):
+    """Mutation search from the witnesses of the rarest schemes seen.
+
+    With use_net, the network (trained first on train_n uniform masks
+    labelled by the exact kernel) shapes every mutation: the gradient of its
+    novelty score with respect to the parent's signs gives, per bit, the
+    first-order gain of flipping it, and flips are drawn in proportion to
+    exp(gain / temperature) (pw_mutate_guided).  Without it (the ablation)
+    the flipped bits are uniform.  Every proposal is judged by the exact
+    kernel (histogram mode; witnesses index a device archive of the judged
+    masks); the training masks count against the budget."""
     import torch
 
     nA = (d + 1) * (d + 2) // 2
@@ -305,7 +401,6 @@ def run_search(tri, d, budget, use_net=True, train_n=1 << 22, epochs=1, batch=16
     used = judge(m, 0)
     net = None
     rarity = None
-    score_hi = 1.0
     if use_net:
         codes = tri.batch(m if wide else m[:, 0].contiguous())
         lab = features(codes)
@@ -313,16 +408,9 @@ def run_search(tri, d, budget, use_net=True, train_n=1 << 22, epochs=1, batch=16
         net = MLP(n_in=nA, seed=seed)
         for ep in range(epochs):
             for a in range(0, train_n - batch + 1, batch):
-                net.train_step(X[a:a + batch], lab[a:a + batch], lr=2e-3)
-        labels = lab.cpu().numpy()
-        r = np.zeros(OUT, dtype=np.float32)
-        st = np.concatenate([[0], np.cumsum(HEADS)])
-        for h in range(6):
-            p = np.bincount(labels[:, h], minlength=HEADS[h]).astype(np.float64) + 0.5
-            p /= p.sum()
-            r[st[h]:st[h + 1]] = -np.log(p)
-        rarity = torch.from_numpy(r).cuda()
-        score_hi = float(sum(r[st[h]:st[h + 1]].max() for h in range(6)))
+                net.train_step(X[a:a + batch], lab[a:a + batch], lr=lr)
+        rarity = torch.from_numpy(rarity_from_labels(lab)).cuda()
+        del codes, lab, X
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     rnd = 0
@@ -331,22 +419,20 @@ def run_search(tri, d, budget, use_net=True, train_n=1 << 22, epochs=1, batch=16
         k = min(per_round, budget - used)
         parents, distinct = rarest_witnesses(hist, archive, n_elite)
         curve.append((used, distinct))
-        cand = mutate(parents, k * (oversample if use_net else 1), nA, 1 + rnd % 3, seed * 1000003 + rnd)
+        flips = 1 + rnd % 3
         if use_net:
-            Y = net.forward(encode(cand, cand.shape[0], nA))
-            sc = score(Y, rarity)
-            sel = select(sc, cand, top_threshold(sc, k, 0.0, score_hi), k)
-            if sel.shape[0] == 0:
-                sel = cand[:k]
+            np_ = parents.shape[0]
+            dX = net.input_gradient(encode(parents, np_, nA), rarity)
+            cand = mutate_guided(parents, dX, k, nA, flips, seed * 1000003 + rnd, temp, explore)
         else:
-            sel = cand[:k]          # random ranking: the mutants are already in random order
-        used = judge(sel, used)
+            cand = mutate(parents, k, nA, flips, seed * 1000003 + rnd)
+        used = judge(cand, used)
         if log and rnd % 16 == 0:
             log(f"round {rnd}: {used} evaluations, {distinct} schemes")
     final = len(hist.read())
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     curve.append((used, final))
-    return {"method": "learned" if use_net else "ablation (random ranking)", "evaluations": used,
+    return {"method": "learned" if use_net else "ablation (uniform flips)", "evaluations": used,
             "distinct": final, "gpu_seconds": dt, "train_seconds": train_s, "rounds": rnd,
             "curve": curve[:: max(1, len(curve) // 32)] + ([curve[-1]] if len(curve) > 32 else [])}
