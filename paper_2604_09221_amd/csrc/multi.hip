@@ -13,9 +13,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <cstdint>
 #include <cstring>
-#include <mutex>
 #include <vector>
 
 #include "patchwork.h"
@@ -205,11 +205,12 @@ extern "C" pw_status patchwork_scheme_batch_multi(const pw_tri_t* tris, int32_t 
   const int threads = 64 * c.waves_per_block;
   const size_t lds = (size_t)max_words * 4 * 64 * c.waves_per_block;
   if (lds > 160 * 1024) return set_err(PW_ERR_ARG, "block needs %zu bytes of LDS", lds);
-  static std::once_flag once;
-  std::call_once(once, [] {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_multi), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              160 * 1024);
-  });
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_multi),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (attr != hipSuccess) {
+    (void)hipGetLastError();
+    return set_err(PW_ERR_HIP, "hipFuncSetAttribute: %s (code %d)", hipGetErrorString(attr), (int)attr);
+  }
   int per_cu = (int)((160 * 1024) / lds);
   if (c.blocks_per_cu > 0) per_cu = std::min(per_cu, c.blocks_per_cu);
   per_cu = std::max(1, std::min(per_cu, 32 / c.waves_per_block));

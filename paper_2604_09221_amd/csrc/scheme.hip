@@ -9,7 +9,6 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
-#include <mutex>
 #include <new>
 #include <vector>
 
@@ -90,17 +89,25 @@ int blocks_for(int64_t units_per_block, int64_t n) {
   return (int)std::max<int64_t>(1, std::min(need, (int64_t)cu_count() * per_cu));
 }
 
+// Let a kernel use up to 160 KiB of LDS in total: its dynamic part may then
+// be 160 KiB minus the static parent table (set once per kernel).
+template <int D>
+hipError_t allow_lds(const void* kernel) {
+  using C = Cfg<D>;
+  const hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           160 * 1024 - C::WAVES * C::PAR_ROWS * 64);
+  if (e != hipSuccess) (void)hipGetLastError();
+  return e;
+}
+
 template <int D>
 pw_status launch_codes(const pw_tri* t, const void* masks, int64_t n, uint64_t* codes, hipStream_t s) {
   using C = Cfg<D>;
   const int threads = 64 * C::WAVES;
   const size_t lds = (size_t)C::DYN_WORDS * 4 * 64 * C::WAVES;  // + the static parent table
-  static std::once_flag once;
-  std::call_once(once, [] {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_codes<D>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  });
-  if (t->jit_codes) {
+  static const hipError_t attr = allow_lds<D>(reinterpret_cast<const void*>(&k_codes<D>));
+  if (attr != hipSuccess) return set_err(PW_ERR_HIP, "hipFuncSetAttribute: %s (code %d)", hipGetErrorString(attr), (int)attr);
+  if (t->jit_codes && lds <= 64 * 1024) {  // module kernels keep the default 64 KiB limit
     const void* m_ = masks;
     uint64_t* c_ = codes;
     uint32_t* e_ = t->d_err;
@@ -121,12 +128,9 @@ pw_status launch_hist(const pw_tri* t, const void* masks, int64_t n, uint64_t ba
   using C = Cfg<D>;
   const int threads = 64 * C::WAVES;
   const size_t lds = (size_t)C::DYN_WORDS * 4 * 64 * C::WAVES;  // + the static parent table
-  static std::once_flag once;
-  std::call_once(once, [] {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hist<D>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  });
-  if (t->jit_hist) {
+  static const hipError_t attr = allow_lds<D>(reinterpret_cast<const void*>(&k_hist<D>));
+  if (attr != hipSuccess) return set_err(PW_ERR_HIP, "hipFuncSetAttribute: %s (code %d)", hipGetErrorString(attr), (int)attr);
+  if (t->jit_hist && lds <= 64 * 1024) {
     const void* m_ = masks;
     const HistDev* hd = h->d_dev;
     uint32_t* e_ = t->d_err;
@@ -147,13 +151,10 @@ pw_status launch_enum(const pw_tri* t, uint64_t first, uint64_t count, const Run
   using C = Cfg<D>;
   const int threads = 64 * C::WAVES;
   const size_t lds = (size_t)C::DYN_WORDS * 4 * 64 * C::WAVES;  // + the static parent table
-  static std::once_flag once;
-  std::call_once(once, [] {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_enum<D>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  });
+  static const hipError_t attr = allow_lds<D>(reinterpret_cast<const void*>(&k_enum<D>));
+  if (attr != hipSuccess) return set_err(PW_ERR_HIP, "hipFuncSetAttribute: %s (code %d)", hipGetErrorString(attr), (int)attr);
   const int64_t n = count > (uint64_t)INT64_MAX ? INT64_MAX : (int64_t)count;
-  if (t->jit_enum) {
+  if (t->jit_enum && lds <= 64 * 1024) {
     Runs r_ = runs;
     const HistDev* hd = h->d_dev;
     uint32_t* e_ = t->d_err;
