@@ -40,6 +40,38 @@ def algorithmic_ops_per_mask(d: int) -> int:
 # chip figures for the ALU roofline: 256 CUs x 64 lanes x 2.4 GHz
 PEAK_INT_OPS = 256 * 64 * 2.4e9
 
+# sources of the specialised d=7 kernel; HBM traffic measured with rocprofv3
+# counters is reported only while these are unchanged
+KERNEL_SOURCES = ("paper_2604_09221_amd/csrc/pw_device.h", "paper_2604_09221_amd/csrc/pw_internal.h",
+                  "paper_2604_09221_amd/csrc/jit.cpp", "paper_2604_09221_amd/csrc/scheme.hip",
+                  "paper_2604_09221_amd/csrc/tri.cpp")
+TRAFFIC_PROFILE = "profiles/pw_jit_enum_d7_sweep_counters.md"
+
+
+def kernel_sources_sha256():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic():
+    """HBM bytes per launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE scaled by a 1 GiB copy), or None if the kernel sources changed
+    since it was taken."""
+    try:
+        text = open(os.path.join(ROOT, TRAFFIC_PROFILE)).read()
+    except OSError:
+        return None
+    vals = dict(line.split(": ", 1) for line in text.splitlines() if line.startswith(("traffic_bytes_per_launch: ",
+                                                                                      "kernel_sources_sha256: ")))
+    if vals.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
 
 def cpu_baseline(d, E, n, codes_gpu_fn):
     import numpy as np
@@ -292,7 +324,7 @@ def main():
             "peak": PEAK_INT_OPS / 1e12,
             "unit": "TOP/s",
             "frac": achieved * 1e12 / PEAK_INT_OPS,
-            "traffic": None,
+            "traffic": None if args.generic or args.chunk_log2 != 32 else profiled_traffic(),
             "kernel": kernel,
             "ops_per_mask": algorithmic_ops_per_mask(d),
             "avg_launch_ms": avg_launch_s * 1e3,
