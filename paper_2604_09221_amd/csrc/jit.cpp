@@ -41,19 +41,14 @@ std::string jit_source(const HostProgram& P) {
     std::string x = "E::bit(m, " + std::to_string(p) + ")";
     return g ? "(" + x + " ^ 1u)" : x;
   };
-  o << "    // phase 1: components of same-sign vertices; r<u> = a root u had,\n"
-       "    // e<k> = first hops of v's walks, read before v's unions\n";
+  o << "    // phase 1: components of same-sign vertices; r<u> = a root u had\n";
   for (int v = 0; v < nV; ++v) {
     const uint32_t rec = P.words[v];
     const int n = (rec >> 8) & 0xFF, off = rec >> 16;
     o << "    uint32_t r" << v << " = " << v << "u; { const uint32_t sv = " << sign(v) << ";";
     for (int k = 0; k < n; ++k) {
       const int u = (int)P.words[nV + off + k];
-      o << " const uint32_t e" << k << " = E::ent(L, (int)r" << u << ");";
-    }
-    for (int k = 0; k < n; ++k) {
-      const int u = (int)P.words[nV + off + k];
-      o << " E::edge_r(L, sv, " << sign(u) << ", " << v << ", r" << v << ", r" << u << ", e" << k << ");";
+      o << " E::edge_r(L, sv, " << sign(u) << ", " << v << ", r" << v << ", r" << u << ");";
     }
     o << " E::close(L, " << v << ", r" << v << "); }\n";
   }

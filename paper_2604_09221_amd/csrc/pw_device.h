@@ -3,35 +3,36 @@
 // mask (Alg. 1 of "Fast Isotopy Computation for T-Curves", Sec. 2), the
 // in-kernel mask generator and the two-level code histogram.
 //
-// LDS layout (per wave; the Cfg and Lane comments give the details): vertex
-// entries (the union-find parent index, u8 or u16) at byte v * ESTRIDE +
-// EB * lane, per-lane words at byte k * 256 + 4 * lane, and the parent
-// table of the region tree in byte rows (x * 64 + lane).  Signs are never
-// stored: the sign of a vertex is a fixed bit of the mask.
+// LDS layout: each wave owns LANE_WORDS * 64 dwords.  Word k of lane l sits
+// at dword k * 64 + l (every lane in its own bank whatever the index) and
+// vertex entry v (u16) at byte v * 128 + 2 l (its own bank for a uniform v,
+// at most two lanes per bank for divergent parent pointers).
 //
 // Per mask (thread) the phases are:
-//   1 components  (Alg. 1: connected components of same-sign vertices):
-//     vertices in program order; each earlier neighbour with the same sign
-//     is unioned.  Links always go from the larger root to the smaller one,
-//     so every parent index is smaller than its child's.
-//   2 regions (Alg. 1: antipodal boundary pairs identified): union along
-//     the 2d pairs.  For even d the union carries parity 1 (each
-//     identification reverses orientation, proof of Thm. 2) and a
-//     same-parity closure marks an odd cycle.
+//   1 components  (Alg. 1 "compute connected components of same-sign
+//     vertices"): vertices in program order; each earlier neighbour with
+//     the same sign is unioned.  Entry of v (u16): parent << 7 (the byte
+//     offset of the parent's entry), odd-cycle flag (roots), parity to the
+//     parent, sign.
+//     Links always go from the larger root to the smaller one, so every
+//     parent index is smaller than its child's.
+//   2 regions (Alg. 1 "coarsen into regions by identifying antipodal
+//     boundary pairs"): union along the 2d pairs.  For even d the union
+//     carries parity 1 (each identification reverses orientation, proof of
+//     Thm. 2) and a same-parity closure marks an odd cycle.
 //   3 region ids and the region tree: vertices in order again; a root gets
 //     the next region id, any other vertex copies the id of its parent
 //     (already relabelled because parents are smaller).  The region tree is
 //     read off a fixed spanning tree of T<> (each vertex's first earlier
 //     neighbour): the first vertex of a region hangs below the region of its
-//     tree parent (Alg. 1's region adjacency graph from crossed edges,
-//     restricted to spanning-tree edges, which cross every curve
-//     component).  The root is the region of a crossed tree edge inside one
-//     region for odd d (the pseudo-line), the region with an odd cycle for
-//     even d.
-//   4 re-root the tree at the root region (Alg. 1 root rule) and build the
-//     canonical code bottom-up (Alg. 1 last step, AHU encoding): children
-//     codes sorted descending by their left-aligned bit strings; leaves
-//     ('10') sort last.
+//     tree parent (Alg. 1 "build region adjacency graph from crossed
+//     edges", restricted to spanning-tree edges, which cross every curve
+//     component).  For odd d a crossed tree edge inside one region marks
+//     the root (the pseudo-line's region).
+//   4 re-root the tree at the root region (Alg. 1 root rule), breadth-first
+//     order, canonical code (Alg. 1 last step, AHU encoding): children codes
+//     sorted descending by their left-aligned bit strings; leaves ('10')
+//     sort last.
 #pragma once
 #if defined(__HIPCC_RTC__)
 // compiled at run time for one triangulation: no standard headers there
@@ -271,29 +272,24 @@ struct Eval {
 
   // Phase 1 step of the specialised kernels: as edge(), but the walk starts
   // from ru, a register holding a root u had at some earlier time (u's root
-  // when u was closed, refreshed by each later walk from u), and its first
-  // hop eu = entry of ru was read before any of v's unions.  That read may
-  // be stale only for a vertex that was a root and was linked while v was
-  // being processed -- and every such link points into v's current
-  // component, so treating it as a root and linking it (again) below the
-  // smaller root only shortens its path.  Entries of non-roots do not
-  // change during phase 1 apart from these links.  ru is refreshed with a
-  // root of u's component; nothing is written back to u's entry.
+  // when u was closed, refreshed by each later walk from u), so the first
+  // LDS read does not wait for another one.  ru is refreshed with u's
+  // current root; nothing is written back to u's entry.
   __device__ static __forceinline__ void edge_r(const Lane& L, uint32_t sv, uint32_t su, int v, uint32_t& rv,
-                                                uint32_t& ru, uint32_t eu) {
+                                                uint32_t& ru) {
     uint32_t r = ru;
-    uint32_t er = eu;
+    uint32_t er = ent(L, (int)r);
     while (er != r) {
       r = er;
       er = ent(L, (int)r);
     }
+    ru = r;
     const bool same = su == sv;
     const uint32_t lo = r < rv ? r : rv, hi = r < rv ? rv : r;
     int w = same ? (int)hi : v;
     PW_OPAQUE(w);
     ent(L, w) = (Ent)lo;
     rv = same ? lo : rv;
-    ru = same ? lo : r;
   }
 
   // Phase 2 step: one antipodal pair (a, b).
