@@ -229,11 +229,14 @@ pw_status patchwork_scheme_batch_multi(const pw_tri_t *tris, int32_t n_tris, con
  * (k, n) of B is B[k * b_k + n * b_n] (so one call serves X W, dY W^T and
  * X^T dY); gate (M x N, row stride g_m) and bias (N floats) may be NULL.
  * Output row stride c_m; C32 (fp32) and/or C16 (bf16), at least one;
- * accumulate != 0 adds into C32.  M and N must be multiples of 64, K of 32.
+ * accumulate != 0 adds into C32.  colsum (N floats, or NULL) receives
+ * colsum[n] += sum over m of the final C[m][n] (after the epilogue, before
+ * bf16 rounding; FP32 atomics, in no fixed order) -- the bias gradient of a
+ * backward product.  M and N must be multiples of 64, K of 32.
  */
 pw_status pw_mlp_gemm(const uint16_t *A, int64_t a_m, int64_t a_k, const uint16_t *B, int64_t b_k, int64_t b_n,
                       int32_t M, int32_t N, int32_t K, const float *bias, const uint16_t *gate, int64_t g_m,
-                      int32_t relu, float *C32, uint16_t *C16, int64_t c_m, int32_t accumulate,
+                      int32_t relu, float *C32, uint16_t *C16, int64_t c_m, int32_t accumulate, float *colsum,
                       hipStream_t stream);
 
 /*
@@ -314,17 +317,25 @@ pw_status pw_mutate(const uint64_t *parents, int64_t n_parents, int64_t n, int32
                     uint64_t seed, uint64_t *out, hipStream_t stream);
 
 /*
- * Guided mutants: out[k] = parents[p], p = k mod n_parents, with `flips` bit
- * positions in [1, n_bits) toggled.  Each position j is drawn with
- * probability proportional to exp(gain_j / (temp * max |gain|)), gain_j =
- * -2 x_j dX[p * ldx + j] (x_j = +1 for '+', -1 for '-'; dX = gradient of
- * the network's novelty score with respect to its input), except that a
- * fraction `explore` of the draws is uniform.  Random numbers: the
- * SplitMix64 finaliser applied to a key of (seed, k, flip index).
+ * Flip distribution of each parent for guided mutation: cdf[p * 64 + j] =
+ * P(flipped bit <= j) over bits 1 .. n_bits-1, where bit j has probability
+ * (1 - explore) * softmax_j(gain / (temp * max |gain|)) + explore / (n_bits
+ * - 1) and gain_j = -2 x_j dX[p * ldx + j] (x_j = +1 for '+', -1 for '-';
+ * dX = gradient of the network's novelty score with respect to its input):
+ * the first-order change of the score when bit j flips.  cdf: n_parents x
+ * 64 floats; cdf[p*64] = 0, entries from n_bits - 1 on are 1.  n_bits <= 64.
  */
-pw_status pw_mutate_guided(const uint64_t *parents, const float *dX, int64_t ldx, int64_t n_parents, int64_t n,
-                           int32_t n_bits, int32_t flips, float temp, float explore, uint64_t seed, uint64_t *out,
-                           hipStream_t stream);
+pw_status pw_flip_cdf(const uint64_t *parents, const float *dX, int64_t ldx, int64_t n_parents, int32_t n_bits,
+                      float temp, float explore, float *cdf, hipStream_t stream);
+
+/*
+ * Guided mutants: out[k] = parents[p], p = k mod n_parents, with `flips` bits
+ * toggled, each drawn from the parent's distribution in cdf (pw_flip_cdf)
+ * by inverting a 24-bit uniform taken from the SplitMix64 finaliser applied
+ * to a key of (seed, k, flip index).  Bit 0 is never drawn.
+ */
+pw_status pw_mutate_cdf(const uint64_t *parents, const float *cdf, int64_t n_parents, int64_t n, int32_t flips,
+                        uint64_t seed, uint64_t *out, hipStream_t stream);
 
 /*
  * Uniform masks: word w of mask k is the SplitMix64 output number

@@ -69,6 +69,7 @@ struct GemmArgs {
   int64_t c_m;
   int accumulate;  // C32 += result
   int atomic;      // partial tiles of a split K: C32 += result atomically
+  float* colsum;   // N or null: colsum[n] += sum over m of the final C[m][n]
 };
 
 // One ROWS x TBK slab of an operand X (element (r, k) at X[r s_row + k s_k])
@@ -166,6 +167,9 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
       for (int b = 0; b < FN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
     __syncthreads();
   }
+  float csum[FN];
+#pragma unroll
+  for (int b = 0; b < FN; ++b) csum[b] = 0.f;
 #pragma unroll
   for (int a = 0; a < FM; ++a)
 #pragma unroll
@@ -182,12 +186,22 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
         if (g.bias) v += g.bias[n];
         if (g.relu) v = v > 0.f ? v : 0.f;
         if (g.gate && !(bf16_to_f32(g.gate[(int64_t)m * g.g_m + n]) > 0.f)) v = 0.f;
+        csum[b] += v;
         if (g.C32) {
           float* o = &g.C32[(int64_t)m * g.c_m + n];
           *o = g.accumulate ? *o + v : v;
         }
         if (g.C16) g.C16[(int64_t)m * g.c_m + n] = f32_to_bf16(v);
       }
+  if (g.colsum) {  // lanes l, l^16, l^32, l^48 hold the same column
+#pragma unroll
+    for (int b = 0; b < FN; ++b) {
+      float v = csum[b];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      if (lane < 16) unsafeAtomicAdd(&g.colsum[n0 + wn + 16 * b + lane], v);
+    }
+  }
 }
 
 // ------------------------------------------------------------- elementwise
@@ -397,22 +411,20 @@ __global__ void k_mutate(const uint64_t* __restrict__ parents, int64_t n_parents
   out[2 * k + 1] = hi;
 }
 
-// Guided mutants: candidate k = parent p = k % n_parents with `flips` bits
-// toggled, each drawn from [1, n_bits) with probability proportional to
-// exp(gain_j / (temp * max_j |gain_j|)) (a fraction `explore` of the draws
-// is uniform instead), where gain_j = -2 x_j dX[p][j] is the first-order
-// change of the network's novelty score when bit j of the parent flips
-// (x_j = +1 for '+', -1 for '-'; dX = d score / d input).
-__global__ void k_mutate_guided(const uint64_t* __restrict__ parents, const float* __restrict__ dX, int64_t ldx,
-                                int64_t n_parents, int64_t n, int n_bits, int flips, float temp, float explore,
-                                uint64_t seed, uint64_t* __restrict__ out) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  const int64_t p = k % n_parents;
-  const uint64_t lo0 = parents[2 * p], hi0 = parents[2 * p + 1];
+// Flip distribution of each parent: cdf[p][j] = P(bit <= j) over bits
+// 1 .. n_bits-1 with P(j) = (1 - explore) softmax_j(gain / (temp max|gain|))
+// + explore / (n_bits - 1), where gain_j = -2 x_j dX[p][j] is the
+// first-order change of the network's novelty score when bit j of the parent
+// flips (x_j = +1 for '+', -1 for '-'; dX = d score / d input).  cdf[p][0] =
+// 0; entries past n_bits - 1 are 1.
+__global__ void k_flip_cdf(const uint64_t* __restrict__ parents, const float* __restrict__ dX, int64_t ldx,
+                           int64_t n_parents, int n_bits, float temp, float explore, float* __restrict__ cdf) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_parents) return;
+  const uint64_t lo = parents[2 * p], hi = parents[2 * p + 1];
   const float* g = dX + p * ldx;
   auto gain = [&](int j) {
-    const uint64_t b = j < 64 ? (lo0 >> j) & 1 : (hi0 >> (j - 64)) & 1;
+    const uint64_t b = j < 64 ? (lo >> j) & 1 : (hi >> (j - 64)) & 1;
     return (b ? 2.f : -2.f) * g[j];
   };
   float gmax = -INFINITY, amax = 0.f;
@@ -424,25 +436,34 @@ __global__ void k_mutate_guided(const uint64_t* __restrict__ parents, const floa
   const float inv = 1.f / (temp * amax + 1e-30f);
   float z = 0.f;
   for (int j = 1; j < n_bits; ++j) z += expf((gain(j) - gmax) * inv);
-  uint64_t lo = lo0, hi = hi0;
+  float* c = cdf + p * 64;
+  const float u = explore / (float)(n_bits - 1);
+  float acc = 0.f;
+  c[0] = 0.f;
+  for (int j = 1; j < 64; ++j) {
+    if (j < n_bits) acc += (1.f - explore) * expf((gain(j) - gmax) * inv) / z + u;
+    c[j] = j < n_bits - 1 ? acc : 1.f;
+  }
+}
+
+// Guided mutants: candidate k = parent p = k % n_parents with `flips` bits
+// toggled, bit j drawn with probability cdf[p][j] - cdf[p][j-1] (inverse
+// transform of a 24-bit uniform by binary search over the 64 entries).
+__global__ void k_mutate_cdf(const uint64_t* __restrict__ parents, const float* __restrict__ cdf,
+                             int64_t n_parents, int64_t n, int flips, uint64_t seed, uint64_t* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int64_t p = k % n_parents;
+  uint64_t lo = parents[2 * p], hi = parents[2 * p + 1];
+  const float* c = cdf + p * 64;
   for (int f = 0; f < flips; ++f) {
     const uint64_t r = mix64(seed ^ mix64((uint64_t)k * 0x100000001B3ull + (uint64_t)f));
-    const float u = (float)(r >> 40) * (1.f / 16777216.f);          // 24 bits
-    int b;
-    if ((float)((r >> 8) & 0xFFFF) * (1.f / 65536.f) < explore) {
-      b = 1 + (int)((r & 0xFF) % (uint64_t)(n_bits - 1));
-    } else {
-      const float target = u * z;
-      float acc = 0.f;
-      b = n_bits - 1;
-      for (int j = 1; j < n_bits; ++j) {
-        acc += expf((gain(j) - gmax) * inv);
-        if (acc > target) {
-          b = j;
-          break;
-        }
-      }
-    }
+    const float u = (float)(r >> 40) * (1.f / 16777216.f);
+    int j = 0;  // largest j with c[j] <= u, then bit j + 1
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1)
+      if (c[j + step] <= u) j += step;
+    const int b = j + 1 < 64 ? j + 1 : 63;
     if (b < 64)
       lo ^= 1ull << b;
     else
@@ -506,12 +527,13 @@ extern "C" {
 
 pw_status pw_mlp_gemm(const uint16_t* A, int64_t a_m, int64_t a_k, const uint16_t* B, int64_t b_k, int64_t b_n,
                       int32_t M, int32_t N, int32_t K, const float* bias, const uint16_t* gate, int64_t g_m,
-                      int32_t relu, float* C32, uint16_t* C16, int64_t c_m, int32_t accumulate, hipStream_t s) {
+                      int32_t relu, float* C32, uint16_t* C16, int64_t c_m, int32_t accumulate, float* colsum,
+                      hipStream_t s) {
   if (!A || !B || (!C32 && !C16)) return set_err(PW_ERR_ARG, "null operand");
   if (M <= 0 || N <= 0 || K <= 0 || M % 64 || N % 64 || K % TBK)
     return set_err(PW_ERR_ARG, "gemm sizes must be positive multiples of 64 (M, N) and 32 (K): %d %d %d", M, N, K);
   if (accumulate && !C32) return set_err(PW_ERR_ARG, "accumulate needs the fp32 output");
-  GemmArgs g{A, a_m, a_k, B, b_k, b_n, M, N, K, K, bias, gate, g_m, relu, C32, C16, c_m, accumulate, 0};
+  GemmArgs g{A, a_m, a_k, B, b_k, b_n, M, N, K, K, bias, gate, g_m, relu, C32, C16, c_m, accumulate, 0, colsum};
   // 16-byte staging needs 8-element alignment of the base and the strides
   auto al = [](const void* p, int64_t s1) { return ((uintptr_t)p % 16 == 0) && (s1 % 8 == 0); };
   const int am = (a_k == 1 && al(A, a_m)) ? 1 : ((a_m == 1 && al(A, a_k)) ? 2 : 0);
@@ -522,7 +544,7 @@ pw_status pw_mlp_gemm(const uint16_t* A, int64_t a_m, int64_t a_k, const uint16_
   // no element-wise epilogue (partial sums are added atomically)
   int splits = 1;
   const int ksteps = K / TBK;
-  if (C32 && !C16 && !bias && !gate && !relu && tiles < 512 && ksteps >= 8) {
+  if (C32 && !C16 && !bias && !gate && !relu && !colsum && tiles < 512 && ksteps >= 8) {
     splits = std::min(ksteps / 4, (1024 + tiles - 1) / tiles);
     const int per = (ksteps + splits - 1) / splits;
     g.k_split = per * TBK;
@@ -633,15 +655,25 @@ pw_status pw_mlp_score_grad(const float* Y, const float* rarity, int64_t n, uint
   return PW_OK;
 }
 
-pw_status pw_mutate_guided(const uint64_t* parents, const float* dX, int64_t ldx, int64_t n_parents, int64_t n,
-                           int32_t n_bits, int32_t flips, float temp, float explore, uint64_t seed, uint64_t* out,
-                           hipStream_t s) {
-  if (n < 0 || n_parents <= 0 || n_bits < 2 || n_bits > 128 || ldx < n_bits || flips < 0 || !(temp > 0.f) ||
-      !parents || !dX || !out)
+pw_status pw_flip_cdf(const uint64_t* parents, const float* dX, int64_t ldx, int64_t n_parents, int32_t n_bits,
+                      float temp, float explore, float* cdf, hipStream_t s) {
+  if (n_parents < 0 || n_bits < 2 || n_bits > 64 || ldx < n_bits || !(temp > 0.f) || !(explore >= 0.f) ||
+      !(explore <= 1.f) || !parents || !dX || !cdf)
+    return set_err(PW_ERR_ARG, "bad flip-distribution arguments");
+  if (n_parents == 0) return PW_OK;
+  hipLaunchKernelGGL(k_flip_cdf, dim3(grid1d(n_parents, 64)), dim3(64), 0, s, parents, dX, ldx, n_parents, n_bits,
+                     temp, explore, cdf);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
+pw_status pw_mutate_cdf(const uint64_t* parents, const float* cdf, int64_t n_parents, int64_t n, int32_t flips,
+                        uint64_t seed, uint64_t* out, hipStream_t s) {
+  if (n < 0 || n_parents <= 0 || flips < 0 || !parents || !cdf || !out)
     return set_err(PW_ERR_ARG, "bad guided-mutation arguments");
   if (n == 0) return PW_OK;
-  hipLaunchKernelGGL(k_mutate_guided, dim3(grid1d(n, 256)), dim3(256), 0, s, parents, dX, ldx, n_parents, n, n_bits,
-                     flips, temp, explore, seed, out);
+  hipLaunchKernelGGL(k_mutate_cdf, dim3(grid1d(n, 256)), dim3(256), 0, s, parents, cdf, n_parents, n, flips, seed,
+                     out);
   PW_HIP(hipGetLastError());
   return PW_OK;
 }

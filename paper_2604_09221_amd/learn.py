@@ -34,7 +34,7 @@ def _bind():
         return pw.lib()
     L = pw.lib()
     vp, i32, i64, u64, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_float
-    L.pw_mlp_gemm.argtypes = [vp, i64, i64, vp, i64, i64, i32, i32, i32, vp, vp, i64, i32, vp, vp, i64, i32, vp]
+    L.pw_mlp_gemm.argtypes = [vp, i64, i64, vp, i64, i64, i32, i32, i32, vp, vp, i64, i32, vp, vp, i64, i32, vp, vp]
     L.pw_mlp_encode.argtypes = [vp, i64, i32, i32, vp, vp]
     L.pw_features.argtypes = [vp, i64, vp, vp]
     L.pw_mlp_softmax_xent.argtypes = [vp, vp, i64, vp, vp, vp, vp]
@@ -42,7 +42,8 @@ def _bind():
     L.pw_fill_f32.argtypes = [vp, i64, f32, vp]
     L.pw_label_counts.argtypes = [vp, i64, vp, vp]
     L.pw_mlp_score_grad.argtypes = [vp, vp, i64, vp, vp]
-    L.pw_mutate_guided.argtypes = [vp, vp, i64, i64, i64, i32, i32, f32, f32, u64, vp, vp]
+    L.pw_flip_cdf.argtypes = [vp, vp, i64, i64, i32, f32, f32, vp, vp]
+    L.pw_mutate_cdf.argtypes = [vp, vp, i64, i64, i32, u64, vp, vp]
     L.pw_mlp_adam.argtypes = [vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp, vp]
     L.pw_mlp_score.argtypes = [vp, vp, i64, vp, vp]
     L.pw_to_bf16.argtypes = [vp, i64, vp, vp]
@@ -52,7 +53,7 @@ def _bind():
     L.pw_bin_floats.argtypes = [vp, i64, f32, f32, i32, vp, vp]
     for n in ("pw_mlp_gemm", "pw_mlp_encode", "pw_features", "pw_mlp_softmax_xent", "pw_mlp_colsum",
               "pw_mlp_adam", "pw_mlp_score", "pw_to_bf16", "pw_mutate", "pw_select",
-              "pw_random_masks", "pw_bin_floats", "pw_fill_f32", "pw_mlp_score_grad", "pw_mutate_guided",
+              "pw_random_masks", "pw_bin_floats", "pw_fill_f32", "pw_mlp_score_grad", "pw_flip_cdf", "pw_mutate_cdf",
               "pw_label_counts"):
         getattr(L, n).restype = i32
     _bound = True
@@ -70,11 +71,12 @@ def _s():
 
 
 def gemm(A, a_m, a_k, B, b_k, b_n, M, N, K, C32=None, C16=None, c_m=None, bias=None, gate=None, g_m=0,
-         relu=False, accumulate=False):
-    """C = A B with element strides (A[m,k] = A[m*a_m + k*a_k], ...)."""
+         relu=False, accumulate=False, colsum=None):
+    """C = A B with element strides (A[m,k] = A[m*a_m + k*a_k], ...);
+    colsum (optional) accumulates the column sums of the result."""
     L = _bind()
     pw.check(L.pw_mlp_gemm(_p(A), a_m, a_k, _p(B), b_k, b_n, M, N, K, _p(bias), _p(gate), g_m, int(relu),
-                           _p(C32), _p(C16), N if c_m is None else c_m, int(accumulate), _s()))
+                           _p(C32), _p(C16), N if c_m is None else c_m, int(accumulate), _p(colsum), _s()))
 
 
 def encode(masks128, n, n_bits, width=WIDTH_IN):
@@ -121,10 +123,11 @@ def _offsets():
 class MLP:
     """Device parameters in flat buffers: fp32 masters P, gradients G (plus
     one slot for the loss), Adam moments M, V and the bf16 copy W16, each
-    with per-tensor views.  One training step is 14 kernel launches: zero G,
-    three forward products, the loss, three weight-gradient products, three
-    bias-gradient column sums, two input-gradient products and one Adam
-    update over all parameters."""
+    with per-tensor views.  One training step is 12 kernel launches: zero G,
+    three forward products, the loss, three weight-gradient products, one
+    bias-gradient column sum (the hidden layers' bias gradients are summed
+    in the epilogues of the input-gradient products), two input-gradient
+    products and one Adam update over all parameters."""
 
     def __init__(self, n_in=45, seed=0, device="cuda"):
         import torch
@@ -169,8 +172,7 @@ class MLP:
             e = lambda shp, dt: torch.empty(shp, dtype=dt, device=dev)
             b = {"H1": e((n, HIDDEN), torch.int16), "H2": e((n, HIDDEN), torch.int16), "Y": e((n, OUT), torch.float32),
                  "dY32": e((n, OUT), torch.float32), "dY16": e((n, OUT), torch.int16),
-                 "dH2_32": e((n, HIDDEN), torch.float32), "dH2_16": e((n, HIDDEN), torch.int16),
-                 "dH1_32": e((n, HIDDEN), torch.float32), "dH1_16": e((n, HIDDEN), torch.int16),
+                 "dH2_16": e((n, HIDDEN), torch.int16), "dH1_16": e((n, HIDDEN), torch.int16),
                  "dX": e((n, WIDTH_IN), torch.float32)}
             self._buf = {n: b}          # keep one batch size
         return b
@@ -219,16 +221,14 @@ class MLP:
         # layer 3
         gemm(H2, 1, HIDDEN, b["dY16"], OUT, 1, HIDDEN, OUT, n, C32=self.G["W3"], accumulate=True)
         pw.check(L.pw_mlp_colsum(_p(b["dY32"]), n, OUT, _p(self.G["b3"]), 1, _s()))
-        gemm(b["dY16"], OUT, 1, self.W16["W3"], 1, OUT, n, HIDDEN, OUT, C32=b["dH2_32"], C16=b["dH2_16"], gate=H2,
-             g_m=HIDDEN)
+        gemm(b["dY16"], OUT, 1, self.W16["W3"], 1, OUT, n, HIDDEN, OUT, C16=b["dH2_16"], gate=H2, g_m=HIDDEN,
+             colsum=self.G["b2"])
         # layer 2
         gemm(H1, 1, HIDDEN, b["dH2_16"], HIDDEN, 1, HIDDEN, HIDDEN, n, C32=self.G["W2"], accumulate=True)
-        pw.check(L.pw_mlp_colsum(_p(b["dH2_32"]), n, HIDDEN, _p(self.G["b2"]), 1, _s()))
-        gemm(b["dH2_16"], HIDDEN, 1, self.W16["W2"], 1, HIDDEN, n, HIDDEN, HIDDEN, C32=b["dH1_32"], C16=b["dH1_16"],
-             gate=H1, g_m=HIDDEN)
+        gemm(b["dH2_16"], HIDDEN, 1, self.W16["W2"], 1, HIDDEN, n, HIDDEN, HIDDEN, C16=b["dH1_16"], gate=H1,
+             g_m=HIDDEN, colsum=self.G["b1"])
         # layer 1
         gemm(X16, 1, WIDTH_IN, b["dH1_16"], HIDDEN, 1, WIDTH_IN, HIDDEN, n, C32=self.G["W1"], accumulate=True)
-        pw.check(L.pw_mlp_colsum(_p(b["dH1_32"]), n, HIDDEN, _p(self.G["b1"]), 1, _s()))
         return self.loss
 
     def adam_step(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
@@ -313,12 +313,23 @@ def select(scores, cands, threshold, cap):
     return out[:k]
 
 
+def flip_cdf(parents, dX, n_bits, temp=0.25, explore=0.1):
+    """Per-parent distribution of the bit to flip (n_parents x 64 cumulative
+    probabilities), from the gradient of the novelty score."""
+    import torch
+
+    cdf = torch.empty((parents.shape[0], 64), dtype=torch.float32, device=parents.device)
+    pw.check(_bind().pw_flip_cdf(_p(parents), _p(dX), dX.shape[1], parents.shape[0], n_bits, temp, explore, _p(cdf),
+                                 _s()))
+    return cdf
+
+
 def mutate_guided(parents, dX, n, n_bits, flips, seed, temp=0.25, explore=0.1):
     import torch
 
+    cdf = flip_cdf(parents, dX, n_bits, temp, explore)
     out = torch.empty((n, 2), dtype=torch.int64, device=parents.device)
-    pw.check(_bind().pw_mutate_guided(_p(parents), _p(dX), dX.shape[1], parents.shape[0], n, n_bits, flips, temp,
-                                      explore, seed, _p(out), _s()))
+    pw.check(_bind().pw_mutate_cdf(_p(parents), _p(cdf), parents.shape[0], n, flips, seed, _p(out), _s()))
     return out
 
 
@@ -377,7 +388,7 @@ def run_search(tri, d, budget, use_net=True, train_n=1 << 24, epochs=1, batch=1 
     labelled by the exact kernel) shapes every mutation: the gradient of its
     novelty score with respect to the parent's signs gives, per bit, the
     first-order gain of flipping it, and flips are drawn in proportion to
-    exp(gain / temperature) (pw_mutate_guided).  Without it (the ablation)
+    exp(gain / temperature) (pw_flip_cdf, pw_mutate_cdf).  Without it (the ablation)
     the flipped bits are uniform.  Every proposal is judged by the exact
     kernel (histogram mode; witnesses index a device archive of the judged
     masks); the training masks count against the budget."""

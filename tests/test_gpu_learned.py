@@ -94,3 +94,35 @@ def test_network_ranking_beats_random_ranking(trained):
     rnd = np.random.default_rng(0).choice(len(sc), k, replace=False)
     assert true_rarity[top].mean() > 1.1 * true_rarity[rnd].mean()
     assert novel[top].mean() >= novel[rnd].mean()
+
+
+def test_flip_distribution_and_sampling():
+    """pw_flip_cdf against its formula (numpy), and pw_mutate_cdf's draws
+    against the distribution (one parent, 2^20 single flips, 5 sigma)."""
+    from paper_2604_09221_amd import learn as Lr
+
+    rng = np.random.default_rng(5)
+    n_bits, n_par = 45, 64
+    par = np.zeros((n_par, 2), dtype=np.uint64)
+    par[:, 0] = rng.integers(0, 1 << 45, size=n_par, dtype=np.uint64) & ~np.uint64(1)
+    dX = rng.normal(size=(n_par, 64)).astype(np.float32)
+    temp, explore = 0.3, 0.1
+    pt = torch.from_numpy(par.view(np.int64)).cuda()
+    cdf = Lr.flip_cdf(pt, torch.from_numpy(dX).cuda(), n_bits, temp, explore).cpu().numpy().astype(np.float64)
+    for p in range(n_par):
+        x = np.where((par[p, 0] >> np.arange(64, dtype=np.uint64)) & np.uint64(1), -1.0, 1.0)
+        gain = -2.0 * x[1:n_bits] * dX[p, 1:n_bits]
+        w = np.exp((gain - gain.max()) / (temp * np.abs(gain).max()))
+        prob = (1 - explore) * w / w.sum() + explore / (n_bits - 1)
+        want = np.concatenate([[0.0], np.cumsum(prob)[:-1], np.ones(64 - n_bits + 1)])
+        assert np.allclose(cdf[p], want, atol=2e-6)
+    n = 1 << 20
+    one = pt[:1].contiguous()
+    out = Lr.mutate_guided(one, torch.from_numpy(dX[:1]).cuda(), n, n_bits, 1, 99, temp, explore)
+    diff = (out.cpu().numpy().view(np.uint64)[:, 0] ^ par[0, 0])
+    bits = np.log2(diff.astype(np.float64)).round().astype(int)
+    freq = np.bincount(bits, minlength=64)[:64] / n
+    prob = np.concatenate([[0.0], np.diff(cdf[0][:n_bits]), [1.0 - cdf[0][n_bits - 1]]])[:n_bits]
+    assert freq[0] == 0 and freq[n_bits:].sum() == 0
+    sigma = np.sqrt(prob * (1 - prob) / n)
+    assert np.all(np.abs(freq[:n_bits] - prob) <= 5 * sigma + 1e-6)

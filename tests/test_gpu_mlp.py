@@ -59,14 +59,18 @@ def test_gemm_variants(L, M, N, K, variant):
         Bt, b_k, b_n = bits16(B), N, 1
     C32 = torch.empty((M, N), dtype=torch.float32, device="cuda")
     C16 = torch.empty((M, N), dtype=torch.int16, device="cuda")
+    cs = torch.zeros(N, dtype=torch.float32, device="cuda")
     L.gemm(At, a_m, a_k, Bt, b_k, b_n, M, N, K, C32=C32, C16=C16, bias=torch.from_numpy(bias).cuda(),
-           gate=bits16(gate), g_m=N, relu=True)
+           gate=bits16(gate), g_m=N, relu=True, colsum=cs)
     torch.cuda.synchronize()
     want = np.maximum(A @ B + bias, 0.0) * (gate > 0)
     bound = np.abs(A) @ np.abs(B) * K * 2.0 ** -24 + np.abs(bias) * 2.0 ** -24 + 1e-30
     got = C32.cpu().numpy().astype(np.float64)
     assert np.all(np.abs(got - want) <= bound)
     assert np.all(np.abs(from16(C16) - want) <= bound + np.abs(want) * 2.0 ** -8)
+    # fused column sums: per-element error plus one rounding per addition
+    cbound = bound.sum(axis=0) + (M + 2) * 2.0 ** -24 * np.abs(want).sum(axis=0) + 1e-30
+    assert np.all(np.abs(cs.cpu().numpy().astype(np.float64) - want.sum(axis=0)) <= cbound)
 
 
 @pytest.mark.parametrize("M,N,K,variant,accumulate", [
