@@ -260,7 +260,7 @@ def main():
     # kernels specialised to this triangulation (hipRTC); compile time is
     # setup, outside the timed region
     t_spec = time.perf_counter()
-    kernel = "pw_jit_enum (kernel specialised to the d=7 triangulation)"
+    kernel = "pw_jit_enum_snap (kernel specialised to the d=7 triangulation, shared snapshot per 512 masks)"
     if args.generic:
         kernel = "pw::k_enum<7> (generic)"
     else:

@@ -26,32 +26,22 @@
 
 namespace pw {
 
-std::string jit_source(const HostProgram& P) {
-  std::ostringstream o;
-  const int d = P.d, nV = P.nV, nE = P.nE, nP = P.nP;
-  o << "// generated evaluator for one degree-" << d << " triangulation\n";
-  o << "#include \"pw_device.h\"\n\nnamespace pw {\n\nstruct JitEval {\n";
-  o << "  __device__ __forceinline__ u128 operator()(Cfg<" << d
-    << ">::Mask m, const Lane& L, uint32_t& errs) const {\n";
-  o << "    using E = Eval<" << d << ">;\n";
-  // sign of vertex v: bit p of the mask, flipped by the reflection parity g
-  auto sign = [&](int v) {
-    const uint32_t rec = P.words[v];
-    const int p = rec & 0x7F, g = (rec >> 7) & 1;
-    std::string x = "E::bit(m, " + std::to_string(p) + ")";
-    return g ? "(" + x + " ^ 1u)" : x;
-  };
-  o << "    // phase 1: components of same-sign vertices; r<u> = a root u had\n";
-  for (int v = 0; v < nV; ++v) {
-    const uint32_t rec = P.words[v];
-    const int n = (rec >> 8) & 0xFF, off = rec >> 16;
-    o << "    uint32_t r" << v << " = " << v << "u; { const uint32_t sv = " << sign(v) << ";";
-    for (int k = 0; k < n; ++k) {
-      const int u = (int)P.words[nV + off + k];
-      o << " E::edge_r(L, sv, " << sign(u) << ", " << v << ", r" << v << ", r" << u << ");";
-    }
-    o << " E::close(L, " << v << ", r" << v << "); }\n";
-  }
+namespace {
+
+// sign of vertex v as an expression: bit p of the mask, flipped by the
+// reflection parity g
+std::string sign_expr(const HostProgram& P, int v) {
+  const uint32_t rec = P.words[v];
+  const int p = rec & 0x7F, g = (rec >> 7) & 1;
+  std::string x = "E::bit(m, " + std::to_string(p) + ")";
+  return g ? "(" + x + " ^ 1u)" : x;
+}
+
+int lattice_bit(const HostProgram& P, int v) { return (int)(P.words[v] & 0x7F); }
+
+// phases 2 and 3 and the call of phase 4, common to both evaluators
+void emit_tail(std::ostringstream& o, const HostProgram& P) {
+  const int nV = P.nV, nE = P.nE, nP = P.nP;
   o << "    // phase 2: antipodal pairs\n";
   for (int t = 0; t < nP; ++t) {
     const uint32_t pr = P.words[nV + nE + t];
@@ -61,22 +51,120 @@ std::string jit_source(const HostProgram& P) {
   o << "    int nR = 0;\n    E::Adj roots = 0;\n";
   for (int v = 0; v < nV; ++v) {
     const int t = v > 0 ? (int)P.words[nV + (P.words[v] >> 16)] : -1;
-    o << "    E::vertex3(L, " << v << ", " << t << ", " << sign(v) << ", " << (t >= 0 ? sign(t) : std::string("0u"))
-      << ", nR, roots);\n";
+    o << "    E::vertex3(L, " << v << ", " << t << ", " << sign_expr(P, v) << ", "
+      << (t >= 0 ? sign_expr(P, t) : std::string("0u")) << ", nR, roots);\n";
   }
-  o << "    return E::finish(L, nR, roots, errs);\n  }\n};\n\n}  // namespace pw\n\n";
-  o << "extern \"C\" __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pw::Cfg<" << d << ">::WAVES_PER_EU))) void pw_jit_codes(const void* masks, int64_t n, "
-       "uint64_t* codes, uint32_t* errflag) {\n"
+  o << "    return E::finish(L, nR, roots, errs);\n";
+}
+
+}  // namespace
+
+// Lattice bits that vary inside one chunk of the sweep kernel with the
+// snapshot: the index bits 0 .. 5 + kSnapBits land on mask bits 1 .. 6 +
+// kSnapBits when only sigma(0,0) is fixed.
+constexpr int kSnapVaryingBits = 6 + 3;
+
+bool snapshot_applies(const HostProgram& P) { return P.nA - 1 >= kSnapVaryingBits + 8; }
+
+std::string jit_source(const HostProgram& P) {
+  std::ostringstream o;
+  const int d = P.d, nV = P.nV;
+  o << "// generated evaluator for one degree-" << d << " triangulation\n";
+  o << "#include \"pw_device.h\"\n\nnamespace pw {\n\nstruct JitEval {\n";
+  o << "  __device__ __forceinline__ u128 operator()(Cfg<" << d
+    << ">::Mask m, const Lane& L, uint32_t& errs) const {\n";
+  o << "    using E = Eval<" << d << ">;\n";
+  o << "    // phase 1: components of same-sign vertices; r<u> = a root u had\n";
+  for (int v = 0; v < nV; ++v) {
+    const uint32_t rec = P.words[v];
+    const int n = (rec >> 8) & 0xFF, off = rec >> 16;
+    o << "    uint32_t r" << v << " = " << v << "u; { const uint32_t sv = " << sign_expr(P, v) << ";";
+    for (int k = 0; k < n; ++k) {
+      const int u = (int)P.words[nV + off + k];
+      o << " E::edge_r(L, sv, " << sign_expr(P, u) << ", " << v << ", r" << v << ", r" << u << ");";
+    }
+    o << " E::close(L, " << v << ", r" << v << "); }\n";
+  }
+  emit_tail(o, P);
+  o << "  }\n};\n\n";
+  if (snapshot_applies(P)) {
+    // vertices whose sign varies inside a chunk, and the full adjacency
+    std::vector<char> vary(nV, 0);
+    std::vector<std::vector<int>> adj(nV);
+    for (int v = 0; v < nV; ++v) {
+      const int b = lattice_bit(P, v);
+      vary[v] = (b >= 1 && b <= kSnapVaryingBits) ? 1 : 0;
+      const uint32_t rec = P.words[v];
+      const int n = (rec >> 8) & 0xFF, off = rec >> 16;
+      for (int k = 0; k < n; ++k) {
+        const int u = (int)P.words[nV + off + k];
+        adj[v].push_back(u);
+        adj[u].push_back(v);
+      }
+    }
+    o << "struct JitSnap {\n  using E = Eval<" << d << ">;\n";
+    o << "  // the edges between vertices of fixed sign; roots into the snapshot row\n";
+    o << "  __device__ __forceinline__ void snapshot(Cfg<" << d
+      << ">::Mask m, const Lane& L, uint8_t* snap, int lane) const {\n";
+    for (int v = 0; v < nV; ++v) {
+      if (vary[v]) continue;
+      const uint32_t rec = P.words[v];
+      const int n = (rec >> 8) & 0xFF, off = rec >> 16;
+      o << "    uint32_t r" << v << " = " << v << "u; { const uint32_t sv = " << sign_expr(P, v) << ";";
+      for (int k = 0; k < n; ++k) {
+        const int u = (int)P.words[nV + off + k];
+        if (vary[u]) continue;
+        o << " E::edge_r(L, sv, " << sign_expr(P, u) << ", " << v << ", r" << v << ", r" << u << ");";
+      }
+      o << " E::close(L, " << v << ", r" << v << "); }\n";
+    }
+    o << "    if (lane == 0) {\n";
+    for (int v = 0; v < nV; ++v)
+      if (!vary[v]) o << "      snap[" << v << "] = (uint8_t)E::root(L, r" << v << ");\n";
+    o << "    }\n  }\n";
+    o << "  // one batch: restore, the edges of the varying vertices, then as usual\n";
+    o << "  __device__ __forceinline__ u128 batch(Cfg<" << d
+      << ">::Mask m, const Lane& L, const uint8_t* snap, uint32_t& errs) const {\n";
+    for (int v = 0; v < nV; ++v)
+      o << "    E::ent(L, " << v << ") = (E::Ent)" << (vary[v] ? std::to_string(v) + "u" : "snap[" + std::to_string(v) + "]")
+        << ";\n";
+    o << "    // phase 1 for the varying vertices (in index order; each with all\n"
+         "    // its fixed-sign neighbours and its earlier varying ones)\n";
+    for (int v = 0; v < nV; ++v) {
+      if (!vary[v]) continue;
+      o << "    uint32_t r" << v << " = " << v << "u; { const uint32_t sv = " << sign_expr(P, v) << ";";
+      std::vector<int> nb = adj[v];
+      std::sort(nb.begin(), nb.end());
+      for (int u : nb) {
+        if (vary[u] && u > v) continue;
+        if (vary[u]) {
+          o << " E::edge_v(L, sv, " << sign_expr(P, u) << ", " << v << ", r" << v << ", r" << u << ");";
+        } else {
+          o << " { uint32_t t = snap[" << u << "]; E::edge_v(L, sv, " << sign_expr(P, u) << ", " << v << ", r" << v
+            << ", t); }";
+        }
+      }
+      o << " }\n";
+    }
+    emit_tail(o, P);
+    o << "  }\n};\n\n";
+  }
+  o << "}  // namespace pw\n\n";
+  const std::string attr = "extern \"C\" __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pw::Cfg<" +
+                           std::to_string(d) + ">::WAVES_PER_EU))) void ";
+  o << attr << "pw_jit_codes(const void* masks, int64_t n, uint64_t* codes, uint32_t* errflag) {\n"
        "  extern __shared__ uint32_t smem[];\n  pw::codes_body<"
     << d << ">(pw::JitEval{}, masks, n, codes, errflag, smem);\n}\n";
-  o << "extern \"C\" __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pw::Cfg<" << d << ">::WAVES_PER_EU))) void pw_jit_hist(const void* masks, int64_t n, "
-       "uint64_t index_base, const pw::HistDev* h, uint32_t* errflag) {\n"
-       "  extern __shared__ uint32_t smem[];\n  pw::hist_body<"
+  o << attr << "pw_jit_hist(const void* masks, int64_t n, uint64_t index_base, const pw::HistDev* h, "
+       "uint32_t* errflag) {\n  extern __shared__ uint32_t smem[];\n  pw::hist_body<"
     << d << ">(pw::JitEval{}, masks, n, index_base, h, errflag, smem);\n}\n";
-  o << "extern \"C\" __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pw::Cfg<" << d << ">::WAVES_PER_EU))) void pw_jit_enum(uint64_t first, uint64_t count, "
-       "pw::Runs runs, const pw::HistDev* h, uint32_t* errflag) {\n"
-       "  extern __shared__ uint32_t smem[];\n  pw::enum_body<"
+  o << attr << "pw_jit_enum(uint64_t first, uint64_t count, pw::Runs runs, const pw::HistDev* h, "
+       "uint32_t* errflag) {\n  extern __shared__ uint32_t smem[];\n  pw::enum_body<"
     << d << ">(pw::JitEval{}, first, count, runs, h, errflag, smem);\n}\n";
+  if (snapshot_applies(P))
+    o << attr << "pw_jit_enum_snap(uint64_t first, uint64_t count, pw::Runs runs, const pw::HistDev* h, "
+         "uint32_t* errflag) {\n  extern __shared__ uint32_t smem[];\n  pw::enum_snap_body<"
+      << d << ">(pw::JitSnap{}, first, count, runs, h, errflag, smem);\n}\n";
   return o.str();
 }
 
@@ -155,10 +243,11 @@ pw_status pw_tri_specialize(pw_tri_t t) {
   if (rc != PW_OK) return rc;
   hipModule_t mod = nullptr;
   PW_HIP(hipModuleLoadData(&mod, code.data()));
-  hipFunction_t fc = nullptr, fh = nullptr, fe = nullptr;
+  hipFunction_t fc = nullptr, fh = nullptr, fe = nullptr, fs = nullptr;
   hipError_t e = hipModuleGetFunction(&fc, mod, "pw_jit_codes");
   if (e == hipSuccess) e = hipModuleGetFunction(&fh, mod, "pw_jit_hist");
   if (e == hipSuccess) e = hipModuleGetFunction(&fe, mod, "pw_jit_enum");
+  if (e == hipSuccess && snapshot_applies(t->prog)) e = hipModuleGetFunction(&fs, mod, "pw_jit_enum_snap");
   if (e != hipSuccess) {
     (void)hipModuleUnload(mod);
     return set_err(PW_ERR_HIP, "%s (code %d)", hipGetErrorString(e), (int)e);
@@ -167,6 +256,7 @@ pw_status pw_tri_specialize(pw_tri_t t) {
   t->jit_codes = fc;
   t->jit_hist = fh;
   t->jit_enum = fe;
+  t->jit_enum_snap = fs;
   return PW_OK;
 }
 

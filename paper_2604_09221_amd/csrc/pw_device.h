@@ -97,12 +97,12 @@ struct Cfg {
   // a stored region code has 2 * (subtree size) <= 2 * harnack(D) bits
   static constexpr int CODE_W = 2 * harnack(D) <= 32 ? 1 : (int)(sizeof(Code) / 4);
   // per-lane LDS words:
-  //   [0, E_WORDS)            vertex entries (phases 1-3)
+  //   [0, E_WORDS)            vertex entries (phases 1-3) and a spare row
   //   [PAR_BASE, +PAR_WORDS)  parent region of every region, one byte row
   //                           of the wave per region (phases 3-4)
   // after phase 3 the entry words hold, per region: child mask (ADJ_W
   // words) and code (CODE_W words).
-  static constexpr int E_WORDS = (NV * EB + 3) / 4;
+  static constexpr int E_WORDS = ((NV + 1) * EB + 3) / 4;  // + a spare entry row (index NV)
   static constexpr int CHILD_BASE = 0;
   static constexpr int CODE_BASE = RMAX * ADJ_W;
   static constexpr int TAIL_WORDS = CODE_BASE + RMAX * CODE_W;
@@ -115,6 +115,7 @@ struct Cfg {
   // dynamic area (DYN_WORDS per lane)
   static constexpr int PAR_ROWS = RMAX + 1;
   static constexpr int DYN_WORDS = LOW_WORDS;
+  static constexpr int SNAP_BYTES = (NV + 3) / 4 * 4;  // snapshot row of the sweep kernel
   static constexpr int WAVE_BYTES = LANE_WORDS * 4 * 64;
   // waves per block: as many waves per CU as the 160 KiB of LDS allows,
   // in blocks of at most 4 waves
@@ -290,6 +291,38 @@ struct Eval {
     PW_OPAQUE(w);
     ent(L, w) = (Ent)lo;
     rv = same ? lo : rv;
+  }
+
+  // Phase 1 step for a vertex v processed out of index order (the sweep
+  // kernel that restores a shared snapshot first): v's entry already holds
+  // v, so v may become the smaller root of a union; a lane whose signs
+  // differ stores into the spare entry row NV instead.  rv = v's root so far,
+  // ru = a root u had at some earlier time (refreshed).
+  __device__ static __forceinline__ void edge_v(const Lane& L, uint32_t sv, uint32_t su, int v, uint32_t& rv,
+                                                uint32_t& ru) {
+    uint32_t r = ru;
+    uint32_t er = ent(L, (int)r);
+    while (er != r) {
+      r = er;
+      er = ent(L, (int)r);
+    }
+    const bool same = su == sv;
+    const uint32_t lo = r < rv ? r : rv, hi = r < rv ? rv : r;
+    int w = same ? (int)hi : C::NV;
+    PW_OPAQUE(w);
+    ent(L, w) = (Ent)lo;
+    rv = same ? lo : rv;
+    ru = same ? lo : r;
+  }
+
+  // root of the vertex whose walk starts at r (phase 1 entries)
+  __device__ static __forceinline__ uint32_t root(const Lane& L, uint32_t r) {
+    uint32_t er = ent(L, (int)r);
+    while (er != r) {
+      r = er;
+      er = ent(L, (int)r);
+    }
+    return r;
   }
 
   // Phase 2 step: one antipodal pair (a, b).
@@ -781,6 +814,47 @@ __device__ __forceinline__ void enum_body(const EV& ev, uint64_t first, uint64_t
     const typename C::Mask m = deposit<typename C::Mask>(idx, runs);
     const u128 code = ev(m, L, errs);
     tab.add_batch((uint64_t)code, (uint64_t)(code >> 64), valid, idx, lane, h);
+  }
+  tab.flush(h);
+  if (errs) atomicOr(errflag, errs);
+}
+
+// Exhaustive sweep with a shared snapshot.  The index bits 0..5 of an
+// enumeration select the lane and bits 6 .. 5+kSnapBits the batch within a
+// chunk of 64 << kSnapBits consecutive indices, so inside a chunk only the
+// signs of the lattice points those bits map to vary.  ev.snapshot()
+// computes, once per chunk, the union-find of the edges between vertices
+// whose signs are fixed in the chunk and stores each such vertex's root in
+// the wave's snapshot row; ev.batch() restores the lane's entries from it,
+// adds the edges of the varying vertices and finishes as usual.
+constexpr int kSnapBits = 3;
+
+template <int D, class EV>
+__device__ __forceinline__ void enum_snap_body(const EV& ev, uint64_t first, uint64_t count, const Runs& runs,
+                                               const HistDev* h, uint32_t* __restrict__ errflag, uint32_t* smem) {
+  using C = Cfg<D>;
+  constexpr uint64_t CS = 64ull << kSnapBits;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ uint8_t par_rows[C::WAVES * C::PAR_ROWS * 64];
+  __shared__ uint8_t snap_rows[C::WAVES * C::SNAP_BYTES];
+  const Lane L = lane_memory_split<D>(smem, par_rows);
+  uint8_t* snap = snap_rows + wave * C::SNAP_BYTES;
+  WaveTable tab;
+  tab.clear();
+  uint32_t errs = 0;
+  const uint64_t waves_total = (uint64_t)gridDim.x * (blockDim.x >> 6);
+  const uint64_t c1 = (first + count - 1) / CS;
+  for (uint64_t c = first / CS + (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave; c <= c1; c += waves_total) {
+    const uint64_t cbase = c * CS;
+    ev.snapshot(deposit<typename C::Mask>(cbase + (uint64_t)lane, runs), L, snap, lane);
+    __builtin_amdgcn_wave_barrier();
+    for (int b = 0; b < (1 << kSnapBits); ++b) {
+      const uint64_t idx = cbase + (uint64_t)(b * 64 + lane);
+      const bool valid = idx >= first && idx - first < count;
+      const u128 code = ev.batch(deposit<typename C::Mask>(idx, runs), L, snap, errs);
+      tab.add_batch((uint64_t)code, (uint64_t)(code >> 64), valid, idx, lane, h);
+    }
+    __builtin_amdgcn_wave_barrier();
   }
   tab.flush(h);
   if (errs) atomicOr(errflag, errs);

@@ -17,6 +17,7 @@ struct pw_tri {
   // kernels specialised to this triangulation (pw_tri_specialize), or null
   hipModule_t jit_mod = nullptr;
   hipFunction_t jit_codes = nullptr, jit_hist = nullptr, jit_enum = nullptr;
+  hipFunction_t jit_enum_snap = nullptr;  // sweep kernel with a shared snapshot, or null
 };
 
 struct pw_hist {

@@ -154,6 +154,20 @@ pw_status launch_enum(const pw_tri* t, uint64_t first, uint64_t count, const Run
   static const hipError_t attr = allow_lds<D>(reinterpret_cast<const void*>(&k_enum<D>));
   if (attr != hipSuccess) return set_err(PW_ERR_HIP, "hipFuncSetAttribute: %s (code %d)", hipGetErrorString(attr), (int)attr);
   const int64_t n = count > (uint64_t)INT64_MAX ? INT64_MAX : (int64_t)count;
+  // the sweep kernel with a shared snapshot needs index bits 0..8 on mask
+  // bits 1..9 (as when only sigma(0,0) is fixed)
+  if (t->jit_enum_snap && lds <= 64 * 1024 && runs.n >= 1 && runs.src_of(0) == 0 && runs.dst_of(0) == 1 &&
+      runs.len_of(0) >= 6 + kSnapBits) {
+    Runs r_ = runs;
+    const HistDev* hd = h->d_dev;
+    uint32_t* e_ = t->d_err;
+    void* args[] = {&first, &count, &r_, &hd, &e_};
+    const uint64_t cs = 64ull << kSnapBits;
+    const int64_t chunks = (int64_t)((first + count - 1) / cs - first / cs + 1);
+    PW_HIP(hipModuleLaunchKernel(t->jit_enum_snap, blocks_for<D>(C::WAVES, chunks), 1, 1, threads, 1, 1,
+                                 (unsigned)lds, s, args, nullptr));
+    return PW_OK;
+  }
   if (t->jit_enum && lds <= 64 * 1024) {
     Runs r_ = runs;
     const HistDev* hd = h->d_dev;

@@ -41,3 +41,4 @@ template <class T> static inline void __hip_atomic_store(T*, T, int, int) { emu_
 template <class T> static inline bool __hip_atomic_compare_exchange_strong(T*, T*, T, int, int, int) { emu_unsupported(); }
 #define PW_OPAQUE(x) asm volatile("" : "+r"(x))
 #define PW_OPAQUE_S(x) asm volatile("" : "+r"(x))
+#define __builtin_amdgcn_wave_barrier() ((void)0)

@@ -248,6 +248,7 @@ def test_specialized_kernels_match_oracle(pw):
     """Kernels generated for one triangulation: codes, histograms and
     witnesses bit-exact against the oracle (and hence the generic path)."""
     cases = [(4, I.lift_triangulation(4, 2, noise=1.0), 1 << 14),
+             (6, I.lift_triangulation(6, 3, noise=1.0), 1 << 15),
              (7, I.standard_triangulation(7), 1 << 18),
              (8, fig2_edges("rank016"), 1 << 16)]
     for d, E, n in cases:
@@ -266,4 +267,10 @@ def test_specialized_kernels_match_oracle(pw):
         tri.histogram(pw.mask_tensor(masks, d), h2, index_base=5)
         assert h2.read() == oracle_hist(oracle.scheme_many(d, E, masks, threads=THREADS),
                                         index_of=np.arange(5, 5 + len(masks), dtype=np.uint64))
+        if d == 7:  # the sweep kernel's last, partial chunk
+            h3 = pw.Histogram(1024)
+            last = (1 << 35) - 5000
+            tri.enumerate_range(last, 5000, h3)
+            want3 = oracle.scheme_many(d, E, enum_masks(last, 5000, nA=I.n_points(d)), threads=THREADS)
+            assert h3.read() == oracle_hist(want3, index_of=np.arange(last, last + 5000, dtype=np.uint64))
         assert tri.errors() == 0

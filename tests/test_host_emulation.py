@@ -5,7 +5,9 @@ hipRTC compiles for gfx950) is compiled here with g++ together with the
 device header, through tests/host_shim.h, and run lane by lane over one
 wave's LDS area.  Every code must equal the oracle's, and a lane may only
 write its own bytes of the area (entries, words, parent-table rows).  No GPU
-is needed; wave-level parts (histogram, ballots) are not covered here."""
+is needed; wave-level parts (histogram, ballots) are not covered here.  The
+sweep kernel's evaluator (a snapshot of the fixed-sign part, restored per
+batch) is checked the same way, with the snapshot taken from another mask."""
 from __future__ import annotations
 
 import os
@@ -43,14 +45,23 @@ int main(int argc, char** argv) {
     memset(own.data(), 0, bytes);
     for (int k = 0; k < C::LOW_WORDS; ++k)
       for (int b = 0; b < 4; ++b) own[k * 256 + 4 * lane + b] = 1;
-    for (int v = 0; v < C::NV; ++v)
+    for (int v = 0; v <= C::NV; ++v)  // entries and the spare row
       for (int b = 0; b < C::EB; ++b) own[v * C::ESTRIDE + C::EB * lane + b] = 1;
     for (int x = 0; x < 4 * C::PAR_WORDS; ++x) own[C::PAR_BASE * 256 + x * 64 + lane] = 1;
     memcpy(snap.data(), smem, bytes);
     typename C::Mask m = (typename C::Mask)in[2 * i];
     if (sizeof(m) == 16) m |= (typename C::Mask)((pw::u128)in[2 * i + 1] << 64);
     uint32_t errs = 0;
+#ifdef SNAP
+    // the sweep kernel's evaluator: snapshot of the fixed-sign part taken
+    // from another mask that differs from m only in the varying bits 1..9
+    typename C::Mask m1 = m ^ (typename C::Mask)((((uint64_t)i * 0x9E3779B97F4A7C15ull) >> 40) & 0x3FEull);
+    static uint8_t srow[C::SNAP_BYTES];
+    pw::JitSnap{}.snapshot(m1, L, srow, 0);
+    const pw::u128 code = pw::JitSnap{}.batch(m, L, srow, errs);
+#else
     const pw::u128 code = pw::JitEval{}(m, L, errs);
+#endif
     out[2 * i] = errs ? 0 : (uint64_t)code;
     out[2 * i + 1] = errs ? 0 : (uint64_t)(code >> 64);
     const unsigned char* cur = (const unsigned char*)smem;
@@ -67,11 +78,11 @@ int main(int argc, char** argv) {
 '''
 
 
-def _compile(tmp_path, d, edges):
+def _compile(tmp_path, d, edges, snap):
     src = pw.jit_source(d, edges)
-    src = src[:src.index('extern "C"')]          # the evaluator; the kernels need a GPU
+    src = src[:src.index('extern "C"')]          # the evaluators; the kernels need a GPU
     path = tmp_path / f"emu_d{d}.cpp"
-    path.write_text('#include "host_shim.h"\n' + src + MAIN.replace("DEG", str(d)))
+    path.write_text(("#define SNAP 1\n" if snap else "") + '#include "host_shim.h"\n' + src + MAIN.replace("DEG", str(d)))
     exe = tmp_path / f"emu_d{d}"
     subprocess.check_call(["g++", "-O1", "-std=c++17", "-w", "-fsanitize=address,undefined",
                            "-fno-sanitize-recover=undefined", "-I", HERE, "-I", CSRC, "-o", str(exe), str(path)])
@@ -79,11 +90,14 @@ def _compile(tmp_path, d, edges):
 
 
 @pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
-@pytest.mark.parametrize("d,noise,seed,n", [(4, None, 0, 3000), (5, 1.0, 2, 2000), (6, 1.0, 3, 2000),
-                                            (7, None, 0, 3000), (7, 1.0, 4, 2000), (9, None, 0, 600)])
-def test_evaluator_on_host_matches_oracle(tmp_path, d, noise, seed, n):
+@pytest.mark.parametrize("d,noise,seed,n,snap", [(4, None, 0, 3000, False), (5, 1.0, 2, 2000, False),
+                                                 (6, 1.0, 3, 2000, False), (7, None, 0, 3000, False),
+                                                 (7, 1.0, 4, 2000, False), (9, None, 0, 600, False),
+                                                 (6, 1.0, 5, 2000, True), (7, None, 0, 3000, True),
+                                                 (7, 1.0, 6, 2000, True)])
+def test_evaluator_on_host_matches_oracle(tmp_path, d, noise, seed, n, snap):
     edges = I.standard_triangulation(d) if noise is None else I.lift_triangulation(d, seed, noise=noise)
-    exe = _compile(tmp_path, d, edges)
+    exe = _compile(tmp_path, d, edges, snap)
     masks = np.ascontiguousarray(I.random_masks(d, seed + 11, n).astype(np.uint64))
     # first rows: the Harnack distribution (the most regions), all '+', all
     # '-' except sigma(0,0), and every single flip of the Harnack mask
