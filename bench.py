@@ -45,7 +45,7 @@ PEAK_INT_OPS = 256 * 64 * 2.4e9
 KERNEL_SOURCES = ("paper_2604_09221_amd/csrc/pw_device.h", "paper_2604_09221_amd/csrc/pw_internal.h",
                   "paper_2604_09221_amd/csrc/jit.cpp", "paper_2604_09221_amd/csrc/scheme.hip",
                   "paper_2604_09221_amd/csrc/tri.cpp")
-TRAFFIC_PROFILE = "profiles/pw_jit_enum_d7_sweep_counters.md"
+TRAFFIC_PROFILE = "profiles/pw_jit_enum_snap_d7_sweep_counters.md"
 
 
 def kernel_sources_sha256():

@@ -120,14 +120,18 @@ std::string jit_source(const HostProgram& P) {
     }
     o << "    if (lane == 0) {\n";
     for (int v = 0; v < nV; ++v)
-      if (!vary[v]) o << "      snap[" << v << "] = (uint8_t)E::root(L, r" << v << ");\n";
+      if (!vary[v]) o << "      snap[" << v << "] = (uint8_t)E::root(L, " << v << "u);\n";
     o << "    }\n  }\n";
     o << "  // one batch: restore, the edges of the varying vertices, then as usual\n";
     o << "  __device__ __forceinline__ u128 batch(Cfg<" << d
       << ">::Mask m, const Lane& L, const uint8_t* snap, uint32_t& errs) const {\n";
-    for (int v = 0; v < nV; ++v)
+    // (a compiler barrier every 8 entries keeps the row loads from all
+    // being hoisted at once, which would need a register each)
+    for (int v = 0; v < nV; ++v) {
       o << "    E::ent(L, " << v << ") = (E::Ent)" << (vary[v] ? std::to_string(v) + "u" : "snap[" + std::to_string(v) + "]")
         << ";\n";
+      if (v % 8 == 7) o << "    PW_FENCE();\n";
+    }
     o << "    // phase 1 for the varying vertices (in index order; each with all\n"
          "    // its fixed-sign neighbours and its earlier varying ones)\n";
     for (int v = 0; v < nV; ++v) {

@@ -55,6 +55,10 @@ typedef __hip_internal::int64_t int64_t;
 #ifndef PW_OPAQUE
 #define PW_OPAQUE(x) asm volatile("" : "+v"(x))
 #endif
+// a compiler-only memory barrier: loads and stores are not moved across it
+#ifndef PW_FENCE
+#define PW_FENCE() asm volatile("" ::: "memory")
+#endif
 // the same for a wave-uniform value (kept in a scalar register)
 #ifndef PW_OPAQUE_S
 #define PW_OPAQUE_S(x) asm volatile("" : "+s"(x))
