@@ -39,17 +39,31 @@ struct Item {
   int64_t count;
 };
 
+// Degrees >= 10 use phase-4 tables capped at 32 regions (about half the
+// LDS of the full tables at d = 12, so more waves fit per CU); a mask with
+// more regions is put on an overflow list and evaluated again, with the
+// full tables, by k_multi_big after the persistent launch.
+constexpr int multi_cap(int d) { return d >= 10 ? 32 : 0; }
+
+struct Overflow {
+  uint64_t* list;              // (triangulation, global mask index) pairs
+  unsigned long long* n;       // entries claimed (may exceed cap)
+  unsigned long long cap;
+};
+
 template <int D>
 __device__ __forceinline__ void run_item(const TriDesc& t, const Item& w, const uint64_t* __restrict__ masks,
-                                         uint64_t* __restrict__ codes, uint32_t* smem, int lane_words, int lane) {
-  using C = Cfg<D>;
-  const Lane L = lane_memory<D>(smem, lane_words);
+                                         uint64_t* __restrict__ codes, uint32_t* smem, int lane_words, int lane,
+                                         const Overflow& ov) {
+  constexpr int RC = multi_cap(D);
+  using C = Cfg<D, RC>;
+  const Lane L = lane_memory<D, RC>(smem, lane_words);
   uint32_t errs = 0;
   WaveTable tab;
   tab.clear();
   for (int64_t base = 0; base < w.count; base += 64) {
     const int64_t i = w.begin + base + lane;
-    const bool valid = base + lane < w.count;
+    bool valid = base + lane < w.count;
     typename C::Mask m = 0;
     if (valid) {
       if constexpr (sizeof(typename C::Mask) == 8) {
@@ -58,7 +72,17 @@ __device__ __forceinline__ void run_item(const TriDesc& t, const Item& w, const 
         m = ((u128)masks[2 * i + 1] << 64) | (u128)masks[2 * i];
       }
     }
-    const u128 code = Eval<D>::run(t.prog, m, L, errs);
+    uint32_t e = 0;
+    const u128 code = Eval<D, RC>::run(t.prog, m, L, e);
+    if (C::CAPPED && (e & kErrOverflow) && valid) {
+      const unsigned long long slot = atomicAdd(ov.n, 1ull);
+      if (slot < ov.cap) {
+        ov.list[2 * slot] = (uint64_t)w.tri;
+        ov.list[2 * slot + 1] = (uint64_t)i;
+      }
+      valid = false;  // counted and written by k_multi_big
+    }
+    errs |= e & ~kErrOverflow;
     if (codes && valid) {
       codes[2 * i] = (uint64_t)code;
       codes[2 * i + 1] = (uint64_t)(code >> 64);
@@ -72,7 +96,7 @@ __device__ __forceinline__ void run_item(const TriDesc& t, const Item& w, const 
 __global__ __launch_bounds__(256) void k_multi(const TriDesc* __restrict__ tris, const Item* __restrict__ items,
                                                int64_t n_items, unsigned long long* __restrict__ ticket,
                                                unsigned long long base, const uint64_t* __restrict__ masks,
-                                               uint64_t* __restrict__ codes, int lane_words) {
+                                               uint64_t* __restrict__ codes, int lane_words, Overflow ov) {
   extern __shared__ uint32_t smem[];
   const int lane = threadIdx.x & 63;
   while (true) {
@@ -85,18 +109,57 @@ __global__ __launch_bounds__(256) void k_multi(const TriDesc* __restrict__ tris,
     const Item w = items[it];
     const TriDesc t = tris[w.tri];
     switch (t.d) {
-      case 1: run_item<1>(t, w, masks, codes, smem, lane_words, lane); break;
-      case 2: run_item<2>(t, w, masks, codes, smem, lane_words, lane); break;
-      case 3: run_item<3>(t, w, masks, codes, smem, lane_words, lane); break;
-      case 4: run_item<4>(t, w, masks, codes, smem, lane_words, lane); break;
-      case 5: run_item<5>(t, w, masks, codes, smem, lane_words, lane); break;
-      case 6: run_item<6>(t, w, masks, codes, smem, lane_words, lane); break;
-      case 7: run_item<7>(t, w, masks, codes, smem, lane_words, lane); break;
-      case 8: run_item<8>(t, w, masks, codes, smem, lane_words, lane); break;
-      case 9: run_item<9>(t, w, masks, codes, smem, lane_words, lane); break;
-      case 10: run_item<10>(t, w, masks, codes, smem, lane_words, lane); break;
-      case 11: run_item<11>(t, w, masks, codes, smem, lane_words, lane); break;
-      case 12: run_item<12>(t, w, masks, codes, smem, lane_words, lane); break;
+      case 1: run_item<1>(t, w, masks, codes, smem, lane_words, lane, ov); break;
+      case 2: run_item<2>(t, w, masks, codes, smem, lane_words, lane, ov); break;
+      case 3: run_item<3>(t, w, masks, codes, smem, lane_words, lane, ov); break;
+      case 4: run_item<4>(t, w, masks, codes, smem, lane_words, lane, ov); break;
+      case 5: run_item<5>(t, w, masks, codes, smem, lane_words, lane, ov); break;
+      case 6: run_item<6>(t, w, masks, codes, smem, lane_words, lane, ov); break;
+      case 7: run_item<7>(t, w, masks, codes, smem, lane_words, lane, ov); break;
+      case 8: run_item<8>(t, w, masks, codes, smem, lane_words, lane, ov); break;
+      case 9: run_item<9>(t, w, masks, codes, smem, lane_words, lane, ov); break;
+      case 10: run_item<10>(t, w, masks, codes, smem, lane_words, lane, ov); break;
+      case 11: run_item<11>(t, w, masks, codes, smem, lane_words, lane, ov); break;
+      case 12: run_item<12>(t, w, masks, codes, smem, lane_words, lane, ov); break;
+      default: break;
+    }
+  }
+}
+
+// One overflow entry per lane, full phase-4 tables (Cfg<D>).
+template <int D>
+__device__ __forceinline__ void run_big(const TriDesc& t, int64_t i, const uint64_t* __restrict__ masks,
+                                        uint64_t* __restrict__ codes, uint32_t* smem) {
+  using C = Cfg<D>;
+  const Lane L = lane_memory<D>(smem, Cfg<12>::LANE_WORDS);
+  typename C::Mask m;
+  if constexpr (sizeof(typename C::Mask) == 8) {
+    m = masks[2 * i];
+  } else {
+    m = ((u128)masks[2 * i + 1] << 64) | (u128)masks[2 * i];
+  }
+  uint32_t e = 0;
+  const u128 code = Eval<D>::run(t.prog, m, L, e);
+  if (e) atomicOr(t.err, e);
+  if (codes) {
+    codes[2 * i] = (uint64_t)code;
+    codes[2 * i + 1] = (uint64_t)(code >> 64);
+  }
+  // (the descriptor differs between lanes here: a plain vector load)
+  if (t.use_hist && code != 0) global_insert(*t.hist, (uint64_t)code, (uint64_t)(code >> 64), 1, (uint64_t)i);
+}
+
+__global__ __launch_bounds__(64) void k_multi_big(const TriDesc* __restrict__ tris, const uint64_t* __restrict__ list,
+                                                  int64_t n, const uint64_t* __restrict__ masks,
+                                                  uint64_t* __restrict__ codes) {
+  extern __shared__ uint32_t smem[];
+  for (int64_t k = (int64_t)blockIdx.x * 64 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 64) {
+    const TriDesc t = tris[list[2 * k]];
+    const int64_t i = (int64_t)list[2 * k + 1];
+    switch (t.d) {
+      case 10: run_big<10>(t, i, masks, codes, smem); break;
+      case 11: run_big<11>(t, i, masks, codes, smem); break;
+      case 12: run_big<12>(t, i, masks, codes, smem); break;
       default: break;
     }
   }
@@ -113,9 +176,9 @@ int lane_words_for(int d) {
     case 7: return Cfg<7>::LANE_WORDS;
     case 8: return Cfg<8>::LANE_WORDS;
     case 9: return Cfg<9>::LANE_WORDS;
-    case 10: return Cfg<10>::LANE_WORDS;
-    case 11: return Cfg<11>::LANE_WORDS;
-    case 12: return Cfg<12>::LANE_WORDS;
+    case 10: return Cfg<10, multi_cap(10)>::LANE_WORDS;
+    case 11: return Cfg<11, multi_cap(11)>::LANE_WORDS;
+    case 12: return Cfg<12, multi_cap(12)>::LANE_WORDS;
     default: return 0;
   }
 }
@@ -129,7 +192,11 @@ struct MultiScratch {
   size_t item_cap = 0;
   unsigned long long* d_ticket = nullptr;
   unsigned long long issued = 0;  // tickets handed out by earlier launches
+  uint64_t* d_over = nullptr;     // overflow list (kOverflowCap pairs)
+  unsigned long long* d_over_n = nullptr;
 };
+
+constexpr unsigned long long kOverflowCap = 1ull << 20;
 
 MultiScratch& scratch_for_multi() {
   static MultiScratch s;
@@ -196,6 +263,11 @@ extern "C" pw_status patchwork_scheme_batch_multi(const pw_tri_t* tris, int32_t 
     PW_HIP(hipMemset(S.d_ticket, 0, sizeof(unsigned long long)));
     S.issued = 0;
   }
+  if (!S.d_over) {
+    PW_HIP(hipMalloc(&S.d_over, sizeof(uint64_t) * 2 * kOverflowCap));
+    PW_HIP(hipMalloc(&S.d_over_n, sizeof(unsigned long long)));
+  }
+  PW_HIP(hipMemsetAsync(S.d_over_n, 0, sizeof(unsigned long long), stream));
   // the descriptor and item tables are reused by the next call: finish the
   // copies before returning so the host vectors may go away
   PW_HIP(hipMemcpyAsync(S.d_tris, desc.data(), sizeof(TriDesc) * desc.size(), hipMemcpyHostToDevice, stream));
@@ -218,10 +290,30 @@ extern "C" pw_status patchwork_scheme_batch_multi(const pw_tri_t* tris, int32_t 
   const unsigned long long base = S.issued;
   // every block takes one ticket past the end before it stops
   S.issued += items.size() + (unsigned long long)blocks * c.waves_per_block;
+  const Overflow ov{S.d_over, S.d_over_n, kOverflowCap};
   hipLaunchKernelGGL(k_multi, dim3((unsigned)blocks), dim3(threads), lds, stream, S.d_tris, S.d_items,
                      (int64_t)items.size(), S.d_ticket, base, static_cast<const uint64_t*>(d_masks), d_codes,
-                     max_words);
+                     max_words, ov);
   PW_HIP(hipGetLastError());
+  unsigned long long n_over = 0;
+  PW_HIP(hipMemcpyAsync(&n_over, S.d_over_n, sizeof n_over, hipMemcpyDeviceToHost, stream));
   PW_HIP(hipStreamSynchronize(stream));
+  if (n_over > kOverflowCap)
+    return set_err(PW_ERR_INTERNAL, "%llu masks have more than 31 ovals (at most %llu per call): split the call",
+                   n_over, kOverflowCap);
+  if (n_over > 0) {
+    const size_t big_lds = (size_t)Cfg<12>::LANE_WORDS * 4 * 64;
+    static const hipError_t attr_big = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_multi_big),
+                                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (attr_big != hipSuccess) {
+      (void)hipGetLastError();
+      return set_err(PW_ERR_HIP, "hipFuncSetAttribute: %s (code %d)", hipGetErrorString(attr_big), (int)attr_big);
+    }
+    const int64_t nb = std::min<int64_t>(((int64_t)n_over + 63) / 64, (int64_t)cu_count());
+    hipLaunchKernelGGL(k_multi_big, dim3((unsigned)nb), dim3(64), big_lds, stream, S.d_tris, S.d_over,
+                       (int64_t)n_over, static_cast<const uint64_t*>(d_masks), d_codes);
+    PW_HIP(hipGetLastError());
+    PW_HIP(hipStreamSynchronize(stream));
+  }
   return PW_OK;
 }

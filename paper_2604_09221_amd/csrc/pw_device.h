@@ -79,17 +79,23 @@ struct cond<false, X, Y> {
 
 // ------------------------------------------------------------------ config
 
-template <int D>
+// RCAP > 0: the phase-4 tables are sized for at most RCAP regions (a mask
+// with more is reported as kErrOverflow and must be evaluated again with
+// the full tables); RCAP = 0: sized for the Harnack bound.
+template <int D, int RCAP = 0>
 struct Cfg {
   static constexpr int NA = n_points(D);
   static constexpr int NV = n_vertices(D);
   static constexpr int NE = n_diamond_edges(D);
   static constexpr int NP = 2 * D;
-  static constexpr int RMAX = harnack(D) + 1;  // regions = ovals + 1 <= M + 1
+  static constexpr int RFULL = harnack(D) + 1;  // regions = ovals + 1 <= M + 1
+  static constexpr bool CAPPED = RCAP > 0 && RCAP < RFULL;
+  static constexpr int RMAX = CAPPED ? RCAP : RFULL;
   static constexpr bool EVEN = (D % 2) == 0;
   using Mask = typename cond<(NA <= 64), uint64_t, u128>::type;
   using Adj = typename cond<(RMAX <= 32), uint32_t, uint64_t>::type;
-  using Code = typename cond<(D <= 9), uint64_t, u128>::type;
+  // codes of at most RMAX - 1 nodes below the root: 2 (RMAX - 1) bits
+  using Code = typename cond<(2 * (RMAX - 1) + 2 <= 64), uint64_t, u128>::type;
   static constexpr int ADJ_W = sizeof(Adj) / 4;
   // vertex entries: u8 (parent index) where odd d needs no parity flags
   // and 7 bits index every vertex (d <= 7); u16 otherwise (parent index in
@@ -98,8 +104,8 @@ struct Cfg {
   using Ent = typename cond<NARROW, uint8_t, uint16_t>::type;
   static constexpr int EB = NARROW ? 1 : 2;
   static constexpr int ESTRIDE = 64 * EB;  // bytes between entries v and v + 1 of a lane
-  // a stored region code has 2 * (subtree size) <= 2 * harnack(D) bits
-  static constexpr int CODE_W = 2 * harnack(D) <= 32 ? 1 : (int)(sizeof(Code) / 4);
+  // a stored region code has 2 * (subtree size) <= 2 * (RMAX - 1) bits
+  static constexpr int CODE_W = 2 * (RMAX - 1) <= 32 ? 1 : (int)(sizeof(Code) / 4);
   // per-lane LDS words:
   //   [0, E_WORDS)            vertex entries (phases 1-3) and a spare row
   //   [PAR_BASE, +PAR_WORDS)  parent region of every region, one byte row
@@ -183,9 +189,9 @@ __device__ __forceinline__ int popc_t(T x) {
 
 // ------------------------------------------------------------- one mask
 
-template <int D>
+template <int D, int RCAP = 0>
 struct Eval {
-  using C = Cfg<D>;
+  using C = Cfg<D, RCAP>;
   using Mask = typename C::Mask;
   using Adj = typename C::Adj;
   using Code = typename C::Code;
@@ -423,7 +429,7 @@ struct Eval {
   __device__ __forceinline__ static u128 finish(const Lane& L, int nR, Adj roots, uint32_t& errs) {
     uint32_t err = 0;
     if (roots == 0 || (roots & (roots - 1))) err |= kErrRoot;  // exactly one root region
-    if (nR > C::RMAX) err |= kErrRegions;
+    if (nR > C::RMAX) err |= C::CAPPED ? kErrOverflow : kErrRegions;
     const int root = roots ? ctz_t(roots) : 0;
     if (err) {
       errs |= err;
@@ -731,12 +737,13 @@ struct RtEval {
 
 // this lane's view of its wave's area (lane_words words per lane, the
 // parent table at word PAR_BASE)
-template <int D>
+template <int D, int RCAP = 0>
 __device__ __forceinline__ Lane lane_memory(uint32_t* smem, int lane_words) {
+  using C = Cfg<D, RCAP>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t* base = smem + wave * lane_words * 64;
   char* cb = reinterpret_cast<char*>(base);
-  return Lane{base + lane, cb + Cfg<D>::EB * lane, cb + Cfg<D>::PAR_BASE * 256 + lane};
+  return Lane{base + lane, cb + C::EB * lane, cb + C::PAR_BASE * 256 + lane};
 }
 
 // the same with the parent table in its own __shared__ array (par: PAR_ROWS

@@ -36,6 +36,7 @@ constexpr uint32_t kErrRegions = 1u;   // more regions than Harnack's bound
 constexpr uint32_t kErrRoot = 2u;      // no unique root
 constexpr uint32_t kErrTree = 4u;      // adjacency graph is not a tree
 constexpr uint32_t kErrSelfLoop = 8u;  // self-loop for even d
+constexpr uint32_t kErrOverflow = 16u;  // more regions than capped tables hold (not an error of the input)
 
 #if !defined(__HIPCC_RTC__)
 struct HostProgram {

@@ -98,3 +98,43 @@ def test_multi_literal_lift_slots_and_edge_cases(pw):
         pw.batch_multi(tris, mt, off3, codes=codes)
     empty = np.zeros(len(tris) + 1, dtype=np.int64)
     pw.batch_multi(tris, mt, empty, codes=codes)                 # nothing to do
+
+
+def test_multi_many_regions_take_the_overflow_path(pw):
+    """Degrees 10..12 run with phase-4 tables for at most 32 regions; masks
+    with more (Harnack: 38, 46, 57 regions, and near-Harnack masks) are
+    evaluated again with the full tables.  Codes, histograms (counts and
+    witnesses) and error flags must be as for any other mask."""
+    rng = np.random.default_rng(9)
+    degs = [10, 11, 12, 9, 12]
+    edges = [I.standard_triangulation(d) if k % 2 == 0 else I.lift_triangulation(d, 40 + k, noise=1.0)
+             for k, d in enumerate(degs)]
+    masks = []
+    for k, d in enumerate(degs):
+        nA = I.n_points(d)
+        h = I.harnack_mask(d)
+        rows = [h] + [h ^ (1 << int(b)) for b in rng.integers(1, nA, size=150)]
+        rows += [h ^ (1 << int(a)) ^ (1 << int(b)) for a, b in rng.integers(1, nA, size=(100, 2))]
+        m = np.zeros((len(rows) + 300, 2), dtype=np.uint64)
+        m[:len(rows), 0] = [x & ((1 << 64) - 1) for x in rows]
+        m[:len(rows), 1] = [x >> 64 for x in rows]
+        m[len(rows):] = I.random_masks(d, 77 + k, 300)
+        masks.append(m)
+    offsets = np.concatenate([[0], np.cumsum([len(m) for m in masks])]).astype(np.int64)
+    tris = [pw.Triangulation(int(d), E) for d, E in zip(degs, edges)]
+    allm = np.vstack(masks)
+    mt = torch.from_numpy(I.masks128(allm)).cuda()
+    codes = torch.empty((len(allm), 2), dtype=torch.int64, device="cuda")
+    hists = [pw.Histogram(4096) for _ in tris]
+    pw.batch_multi(tris, mt, offsets, hists=hists, codes=codes, config=(256, 1, 0))
+    got = codes.cpu().numpy().view(np.uint64)
+    many = 0
+    for t, (d, E) in enumerate(zip(degs, edges)):
+        a, b = offsets[t], offsets[t + 1]
+        want = oracle.scheme_many(int(d), E, masks[t], threads=THREADS)
+        assert np.array_equal(got[a:b], want), (t, int(d))
+        assert hists[t].read() == hist_of(want, a), (t, int(d))
+        assert tris[t].errors() == 0
+        if d >= 10:
+            many += sum(oracle.n_ovals(int(lo) | (int(hi) << 64)) + 1 > 32 for lo, hi in want)
+    assert many > 100   # the overflow path did run
