@@ -196,12 +196,20 @@ def bench_learned(args):
     log = (lambda m: print(m, file=sys.stderr, flush=True))
     res = [Lr.run_uniform(tri, d, budget)]
     per_round = max(1 << 20, budget >> 8)
+    target = res[0]["distinct"]
     res.append(Lr.run_search(tri, d, budget, use_net=True, train_n=min(1 << 24, budget // 4), per_round=per_round,
-                             log=log))
+                             log=log, target=target))
     res.append(Lr.run_search(tri, d, budget, use_net=False, train_n=min(1 << 24, budget // 4), per_round=per_round,
-                             log=log))
+                             log=log, target=target))
+    # the same uniform stream again, untimed, for its curve
+    res[0]["curve"] = Lr.run_uniform(tri, d, budget, curve=True)["curve"]
     for r in res:
         r["distinct_per_gpu_second"] = r["distinct"] / r["gpu_seconds"]
+    # GPU-seconds each search needs to find as many schemes as uniform
+    # sampling found with the whole budget (curve points: evaluations,
+    # distinct, seconds since the start, training included)
+    for r in res[1:]:
+        r["seconds_to_uniform_count"] = r.pop("seconds_to_target")
     return {
         "metric": "distinct real schemes found per GPU-second at d=8",
         "value": res[1]["distinct_per_gpu_second"], "unit": "schemes/s", "n_gpus": 1, "steps": 1, "warmup": 0,

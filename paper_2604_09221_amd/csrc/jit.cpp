@@ -39,6 +39,8 @@ std::string sign_expr(const HostProgram& P, int v) {
 
 int lattice_bit(const HostProgram& P, int v) { return (int)(P.words[v] & 0x7F); }
 
+constexpr int kAhead = 4;  // phase 3 reads entries this many vertices ahead
+
 // phases 2 and 3 and the call of phase 4, common to both evaluators
 void emit_tail(std::ostringstream& o, const HostProgram& P) {
   const int nV = P.nV, nE = P.nE, nP = P.nP;
@@ -47,12 +49,15 @@ void emit_tail(std::ostringstream& o, const HostProgram& P) {
     const uint32_t pr = P.words[nV + nE + t];
     o << "    E::pair(L, " << (pr & 0xFFFF) << ", " << (pr >> 16) << ");\n";
   }
-  o << "    // phase 3: region ids and the region tree\n";
+  o << "    // phase 3: region ids and the region tree (each vertex's entry read\n"
+       "    // " << kAhead << " vertices ahead)\n";
   o << "    int nR = 0;\n    E::Adj roots = 0;\n";
+  for (int v = 0; v < std::min(kAhead, nV); ++v) o << "    const uint32_t e" << v << " = E::ent(L, " << v << ");\n";
   for (int v = 0; v < nV; ++v) {
     const int t = v > 0 ? (int)P.words[nV + (P.words[v] >> 16)] : -1;
-    o << "    E::vertex3(L, " << v << ", " << t << ", " << sign_expr(P, v) << ", "
-      << (t >= 0 ? sign_expr(P, t) : std::string("0u")) << ", nR, roots);\n";
+    if (v + kAhead < nV) o << "    const uint32_t e" << v + kAhead << " = E::ent(L, " << v + kAhead << ");\n";
+    o << "    E::vertex3e(L, " << v << ", " << t << ", " << sign_expr(P, v) << ", "
+      << (t >= 0 ? sign_expr(P, t) : std::string("0u")) << ", e" << v << ", nR, roots);\n";
   }
   o << "    return E::finish(L, nR, roots, errs);\n";
 }

@@ -369,7 +369,14 @@ struct Eval {
   // the parent table.
   __device__ static __forceinline__ void vertex3(const Lane& L, int v, int t, uint32_t sv, uint32_t st, int& nR,
                                                  Adj& roots) {
-    const uint32_t ev = ent(L, v);
+    vertex3e(L, v, t, sv, st, ent(L, v), nR, roots);
+  }
+
+  // the same with v's entry ev read in advance (phase 3 rewrites only the
+  // entries of vertices already done, so it may be read any time after
+  // phase 2)
+  __device__ static __forceinline__ void vertex3e(const Lane& L, int v, int t, uint32_t sv, uint32_t st,
+                                                  uint32_t ev, int& nR, Adj& roots) {
     const uint32_t p = idx(ev);
     const bool is_root = p == (uint32_t)v;
     const uint32_t ep = ent(L, (int)p);  // p < v holds its region id already; a root reads its own entry

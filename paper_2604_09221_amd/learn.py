@@ -360,8 +360,10 @@ def rarest_witnesses(hist, archive, k):
     return archive[idx], len(h)
 
 
-def run_uniform(tri, d, budget, chunk=1 << 22, seed=1):
-    """Uniform masks judged by the exact kernel (histogram mode)."""
+def run_uniform(tri, d, budget, chunk=1 << 22, seed=1, curve=False):
+    """Uniform masks judged by the exact kernel (histogram mode).  With
+    curve=True the histogram is read after every chunk (a host round trip,
+    so such a run is for the curve, not for timing)."""
     import torch
 
     nA = (d + 1) * (d + 2) // 2
@@ -369,19 +371,25 @@ def run_uniform(tri, d, budget, chunk=1 << 22, seed=1):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = 0
+    points = []
     while done < budget:
         n = min(chunk, budget - done)
         m = random_masks(seed, done, n, nA)
         m64 = m[:, 0].contiguous() if pw.mask_bytes(d) == 8 else m
         tri.histogram(m64, hist, index_base=done)
         done += n
+        if curve:
+            points.append((done, len(hist.read())))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return {"method": "uniform", "evaluations": done, "distinct": len(hist.read()), "gpu_seconds": dt}
+    out = {"method": "uniform", "evaluations": done, "distinct": len(hist.read()), "gpu_seconds": dt}
+    if curve:
+        out["curve"] = points[:: max(1, len(points) // 32)] + ([points[-1]] if len(points) > 32 else [])
+    return out
 
 
 def run_search(tri, d, budget, use_net=True, train_n=1 << 24, epochs=1, batch=1 << 16, lr=3e-3, per_round=1 << 22,
-               n_elite=4096, temp=0.25, explore=0.1, seed=7, log=None):
+               n_elite=4096, temp=0.25, explore=0.1, seed=7, log=None, target=None):
     """Mutation search from the witnesses of the rarest schemes seen.
 
     With use_net, the network (trained first on train_n uniform masks
@@ -391,7 +399,9 @@ def run_search(tri, d, budget, use_net=True, train_n=1 << 24, epochs=1, batch=1 
     exp(gain / temperature) (pw_flip_cdf, pw_mutate_cdf).  Without it (the ablation)
     the flipped bits are uniform.  Every proposal is judged by the exact
     kernel (histogram mode; witnesses index a device archive of the judged
-    masks); the training masks count against the budget."""
+    masks); the training masks count against the budget.  With `target`,
+    the result also holds the seconds (training included) until at least
+    that many distinct schemes had been seen."""
     import torch
 
     nA = (d + 1) * (d + 2) // 2
@@ -429,7 +439,7 @@ def run_search(tri, d, budget, use_net=True, train_n=1 << 24, epochs=1, batch=1 
         rnd += 1
         k = min(per_round, budget - used)
         parents, distinct = rarest_witnesses(hist, archive, n_elite)
-        curve.append((used, distinct))
+        curve.append((used, distinct, round(time.perf_counter() - t0, 4)))
         flips = 1 + rnd % 3
         if use_net:
             np_ = parents.shape[0]
@@ -443,7 +453,12 @@ def run_search(tri, d, budget, use_net=True, train_n=1 << 24, epochs=1, batch=1 
     final = len(hist.read())
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    curve.append((used, final))
+    curve.append((used, final, round(dt, 4)))
+    reach = None
+    if target is not None:
+        hit = [c for c in curve if c[1] >= target]
+        reach = hit[0][2] if hit else None
     return {"method": "learned" if use_net else "ablation (uniform flips)", "evaluations": used,
+            "seconds_to_target": reach,
             "distinct": final, "gpu_seconds": dt, "train_seconds": train_s, "rounds": rnd,
             "curve": curve[:: max(1, len(curve) // 32)] + ([curve[-1]] if len(curve) > 32 else [])}

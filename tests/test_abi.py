@@ -97,7 +97,7 @@ def test_specialized_source_compiles_for_gfx950():
     d = 3
     E = I.standard_triangulation(d)
     src = pw.jit_source(d, E)
-    assert "struct JitEval" in src and src.count("E::vertex3(") == 2 * d * d + 2 * d + 1
+    assert "struct JitEval" in src and src.count("E::vertex3e(") == 2 * d * d + 2 * d + 1
     assert src.count("E::pair(") == 2 * d
     assert pw.jit_compile(d, E) > 0
     with pytest.raises(pw.PatchworkError):
