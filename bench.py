@@ -210,11 +210,39 @@ def bench_learned(args):
     # distinct, seconds since the start, training included)
     for r in res[1:]:
         r["seconds_to_uniform_count"] = r.pop("seconds_to_target")
+    # roofline of the dominant contraction: the 512 x 512 hidden layer of the
+    # forward pass (k_gemm_bf16, 128 x 128 tiles), timed with HIP events on
+    # the stream it runs on
+    rows = 1 << 18
+    net = Lr.MLP(n_in=45, seed=1)
+    H1 = torch.zeros((rows, Lr.HIDDEN), dtype=torch.int16, device="cuda")
+    H2 = torch.empty((rows, Lr.HIDDEN), dtype=torch.int16, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def layer2():
+        Lr.gemm(H1, Lr.HIDDEN, 1, net.W16["W2"], Lr.HIDDEN, 1, rows, Lr.HIDDEN, Lr.HIDDEN, C16=H2,
+                bias=net.P["b2"], relu=True)
+
+    for _ in range(3):
+        layer2()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record(stream)
+    for _ in range(reps):
+        layer2()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    gemm_s = e0.elapsed_time(e1) / 1e3 / reps
+    flops = 2.0 * rows * Lr.HIDDEN * Lr.HIDDEN
     return {
         "metric": "distinct real schemes found per GPU-second at d=8",
         "value": res[1]["distinct_per_gpu_second"], "unit": "schemes/s", "n_gpus": 1, "steps": 1, "warmup": 0,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16+u64", "data": "synthetic",
         "config": {"workload": f"d=8 standard triangulation, {budget} judged masks per method", "results": res},
+        "roofline": {"bound": "mfma", "achieved": flops / gemm_s / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": flops / gemm_s / 2.5e15, "traffic": None,
+                     "kernel": "pw::k_gemm_bf16<128,128> (hidden layer 512x512, forward, 2^18 rows)",
+                     "avg_launch_ms": gemm_s * 1e3},
     }
 
 

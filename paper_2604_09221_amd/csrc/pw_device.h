@@ -461,17 +461,22 @@ struct Eval {
       }
     }
     for (int x = 0; x < nR; ++x) store_adj(L, x, (Adj)0);
+    Adj inner = 0;  // regions with at least one child
     for (int x = 0; x < nR; ++x) {
       const int px = par(L, x);
-      if (px != 0xFF) store_adj(L, px, load_adj(L, px) | one(x));
+      if (px != 0xFF) {
+        store_adj(L, px, load_adj(L, px) | one(x));
+        inner |= one(px);
+      }
     }
-    // Bottom-up order: the regions off the path by decreasing id (all their
+    // Bottom-up order over the regions with children (a leaf is '10' and
+    // needs no work): those off the path by decreasing id (all their
     // children have larger ids), then the path from region 0 up to the root
     // (the children of a path region are off the path or the path region
     // done just before it).
     constexpr int AB = 8 * (int)sizeof(Adj);
-    Adj todo = (nR >= AB ? ~(Adj)0 : (one(nR) - 1)) & ~path;
-    Adj leaves = 0;
+    const Adj leaves = (nR >= AB ? ~(Adj)0 : (one(nR) - 1)) & ~inner;
+    Adj todo = inner & ~path;
     int last = 0xFF;  // the path region done last
     for (int it = 0; it <= C::RMAX; ++it) {
       int y;
@@ -482,11 +487,8 @@ struct Eval {
         y = last == 0xFF ? 0 : par(L, last);
         last = y;
       }
+      if ((leaves & one(y)) && y != root) continue;  // a leaf on the path
       const Adj kids = load_adj(L, y);
-      if (kids == 0 && y != root) {
-        leaves |= one(y);
-        continue;
-      }
       Adj rest = kids & ~leaves;
       const int nleaf = popc_t(kids & leaves);
       Code acc = 0;
