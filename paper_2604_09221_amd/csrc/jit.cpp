@@ -42,10 +42,13 @@ int lattice_bit(const HostProgram& P, int v) { return (int)(P.words[v] & 0x7F); 
 constexpr int kAhead = 4;  // phase 3 reads entries this many vertices ahead
 
 // phases 2 and 3 and the call of phase 4, common to both evaluators
-void emit_tail(std::ostringstream& o, const HostProgram& P) {
+// skip_pair(t): the pair is already merged (the sweep kernel's snapshot)
+template <class Skip>
+void emit_tail(std::ostringstream& o, const HostProgram& P, Skip skip_pair) {
   const int nV = P.nV, nE = P.nE, nP = P.nP;
   o << "    // phase 2: antipodal pairs\n";
   for (int t = 0; t < nP; ++t) {
+    if (skip_pair(t)) continue;
     const uint32_t pr = P.words[nV + nE + t];
     o << "    E::pair(L, " << (pr & 0xFFFF) << ", " << (pr >> 16) << ");\n";
   }
@@ -90,7 +93,7 @@ std::string jit_source(const HostProgram& P) {
     }
     o << " E::close(L, " << v << ", r" << v << "); }\n";
   }
-  emit_tail(o, P);
+  emit_tail(o, P, [](int) { return false; });
   o << "  }\n};\n\n";
   if (snapshot_applies(P)) {
     // vertices whose sign varies inside a chunk, and the full adjacency
@@ -123,6 +126,19 @@ std::string jit_source(const HostProgram& P) {
       }
       o << " E::close(L, " << v << ", r" << v << "); }\n";
     }
+    // For odd d the antipodal identification is a plain union (no parity),
+    // and the regions do not depend on the order of unions: the pairs of
+    // fixed-sign vertices are merged here, once per chunk.
+    const int nE = P.nE;
+    auto fixed_pair = [&](int t) {
+      const uint32_t pr = P.words[nV + nE + t];
+      return (d % 2 == 1) && !vary[pr & 0xFFFF] && !vary[pr >> 16];
+    };
+    for (int t = 0; t < P.nP; ++t)
+      if (fixed_pair(t)) {
+        const uint32_t pr = P.words[nV + nE + t];
+        o << "    E::pair(L, " << (pr & 0xFFFF) << ", " << (pr >> 16) << ");\n";
+      }
     o << "    if (lane == 0) {\n";
     for (int v = 0; v < nV; ++v)
       if (!vary[v]) o << "      snap[" << v << "] = (uint8_t)E::root(L, " << v << "u);\n";
@@ -155,7 +171,7 @@ std::string jit_source(const HostProgram& P) {
       }
       o << " }\n";
     }
-    emit_tail(o, P);
+    emit_tail(o, P, fixed_pair);
     o << "  }\n};\n\n";
   }
   o << "}  // namespace pw\n\n";
