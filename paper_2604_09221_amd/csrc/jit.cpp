@@ -139,20 +139,31 @@ std::string jit_source(const HostProgram& P) {
         const uint32_t pr = P.words[nV + nE + t];
         o << "    E::pair(L, " << (pr & 0xFFFF) << ", " << (pr >> 16) << ");\n";
       }
-    o << "    if (lane == 0) {\n";
-    for (int v = 0; v < nV; ++v)
-      if (!vary[v]) o << "      snap[" << v << "] = (uint8_t)E::root(L, " << v << "u);\n";
-    o << "    }\n  }\n";
+    // Every lane holds the same union-find of the fixed-sign part: lane l
+    // writes the row entries l, l + 64, ...; a varying vertex (and the
+    // padding after vertex NV-1) gets its own index, its entry before its
+    // edges are added.
+    o << "    E::Ent* row = reinterpret_cast<E::Ent*>(snap);\n";
+    o << "    constexpr int kRow = Cfg<" << d << ">::SNAP_WORDS * 4 / Cfg<" << d << ">::EB;\n";
+    for (int k = 0; k * 64 < nV; ++k) {
+      uint64_t fixed = 0;
+      for (int j = 0; j < 64 && 64 * k + j < nV; ++j)
+        if (!vary[64 * k + j]) fixed |= 1ull << j;
+      o << "    { const int v = lane + " << 64 * k << "; if (v < kRow) row[v] = (E::Ent)(((0x" << std::hex << fixed
+        << std::dec << "ull >> lane) & 1) ? E::root(L, (uint32_t)v) : (uint32_t)v); }\n";
+    }
+    o << "  }\n";
     o << "  // one batch: restore, the edges of the varying vertices, then as usual\n";
     o << "  __device__ __forceinline__ u128 batch(Cfg<" << d
       << ">::Mask m, const Lane& L, const uint8_t* snap, uint32_t& errs) const {\n";
-    // (a compiler barrier every 8 entries keeps the row loads from all
-    // being hoisted at once, which would need a register each)
-    for (int v = 0; v < nV; ++v) {
-      o << "    E::ent(L, " << v << ") = (E::Ent)" << (vary[v] ? std::to_string(v) + "u" : "snap[" + std::to_string(v) + "]")
-        << ";\n";
-      if (v % 8 == 7) o << "    PW_FENCE();\n";
-    }
+    // the restore: the row, a word at a time (a compiler barrier every 8
+    // words keeps the loads from all being hoisted at once, which would
+    // need a register each)
+    o << "    {\n      const uint32_t* s = reinterpret_cast<const uint32_t*>(__builtin_assume_aligned(snap, 16));\n"
+         "      uint32_t* e = reinterpret_cast<uint32_t*>(L.e);\n"
+         "#pragma unroll\n      for (int k = 0; k < Cfg<"
+      << d << ">::SNAP_WORDS; ++k) {\n        e[k] = s[k];\n        if (k % 8 == 7) PW_FENCE();\n      }\n    }\n";
+    o << "    const E::Ent* srow = reinterpret_cast<const E::Ent*>(snap);\n";
     o << "    // phase 1 for the varying vertices (in index order; each with all\n"
          "    // its fixed-sign neighbours and its earlier varying ones)\n";
     for (int v = 0; v < nV; ++v) {
@@ -165,7 +176,7 @@ std::string jit_source(const HostProgram& P) {
         if (vary[u]) {
           o << " E::edge_v(L, sv, " << sign_expr(P, u) << ", " << v << ", r" << v << ", r" << u << ");";
         } else {
-          o << " { uint32_t t = snap[" << u << "]; E::edge_v(L, sv, " << sign_expr(P, u) << ", " << v << ", r" << v
+          o << " { uint32_t t = srow[" << u << "]; E::edge_v(L, sv, " << sign_expr(P, u) << ", " << v << ", r" << v
             << ", t); }";
         }
       }

@@ -103,16 +103,17 @@ struct Cfg {
   static constexpr bool NARROW = !EVEN && NV <= 128;
   using Ent = typename cond<NARROW, uint8_t, uint16_t>::type;
   static constexpr int EB = NARROW ? 1 : 2;
-  static constexpr int ESTRIDE = 64 * EB;  // bytes between entries v and v + 1 of a lane
   // a stored region code has 2 * (subtree size) <= 2 * (RMAX - 1) bits
   static constexpr int CODE_W = 2 * (RMAX - 1) <= 32 ? 1 : (int)(sizeof(Code) / 4);
   // per-lane LDS words:
-  //   [0, E_WORDS)            vertex entries (phases 1-3) and a spare row
+  //   [0, E_WORDS)            vertex entries (phases 1-3) and a spare entry
+  //                           (index NV); an odd number of words, so that
+  //                           the lanes' entry rows start in distinct banks
   //   [PAR_BASE, +PAR_WORDS)  parent region of every region, one byte row
   //                           of the wave per region (phases 3-4)
   // after phase 3 the entry words hold, per region: child mask (ADJ_W
   // words) and code (CODE_W words).
-  static constexpr int E_WORDS = ((NV + 1) * EB + 3) / 4;  // + a spare entry row (index NV)
+  static constexpr int E_WORDS = (((NV + 1) * EB + 3) / 4) | 1;
   static constexpr int CHILD_BASE = 0;
   static constexpr int CODE_BASE = RMAX * ADJ_W;
   static constexpr int TAIL_WORDS = CODE_BASE + RMAX * CODE_W;
@@ -125,7 +126,10 @@ struct Cfg {
   // dynamic area (DYN_WORDS per lane)
   static constexpr int PAR_ROWS = RMAX + 1;
   static constexpr int DYN_WORDS = LOW_WORDS;
-  static constexpr int SNAP_BYTES = (NV + 3) / 4 * 4;  // snapshot row of the sweep kernel
+  // snapshot row of the sweep kernel: the entries of vertices 0 .. NV-1
+  // (SNAP_WORDS words, copied word by word), padded to 16 bytes
+  static constexpr int SNAP_WORDS = (NV * EB + 3) / 4;
+  static constexpr int SNAP_BYTES = (SNAP_WORDS * 4 + 15) / 16 * 16;
   static constexpr int WAVE_BYTES = LANE_WORDS * 4 * 64;
   // waves per block: as many waves per CU as the 160 KiB of LDS allows,
   // in blocks of at most 4 waves
@@ -140,16 +144,19 @@ struct Cfg {
 
 // ------------------------------------------------------------ lane memory
 
-// Vertex entries sit at byte v * ESTRIDE + EB * lane of the wave's area
-// (EB = 1 or 2 bytes per entry) and hold the index of the vertex's
-// union-find parent (phases 1-2; for even d also the parity to the parent
-// and, at a root, the odd-cycle flag), then its region id (phase 3).  Signs
-// are not stored: the sign of a vertex is a fixed bit of the mask.  Word k
-// of a lane (region data, reused entry space) sits at byte k * 256 + 4 *
-// lane, and byte row x (the parent table) at byte x * 64 + lane.  For uniform v every lane hits its own bank; for divergent parents
-// a few lanes may share one.  Entry bytes of one lane overlap words of
-// others: phase 4 writes words only after every lane of the wave has
-// finished phase 3, which the wave's lockstep execution and program order
+// Vertex entries of a lane form one row: entry v at byte lane * 4 * E_WORDS
+// + EB * v of the wave's area (EB = 1 or 2 bytes per entry).  An entry
+// holds the index of the vertex's union-find parent (phases 1-2; for even d
+// also the parity to the parent and, at a root, the odd-cycle flag), then
+// its region id (phase 3).  Signs are not stored: the sign of a vertex is a
+// fixed bit of the mask.  E_WORDS is odd, so for a uniform v the 64 lanes
+// touch 64 distinct banks; divergent parent pointers may share a few.  A
+// row is contiguous, so it can be copied a word at a time (the sweep
+// kernel's restore).  Word k of a lane (region data, reused entry space)
+// sits at byte k * 256 + 4 * lane, and byte row x (the parent table) at
+// byte x * 64 + lane.  Entry bytes of one lane overlap words of others:
+// phase 4 writes words only after every lane of the wave has finished
+// phase 3, which the wave's lockstep execution and program order
 // guarantee.
 struct Lane {
   uint32_t* w;  // word 0 of this lane; word k at w[k * 64]
@@ -206,7 +213,7 @@ struct Eval {
 
   // ---- entries
   __device__ static __forceinline__ Ent& ent(const Lane& L, int v) {
-    return *reinterpret_cast<Ent*>(L.e + v * C::ESTRIDE);
+    return *reinterpret_cast<Ent*>(L.e + v * C::EB);
   }
   // end of phase 1 for v: its root so far
   __device__ static __forceinline__ void close(const Lane& L, int v, uint32_t rv) { ent(L, v) = (Ent)rv; }
@@ -752,7 +759,7 @@ __device__ __forceinline__ Lane lane_memory(uint32_t* smem, int lane_words) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t* base = smem + wave * lane_words * 64;
   char* cb = reinterpret_cast<char*>(base);
-  return Lane{base + lane, cb + C::EB * lane, cb + C::PAR_BASE * 256 + lane};
+  return Lane{base + lane, cb + 4 * C::E_WORDS * lane, cb + C::PAR_BASE * 256 + lane};
 }
 
 // the same with the parent table in its own __shared__ array (par: PAR_ROWS
@@ -763,7 +770,7 @@ __device__ __forceinline__ Lane lane_memory_split(uint32_t* smem, uint8_t* par) 
   using C = Cfg<D>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t* base = smem + wave * C::DYN_WORDS * 64;
-  return Lane{base + lane, reinterpret_cast<char*>(base) + C::EB * lane,
+  return Lane{base + lane, reinterpret_cast<char*>(base) + 4 * C::E_WORDS * lane,
               reinterpret_cast<char*>(par) + wave * C::PAR_ROWS * 64 + lane};
 }
 
@@ -844,8 +851,9 @@ __device__ __forceinline__ void enum_body(const EV& ev, uint64_t first, uint64_t
 // chunk of 64 << kSnapBits consecutive indices, so inside a chunk only the
 // signs of the lattice points those bits map to vary.  ev.snapshot()
 // computes, once per chunk, the union-find of the edges between vertices
-// whose signs are fixed in the chunk and stores each such vertex's root in
-// the wave's snapshot row; ev.batch() restores the lane's entries from it,
+// whose signs are fixed in the chunk (every lane computes the same one)
+// and writes the wave's snapshot row: each such vertex's root, each varying
+// vertex's own index; ev.batch() copies the row into the lane's entries,
 // adds the edges of the varying vertices and finishes as usual.
 constexpr int kSnapBits = 3;
 
@@ -856,7 +864,7 @@ __device__ __forceinline__ void enum_snap_body(const EV& ev, uint64_t first, uin
   constexpr uint64_t CS = 64ull << kSnapBits;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   __shared__ uint8_t par_rows[C::WAVES * C::PAR_ROWS * 64];
-  __shared__ uint8_t snap_rows[C::WAVES * C::SNAP_BYTES];
+  __shared__ __attribute__((aligned(16))) uint8_t snap_rows[C::WAVES * C::SNAP_BYTES];
   const Lane L = lane_memory_split<D>(smem, par_rows);
   uint8_t* snap = snap_rows + wave * C::SNAP_BYTES;
   WaveTable tab;

@@ -28,48 +28,68 @@ MAIN = r'''
 Dim3E threadIdx{0, 0, 0}, blockIdx{0, 0, 0}, blockDim{64, 1, 1}, gridDim{1, 1, 1};
 #include <cstring>
 #include <vector>
+using C = pw::Cfg<DEG>;
+static const size_t kBytes = (size_t)C::LANE_WORDS * 64 * 4;
+// the bytes of the wave's area that a lane may write: its entry row (the
+// entries, the spare entry and the padding), its words and its
+// parent-table bytes
+static void own_bytes(int lane, std::vector<unsigned char>& own) {
+  memset(own.data(), 0, kBytes);
+  for (int k = 0; k < C::LOW_WORDS; ++k)
+    for (int b = 0; b < 4; ++b) own[k * 256 + 4 * lane + b] = 1;
+  for (int b = 0; b < 4 * C::E_WORDS; ++b) own[lane * 4 * C::E_WORDS + b] = 1;
+  for (int x = 0; x < 4 * C::PAR_WORDS; ++x) own[C::PAR_BASE * 256 + x * 64 + lane] = 1;
+}
+static bool foreign_write(const std::vector<unsigned char>& own, const std::vector<unsigned char>& before,
+                          const uint32_t* smem) {
+  const unsigned char* cur = (const unsigned char*)smem;
+  for (size_t b = 0; b < kBytes; ++b)
+    if (!own[b] && cur[b] != before[b]) return true;
+  return false;
+}
 int main(int argc, char** argv) {
-  using C = pw::Cfg<DEG>;
   const long n = atol(argv[1]);
   std::vector<uint64_t> in(2 * n), out(2 * n);
   if (fread(in.data(), 8, 2 * n, stdin) != (size_t)(2 * n)) return 3;
-  const size_t bytes = (size_t)C::LANE_WORDS * 64 * 4;
-  uint32_t* smem = (uint32_t*)malloc(bytes);
-  memset(smem, 0xAB, bytes);
-  std::vector<unsigned char> snap(bytes), own(bytes);
+  uint32_t* smem = (uint32_t*)aligned_alloc(16, kBytes);
+  memset(smem, 0xAB, kBytes);
+  std::vector<unsigned char> before(kBytes), own(kBytes);
   long foreign = 0;
   for (long i = 0; i < n; ++i) {
     const int lane = (int)(i % 64);
-    threadIdx.x = lane;
-    const pw::Lane L = pw::lane_memory<DEG>(smem, C::LANE_WORDS);
-    memset(own.data(), 0, bytes);
-    for (int k = 0; k < C::LOW_WORDS; ++k)
-      for (int b = 0; b < 4; ++b) own[k * 256 + 4 * lane + b] = 1;
-    for (int v = 0; v <= C::NV; ++v)  // entries and the spare row
-      for (int b = 0; b < C::EB; ++b) own[v * C::ESTRIDE + C::EB * lane + b] = 1;
-    for (int x = 0; x < 4 * C::PAR_WORDS; ++x) own[C::PAR_BASE * 256 + x * 64 + lane] = 1;
-    memcpy(snap.data(), smem, bytes);
     typename C::Mask m = (typename C::Mask)in[2 * i];
     if (sizeof(m) == 16) m |= (typename C::Mask)((pw::u128)in[2 * i + 1] << 64);
     uint32_t errs = 0;
 #ifdef SNAP
-    // the sweep kernel's evaluator: snapshot of the fixed-sign part taken
-    // from another mask that differs from m only in the varying bits 1..9
+    // the sweep kernel's evaluator: every lane of the wave takes the
+    // snapshot of the fixed-sign part from its own mask, which differs
+    // from m only in the varying bits 1..9
     typename C::Mask m1 = m ^ (typename C::Mask)((((uint64_t)i * 0x9E3779B97F4A7C15ull) >> 40) & 0x3FEull);
-    static uint8_t srow[C::SNAP_BYTES];
-    pw::JitSnap{}.snapshot(m1, L, srow, 0);
+    alignas(16) static uint8_t srow[C::SNAP_BYTES];
+    for (int j = 0; j < 64; ++j) {
+      threadIdx.x = j;
+      const pw::Lane Lj = pw::lane_memory<DEG>(smem, C::LANE_WORDS);
+      const bool check = i < 2;
+      if (check) {
+        own_bytes(j, own);
+        memcpy(before.data(), smem, kBytes);
+      }
+      pw::JitSnap{}.snapshot((m1 & ~(typename C::Mask)0x7E) | (typename C::Mask)(j << 1), Lj, srow, j);
+      if (check && foreign_write(own, before, smem)) ++foreign;
+    }
+#endif
+    threadIdx.x = lane;
+    const pw::Lane L = pw::lane_memory<DEG>(smem, C::LANE_WORDS);
+    own_bytes(lane, own);
+    memcpy(before.data(), smem, kBytes);
+#ifdef SNAP
     const pw::u128 code = pw::JitSnap{}.batch(m, L, srow, errs);
 #else
     const pw::u128 code = pw::JitEval{}(m, L, errs);
 #endif
     out[2 * i] = errs ? 0 : (uint64_t)code;
     out[2 * i + 1] = errs ? 0 : (uint64_t)(code >> 64);
-    const unsigned char* cur = (const unsigned char*)smem;
-    for (size_t b = 0; b < bytes; ++b)
-      if (!own[b] && cur[b] != snap[b]) {
-        ++foreign;
-        break;
-      }
+    if (foreign_write(own, before, smem)) ++foreign;
   }
   fwrite(out.data(), 8, 2 * n, stdout);
   free(smem);
