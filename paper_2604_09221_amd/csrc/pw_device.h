@@ -4,16 +4,18 @@
 // in-kernel mask generator and the two-level code histogram.
 //
 // LDS layout: each wave owns LANE_WORDS * 64 dwords.  Word k of lane l sits
-// at dword k * 64 + l (every lane in its own bank whatever the index) and
-// vertex entry v (u16) at byte v * 128 + 2 l (its own bank for a uniform v,
-// at most two lanes per bank for divergent parent pointers).
+// at dword k * 64 + l (every lane in its own bank whatever the index); the
+// vertex entries of lane l form one contiguous row of E_WORDS (odd) dwords
+// starting at dword l * E_WORDS (its own bank for a uniform vertex).  The
+// parent table of phases 3-4 is one byte row per region.
 //
 // Per mask (thread) the phases are:
 //   1 components  (Alg. 1 "compute connected components of same-sign
 //     vertices"): vertices in program order; each earlier neighbour with
-//     the same sign is unioned.  Entry of v (u16): parent << 7 (the byte
-//     offset of the parent's entry), odd-cycle flag (roots), parity to the
-//     parent, sign.
+//     the same sign is unioned.  Entry of v: the index of its union-find
+//     parent (u8 for odd d <= 7; u16 otherwise, with the parity to the
+//     parent and, at a root, the odd-cycle flag for even d).  Signs are
+//     bits of the mask and are not stored.
 //     Links always go from the larger root to the smaller one, so every
 //     parent index is smaller than its child's.
 //   2 regions (Alg. 1 "coarsen into regions by identifying antipodal
