@@ -102,7 +102,8 @@ __global__ __launch_bounds__(256) void k_multi(const TriDesc* __restrict__ tris,
   while (true) {
     unsigned long long tk = 0;
     if (lane == 0) tk = atomicAdd(ticket, 1ull);
-    tk = (unsigned long long)__builtin_amdgcn_readfirstlane((int)(uint32_t)tk) |
+    // (the builtin returns a signed int: both halves are widened as unsigned)
+    tk = (unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)tk) |
          ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(tk >> 32)) << 32);
     const int64_t it = (int64_t)(tk - base);
     if (it >= n_items) break;

@@ -34,7 +34,7 @@ template <class T> static inline T atomicOr(T*, T) { emu_unsupported(); }
 static inline uint64_t __ballot(int) { emu_unsupported(); }
 static inline int emu_readlane(int, int) { emu_unsupported(); }
 #define __builtin_amdgcn_readlane(a, b) emu_readlane(a, b)
-#define __builtin_amdgcn_readfirstlane(a) (a)
+#define __builtin_amdgcn_readfirstlane(a) ((int)(a))  // returns int on the device too
 #define __HIP_MEMORY_SCOPE_AGENT 0
 template <class T> static inline T __hip_atomic_load(T*, int, int) { emu_unsupported(); }
 template <class T> static inline void __hip_atomic_store(T*, T, int, int) { emu_unsupported(); }
