@@ -30,21 +30,34 @@ namespace {
 
 // sign of vertex v as an expression: bit p of the mask, flipped by the
 // reflection parity g
-std::string sign_expr(const HostProgram& P, int v) {
+// (mv: the mask variable; the sweep kernel's per-chunk flags read the
+// signs of vertices that are fixed in a chunk from m0, the wave-uniform
+// copy of the mask)
+std::string sign_expr(const HostProgram& P, int v, const char* mv = "m") {
   const uint32_t rec = P.words[v];
   const int p = rec & 0x7F, g = (rec >> 7) & 1;
-  std::string x = "E::bit(m, " + std::to_string(p) + ")";
+  std::string x = std::string("E::bit(") + mv + ", " + std::to_string(p) + ")";
   return g ? "(" + x + " ^ 1u)" : x;
 }
+
+// the spanning-tree parent t(v) of the region tree: v's first earlier
+// neighbour (-1 for vertex 0)
+int tree_parent(const HostProgram& P, int v) { return v > 0 ? (int)P.words[P.nV + (P.words[v] >> 16)] : -1; }
 
 int lattice_bit(const HostProgram& P, int v) { return (int)(P.words[v] & 0x7F); }
 
 constexpr int kAhead = 4;  // phase 3 reads entries this many vertices ahead
 
 // phases 2 and 3 and the call of phase 4, common to both evaluators
-// skip_pair(t): the pair is already merged (the sweep kernel's snapshot)
+// skip_pair(t): the pair is already merged (the sweep kernel's snapshot);
+// vary: the sweep kernel's varying vertices (null for the plain evaluator).
+// In the sweep kernel a vertex of fixed sign whose snapshot entry points to
+// another vertex stays a non-root (the later unions link roots only) and
+// nobody's parent, so its phase-3 step only copies its parent's region id
+// (vertex3n); the wave-uniform flags fl.fr (snapshot roots) and fl.cr
+// (crossed tree edges between fixed-sign vertices) select the step.
 template <class Skip>
-void emit_tail(std::ostringstream& o, const HostProgram& P, Skip skip_pair) {
+void emit_tail(std::ostringstream& o, const HostProgram& P, Skip skip_pair, const std::vector<char>* vary) {
   const int nV = P.nV, nE = P.nE, nP = P.nP;
   o << "    // phase 2: antipodal pairs\n";
   for (int t = 0; t < nP; ++t) {
@@ -57,10 +70,23 @@ void emit_tail(std::ostringstream& o, const HostProgram& P, Skip skip_pair) {
   o << "    int nR = 0;\n    E::Adj roots = 0;\n";
   for (int v = 0; v < std::min(kAhead, nV); ++v) o << "    const uint32_t e" << v << " = E::ent(L, " << v << ");\n";
   for (int v = 0; v < nV; ++v) {
-    const int t = v > 0 ? (int)P.words[nV + (P.words[v] >> 16)] : -1;
+    const int t = tree_parent(P, v);
     if (v + kAhead < nV) o << "    const uint32_t e" << v + kAhead << " = E::ent(L, " << v + kAhead << ");\n";
-    o << "    E::vertex3e(L, " << v << ", " << t << ", " << sign_expr(P, v) << ", "
-      << (t >= 0 ? sign_expr(P, t) : std::string("0u")) << ", e" << v << ", nR, roots);\n";
+    if (!vary || (*vary)[v]) {
+      o << "    E::vertex3e(L, " << v << ", " << t << ", " << sign_expr(P, v) << ", "
+        << (t >= 0 ? sign_expr(P, t) : std::string("0u")) << ", e" << v << ", nR, roots);\n";
+      continue;
+    }
+    const std::string fr = "((fl.fr[" + std::to_string(v / 64) + "] >> " + std::to_string(v % 64) + ") & 1u)";
+    std::string cr;
+    if (P.d % 2 == 0 || t < 0)
+      cr = "false";
+    else if (!(*vary)[t])
+      cr = "(((fl.cr[" + std::to_string(v / 64) + "] >> " + std::to_string(v % 64) + ") & 1u) != 0)";
+    else
+      cr = "(" + sign_expr(P, v) + " != " + sign_expr(P, t) + ")";
+    o << "    if (" << fr << ") E::vertex3c(L, " << v << ", " << t << ", " << cr << ", e" << v
+      << ", nR, roots); else E::vertex3n(L, " << v << ", " << t << ", " << cr << ", e" << v << ", roots);\n";
   }
   o << "    return E::finish(L, nR, roots, errs);\n";
 }
@@ -93,7 +119,7 @@ std::string jit_source(const HostProgram& P) {
     }
     o << " E::close(L, " << v << ", r" << v << "); }\n";
   }
-  emit_tail(o, P, [](int) { return false; });
+  emit_tail(o, P, [](int) { return false; }, nullptr);
   o << "  }\n};\n\n";
   if (snapshot_applies(P)) {
     // vertices whose sign varies inside a chunk, and the full adjacency
@@ -153,9 +179,33 @@ std::string jit_source(const HostProgram& P) {
         << std::dec << "ull >> lane) & 1) ? E::root(L, (uint32_t)v) : (uint32_t)v); }\n";
     }
     o << "  }\n";
+    // the wave-uniform flags of a chunk, from the snapshot row (entry v
+    // is v: v is a root of the fixed-sign part) and from m0
+    const int nw = (nV + 63) / 64;
+    o << "  struct Flags {\n    uint64_t fr[" << nw << "];  // fixed-sign vertices that are snapshot roots\n"
+      << "    uint64_t cr[" << nw << "];  // fixed-sign vertices whose tree edge (both ends fixed) is crossed\n  };\n";
+    o << "  __device__ __forceinline__ Flags flags(Cfg<" << d << ">::Mask m0, const uint8_t* snap) const {\n";
+    o << "    Flags fl{};\n    const E::Ent* row = reinterpret_cast<const E::Ent*>(snap);\n";
+    for (int v = 0; v < nV; ++v) {
+      if (vary[v]) continue;
+      o << "    fl.fr[" << v / 64 << "] |= (uint64_t)(__builtin_amdgcn_readfirstlane((uint32_t)row[" << v << "]) == " << v
+        << "u) << " << v % 64 << ";\n";
+      const int t = tree_parent(P, v);
+      if (d % 2 == 1 && t >= 0 && !vary[t])
+        o << "    fl.cr[" << v / 64 << "] |= (uint64_t)(" << sign_expr(P, v, "m0") << " ^ " << sign_expr(P, t, "m0")
+          << ") << " << v % 64 << ";\n";
+    }
+    o << "    return fl;\n  }\n";
     o << "  // one batch: restore, the edges of the varying vertices, then as usual\n";
     o << "  __device__ __forceinline__ u128 batch(Cfg<" << d
-      << ">::Mask m, const Lane& L, const uint8_t* snap, uint32_t& errs) const {\n";
+      << ">::Mask m, const Lane& L, const uint8_t* snap, const Flags& fl_chunk, uint32_t& errs) const {\n";
+    // (the flags pass through an opaque copy per batch: tests of single
+    // flag bits hoisted out of the batch loop would each hold a register)
+    o << "    Flags fl;\n";
+    for (int k = 0; k < nw; ++k)
+      o << "    { uint64_t a = fl_chunk.fr[" << k << "], b = fl_chunk.cr[" << k
+        << "]; PW_OPAQUE(a); PW_OPAQUE(b); fl.fr[" << k << "] = uniform_mask(a); fl.cr[" << k
+        << "] = uniform_mask(b); }\n";
     // the restore: the row, a word at a time (a compiler barrier every 8
     // words keeps the loads from all being hoisted at once, which would
     // need a register each)
@@ -182,7 +232,7 @@ std::string jit_source(const HostProgram& P) {
       }
       o << " }\n";
     }
-    emit_tail(o, P, fixed_pair);
+    emit_tail(o, P, fixed_pair, &vary);
     o << "  }\n};\n\n";
   }
   o << "}  // namespace pw\n\n";

@@ -406,6 +406,47 @@ struct Eval {
     ent(L, v) = (Ent)cid;
   }
 
+  // the same with the crossing of the tree edge (v, t) given (odd d)
+  __device__ static __forceinline__ void vertex3c(const Lane& L, int v, int t, bool crossed, uint32_t ev, int& nR,
+                                                  Adj& roots) {
+    const uint32_t p = idx(ev);
+    const bool is_root = p == (uint32_t)v;
+    const uint32_t ep = ent(L, (int)p);  // p < v holds its region id already; a root reads its own entry
+    const uint32_t et = ent(L, t < 0 ? 0 : t);
+    // ids past the Harnack bound share the spare slot RMAX; finish()
+    // rejects such a mask (nR > RMAX) before reading any region data
+    const int cid = is_root ? (nR < C::RMAX ? nR : C::RMAX) : (int)ep;
+    nR += is_root ? 1 : 0;
+    // keep the running count a plain running count (re-associating the
+    // chain of increments would hold every vertex's flag in a register)
+    PW_OPAQUE(nR);
+    const bool hit = C::EVEN ? (is_root && (ev & kOdd)) : (crossed && (int)et == cid);
+    roots |= hit ? one(cid & (8 * (int)sizeof(Adj) - 1)) : (Adj)0;
+    // (a plain running value: between branches the compiler would
+    // otherwise keep every vertex's term until the end)
+    PW_OPAQUE(roots);
+    const uint32_t pc = t >= 0 ? et : 0xFFu;
+    int slot = is_root ? cid : C::RMAX;
+    PW_OPAQUE(slot);
+    set_par(L, slot, (int)pc);
+    ent(L, v) = (Ent)cid;
+  }
+
+  // Phase-3 step of a vertex known to be no root and nobody's parent: it
+  // takes the region id of its parent (already relabelled, the parent being
+  // smaller); for odd d a crossed tree edge (v, t) inside its region marks
+  // the root region as in vertex3c.
+  __device__ static __forceinline__ void vertex3n(const Lane& L, int v, int t, bool crossed, uint32_t ev,
+                                                  Adj& roots) {
+    const uint32_t cid = ent(L, (int)idx(ev));
+    ent(L, v) = (Ent)cid;
+    if constexpr (!C::EVEN) {
+      const uint32_t et = ent(L, t < 0 ? 0 : t);
+      roots |= (crossed && et == cid) ? one((int)cid & (8 * (int)sizeof(Adj) - 1)) : (Adj)0;
+      PW_OPAQUE(roots);
+    }
+  }
+
   __device__ static __forceinline__ uint32_t sign_of(const uint32_t* __restrict__ prog, Mask m, int v) {
     const uint32_t rec = prog[v];
     return bit(m, rec & 0x7F) ^ ((rec >> 7) & 1u);
@@ -859,6 +900,15 @@ __device__ __forceinline__ void enum_body(const EV& ev, uint64_t first, uint64_t
 // adds the edges of the varying vertices and finishes as usual.
 constexpr int kSnapBits = 3;
 
+// the mask of the wave's first active lane: for the bits that are equal in
+// every lane (the fixed signs of a chunk) a value the compiler keeps in
+// scalar registers
+// (the builtin returns a signed int: each half is widened as unsigned)
+__device__ __forceinline__ uint64_t uniform_mask(uint64_t m) {
+  return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(m >> 32)) << 32) |
+         (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)m);
+}
+
 template <int D, class EV>
 __device__ __forceinline__ void enum_snap_body(const EV& ev, uint64_t first, uint64_t count, const Runs& runs,
                                                const HistDev* h, uint32_t* __restrict__ errflag, uint32_t* smem) {
@@ -876,12 +926,14 @@ __device__ __forceinline__ void enum_snap_body(const EV& ev, uint64_t first, uin
   const uint64_t c1 = (first + count - 1) / CS;
   for (uint64_t c = first / CS + (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave; c <= c1; c += waves_total) {
     const uint64_t cbase = c * CS;
-    ev.snapshot(deposit<typename C::Mask>(cbase + (uint64_t)lane, runs), L, snap, lane);
+    const typename C::Mask mc = deposit<typename C::Mask>(cbase + (uint64_t)lane, runs);
+    ev.snapshot(mc, L, snap, lane);
     __builtin_amdgcn_wave_barrier();
+    const auto fl = ev.flags(uniform_mask(mc), snap);
     for (int b = 0; b < (1 << kSnapBits); ++b) {
       const uint64_t idx = cbase + (uint64_t)(b * 64 + lane);
       const bool valid = idx >= first && idx - first < count;
-      const u128 code = ev.batch(deposit<typename C::Mask>(idx, runs), L, snap, errs);
+      const u128 code = ev.batch(deposit<typename C::Mask>(idx, runs), L, snap, fl, errs);
       tab.add_batch((uint64_t)code, (uint64_t)(code >> 64), valid, idx, lane, h);
     }
     __builtin_amdgcn_wave_barrier();

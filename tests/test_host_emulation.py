@@ -83,7 +83,8 @@ int main(int argc, char** argv) {
     own_bytes(lane, own);
     memcpy(before.data(), smem, kBytes);
 #ifdef SNAP
-    const pw::u128 code = pw::JitSnap{}.batch(m, L, srow, errs);
+    const auto fl = pw::JitSnap{}.flags(m1, srow);
+    const pw::u128 code = pw::JitSnap{}.batch(m, L, srow, fl, errs);
 #else
     const pw::u128 code = pw::JitEval{}(m, L, errs);
 #endif
