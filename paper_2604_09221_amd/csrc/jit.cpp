@@ -51,11 +51,6 @@ constexpr int kAhead = 4;  // phase 3 reads entries this many vertices ahead
 // phases 2 and 3 and the call of phase 4, common to both evaluators
 // skip_pair(t): the pair is already merged (the sweep kernel's snapshot);
 // vary: the sweep kernel's varying vertices (null for the plain evaluator).
-// In the sweep kernel a vertex of fixed sign whose snapshot entry points to
-// another vertex stays a non-root (the later unions link roots only) and
-// nobody's parent, so its phase-3 step only copies its parent's region id
-// (vertex3n); the wave-uniform flags fl.fr (snapshot roots) and fl.cr
-// (crossed tree edges between fixed-sign vertices) select the step.
 template <class Skip>
 void emit_tail(std::ostringstream& o, const HostProgram& P, Skip skip_pair, const std::vector<char>* vary) {
   const int nV = P.nV, nE = P.nE, nP = P.nP;
@@ -69,24 +64,58 @@ void emit_tail(std::ostringstream& o, const HostProgram& P, Skip skip_pair, cons
        "    // " << kAhead << " vertices ahead)\n";
   o << "    int nR = 0;\n    E::Adj roots = 0;\n";
   for (int v = 0; v < std::min(kAhead, nV); ++v) o << "    const uint32_t e" << v << " = E::ent(L, " << v << ");\n";
+  if (!vary) {
+    for (int v = 0; v < nV; ++v) {
+      const int t = tree_parent(P, v);
+      if (v + kAhead < nV) o << "    const uint32_t e" << v + kAhead << " = E::ent(L, " << v + kAhead << ");\n";
+      o << "    E::vertex3e(L, " << v << ", " << t << ", " << sign_expr(P, v) << ", "
+        << (t >= 0 ? sign_expr(P, t) : std::string("0u")) << ", e" << v << ", nR, roots);\n";
+    }
+    o << "    return E::finish(L, nR, roots, errs);\n";
+    return;
+  }
+  // The sweep kernel.  A vertex of fixed sign whose snapshot entry points
+  // to another vertex stays a non-root (the later unions link roots only)
+  // and is nobody's parent; its region is that of its snapshot root
+  // srow[v].  So region ids are assigned walking only the varying vertices
+  // and the snapshot roots (wave-uniform flags fl.fr) in vertex order, a
+  // tree parent's region read through its snapshot root; the crossed tree
+  // edges of the other vertices (fl.cr: both ends fixed; else per lane) are
+  // tested afterwards, with no stores between their loads.
+  const bool odd = P.d % 2 == 1;
+  auto bitflag = [](const char* w, int v) {
+    return std::string("((fl.") + w + "[" + std::to_string(v / 64) + "] >> " + std::to_string(v % 64) + ") & 1u)";
+  };
+  auto crossed = [&](int v, int t) -> std::string {
+    if (!odd || t < 0) return "false";
+    if (!(*vary)[v] && !(*vary)[t]) return "(" + bitflag("cr", v) + " != 0u)";
+    return "(" + sign_expr(P, v) + " != " + sign_expr(P, t) + ")";
+  };
+  auto region_of = [&](int x) -> std::string {  // a vertex whose region id is already assigned
+    return (*vary)[x] ? std::to_string(x) : "(int)srow[" + std::to_string(x) + "]";
+  };
   for (int v = 0; v < nV; ++v) {
     const int t = tree_parent(P, v);
     if (v + kAhead < nV) o << "    const uint32_t e" << v + kAhead << " = E::ent(L, " << v + kAhead << ");\n";
-    if (!vary || (*vary)[v]) {
-      o << "    E::vertex3e(L, " << v << ", " << t << ", " << sign_expr(P, v) << ", "
-        << (t >= 0 ? sign_expr(P, t) : std::string("0u")) << ", e" << v << ", nR, roots);\n";
-      continue;
-    }
-    const std::string fr = "((fl.fr[" + std::to_string(v / 64) + "] >> " + std::to_string(v % 64) + ") & 1u)";
-    std::string cr;
-    if (P.d % 2 == 0 || t < 0)
-      cr = "false";
-    else if (!(*vary)[t])
-      cr = "(((fl.cr[" + std::to_string(v / 64) + "] >> " + std::to_string(v % 64) + ") & 1u) != 0)";
+    const std::string step = "E::vertex3c(L, " + std::to_string(v) + ", " + (t >= 0 ? region_of(t) : "-1") + ", " +
+                             crossed(v, t) + ", e" + std::to_string(v) + ", nR, roots);";
+    if ((*vary)[v])
+      o << "    " << step << "\n";
     else
-      cr = "(" + sign_expr(P, v) + " != " + sign_expr(P, t) + ")";
-    o << "    if (" << fr << ") E::vertex3c(L, " << v << ", " << t << ", " << cr << ", e" << v
-      << ", nR, roots); else E::vertex3n(L, " << v << ", " << t << ", " << cr << ", e" << v << ", roots);\n";
+      o << "    if (" << bitflag("fr", v) << ") " << step << "\n";
+  }
+  if (odd) {
+    o << "    // crossed tree edges of the fixed-sign non-roots\n";
+    for (int v = 0; v < nV; ++v) {
+      const int t = tree_parent(P, v);
+      if ((*vary)[v] || t < 0) continue;
+      if (!(*vary)[t])
+        o << "    if (((fl.cr[" << v / 64 << "] & ~fl.fr[" << v / 64 << "]) >> " << v % 64 << ") & 1u) E::hit(L, srow["
+          << v << "], srow[" << t << "], true, roots);\n";
+      else
+        o << "    if (!" << bitflag("fr", v) << ") E::hit(L, srow[" << v << "], " << t << ", " << crossed(v, t)
+          << ", roots);\n";
+    }
   }
   o << "    return E::finish(L, nR, roots, errs);\n";
 }

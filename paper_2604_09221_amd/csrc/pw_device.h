@@ -406,7 +406,8 @@ struct Eval {
     ent(L, v) = (Ent)cid;
   }
 
-  // the same with the crossing of the tree edge (v, t) given (odd d)
+  // the same with the crossing of the tree edge (v, t) given (odd d); t may
+  // also be any vertex of t's region whose id is assigned already
   __device__ static __forceinline__ void vertex3c(const Lane& L, int v, int t, bool crossed, uint32_t ev, int& nR,
                                                   Adj& roots) {
     const uint32_t p = idx(ev);
@@ -432,19 +433,13 @@ struct Eval {
     ent(L, v) = (Ent)cid;
   }
 
-  // Phase-3 step of a vertex known to be no root and nobody's parent: it
-  // takes the region id of its parent (already relabelled, the parent being
-  // smaller); for odd d a crossed tree edge (v, t) inside its region marks
-  // the root region as in vertex3c.
-  __device__ static __forceinline__ void vertex3n(const Lane& L, int v, int t, bool crossed, uint32_t ev,
-                                                  Adj& roots) {
-    const uint32_t cid = ent(L, (int)idx(ev));
-    ent(L, v) = (Ent)cid;
-    if constexpr (!C::EVEN) {
-      const uint32_t et = ent(L, t < 0 ? 0 : t);
-      roots |= (crossed && et == cid) ? one((int)cid & (8 * (int)sizeof(Adj) - 1)) : (Adj)0;
-      PW_OPAQUE(roots);
-    }
+  // A crossed tree edge between vertices a and b (odd d; their regions
+  // already assigned) inside one region marks it as the root region, as in
+  // vertex3c.
+  __device__ static __forceinline__ void hit(const Lane& L, int a, int b, bool crossed, Adj& roots) {
+    const uint32_t ra = ent(L, a), rb = ent(L, b);
+    roots |= (crossed && ra == rb) ? one((int)ra & (8 * (int)sizeof(Adj) - 1)) : (Adj)0;
+    PW_OPAQUE(roots);
   }
 
   __device__ static __forceinline__ uint32_t sign_of(const uint32_t* __restrict__ prog, Mask m, int v) {
