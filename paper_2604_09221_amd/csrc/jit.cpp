@@ -208,17 +208,49 @@ std::string jit_source(const HostProgram& P) {
         << std::dec << "ull >> lane) & 1) ? E::root(L, (uint32_t)v) : (uint32_t)v); }\n";
     }
     o << "  }\n";
+    // The edges of phase 1 between a varying vertex and a fixed-sign
+    // neighbour, in the order the batch adds them; such an edge is a
+    // duplicate when an earlier fixed-sign neighbour of the same vertex has
+    // the same snapshot root and the same sign (for odd d the antipodal
+    // pairs merged in the snapshot may join vertices of both signs): its
+    // union changes nothing.
+    std::vector<std::vector<int>> earlier_fixed;  // per edge: the earlier fixed neighbours
+    std::vector<int> edge_u;
+    for (int v = 0; v < nV; ++v) {
+      if (!vary[v]) continue;
+      std::vector<int> nb = adj[v];
+      std::sort(nb.begin(), nb.end());
+      std::vector<int> seen;
+      for (int u : nb) {
+        if (vary[u]) continue;
+        earlier_fixed.push_back(seen);
+        edge_u.push_back(u);
+        seen.push_back(u);
+      }
+    }
+    const int n_fixed_edges = (int)edge_u.size();
+    const int nd = std::max(1, (n_fixed_edges + 63) / 64);
     // the wave-uniform flags of a chunk, from the snapshot row (entry v
     // is v: v is a root of the fixed-sign part) and from m0
     const int nw = (nV + 63) / 64;
     o << "  struct Flags {\n    uint64_t fr[" << nw << "];  // fixed-sign vertices that are snapshot roots\n"
-      << "    uint64_t cr[" << nw << "];  // fixed-sign vertices whose tree edge (both ends fixed) is crossed\n  };\n";
+      << "    uint64_t cr[" << nw << "];  // fixed-sign vertices whose tree edge (both ends fixed) is crossed\n"
+      << "    uint64_t dp[" << nd << "];  // duplicate phase-1 edges to fixed-sign neighbours\n  };\n";
     o << "  __device__ __forceinline__ Flags flags(Cfg<" << d << ">::Mask m0, const uint8_t* snap) const {\n";
     o << "    Flags fl{};\n    const E::Ent* row = reinterpret_cast<const E::Ent*>(snap);\n";
+    for (int v = 0; v < nV; ++v)
+      if (!vary[v]) o << "    const uint32_t w" << v << " = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)row[" << v << "]);\n";
+    for (int e = 0; e < n_fixed_edges; ++e) {
+      if (earlier_fixed[e].empty()) continue;
+      o << "    fl.dp[" << e / 64 << "] |= (uint64_t)(";
+      for (size_t k = 0; k < earlier_fixed[e].size(); ++k)
+        o << (k ? " || " : "") << "(w" << edge_u[e] << " == w" << earlier_fixed[e][k] << " && "
+          << sign_expr(P, edge_u[e], "m0") << " == " << sign_expr(P, earlier_fixed[e][k], "m0") << ")";
+      o << ") << " << e % 64 << ";\n";
+    }
     for (int v = 0; v < nV; ++v) {
       if (vary[v]) continue;
-      o << "    fl.fr[" << v / 64 << "] |= (uint64_t)(__builtin_amdgcn_readfirstlane((uint32_t)row[" << v << "]) == " << v
-        << "u) << " << v % 64 << ";\n";
+      o << "    fl.fr[" << v / 64 << "] |= (uint64_t)(w" << v << " == " << v << "u) << " << v % 64 << ";\n";
       const int t = tree_parent(P, v);
       if (d % 2 == 1 && t >= 0 && !vary[t])
         o << "    fl.cr[" << v / 64 << "] |= (uint64_t)(" << sign_expr(P, v, "m0") << " ^ " << sign_expr(P, t, "m0")
@@ -235,6 +267,8 @@ std::string jit_source(const HostProgram& P) {
       o << "    { uint64_t a = fl_chunk.fr[" << k << "], b = fl_chunk.cr[" << k
         << "]; PW_OPAQUE(a); PW_OPAQUE(b); fl.fr[" << k << "] = uniform_mask(a); fl.cr[" << k
         << "] = uniform_mask(b); }\n";
+    for (int k = 0; k < nd; ++k)
+      o << "    { uint64_t a = fl_chunk.dp[" << k << "]; PW_OPAQUE(a); fl.dp[" << k << "] = uniform_mask(a); }\n";
     // the restore: the row, a word at a time (a compiler barrier every 8
     // words keeps the loads from all being hoisted at once, which would
     // need a register each)
@@ -244,7 +278,9 @@ std::string jit_source(const HostProgram& P) {
       << d << ">::SNAP_WORDS; ++k) {\n        e[k] = s[k];\n        if (k % 8 == 7) PW_FENCE();\n      }\n    }\n";
     o << "    const E::Ent* srow = reinterpret_cast<const E::Ent*>(snap);\n";
     o << "    // phase 1 for the varying vertices (in index order; each with all\n"
-         "    // its fixed-sign neighbours and its earlier varying ones)\n";
+         "    // its fixed-sign neighbours and its earlier varying ones; duplicate\n"
+         "    // edges skipped)\n";
+    int fe = 0;  // the next edge to a fixed-sign neighbour
     for (int v = 0; v < nV; ++v) {
       if (!vary[v]) continue;
       o << "    uint32_t r" << v << " = " << v << "u; { const uint32_t sv = " << sign_expr(P, v) << ";";
@@ -255,8 +291,13 @@ std::string jit_source(const HostProgram& P) {
         if (vary[u]) {
           o << " E::edge_v(L, sv, " << sign_expr(P, u) << ", " << v << ", r" << v << ", r" << u << ");";
         } else {
-          o << " { uint32_t t = srow[" << u << "]; E::edge_v(L, sv, " << sign_expr(P, u) << ", " << v << ", r" << v
-            << ", t); }";
+          const std::string step = "{ uint32_t t = srow[" + std::to_string(u) + "]; E::edge_v(L, sv, " +
+                                   sign_expr(P, u) + ", " + std::to_string(v) + ", r" + std::to_string(v) + ", t); }";
+          if (earlier_fixed[fe].empty())
+            o << " " << step;
+          else
+            o << " if (!((fl.dp[" << fe / 64 << "] >> " << fe % 64 << ") & 1u)) " << step;
+          ++fe;
         }
       }
       o << " }\n";
