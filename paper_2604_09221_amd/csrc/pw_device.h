@@ -323,6 +323,8 @@ struct Eval {
     uint32_t er = ent(L, (int)r);
     while (er != r) {
       r = er;
+      // (a plain 32-bit index: narrowed to 8 bits, every step would mask)
+      PW_OPAQUE(r);
       er = ent(L, (int)r);
     }
     const bool same = su == sv;
