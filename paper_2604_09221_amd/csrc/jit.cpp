@@ -63,7 +63,10 @@ void emit_tail(std::ostringstream& o, const HostProgram& P, Skip skip_pair, cons
   o << "    // phase 3: region ids and the region tree (each vertex's entry read\n"
        "    // " << kAhead << " vertices ahead)\n";
   o << "    int nR = 0;\n    E::Adj roots = 0;\n";
-  for (int v = 0; v < std::min(kAhead, nV); ++v) o << "    const uint32_t e" << v << " = E::ent(L, " << v << ");\n";
+  // (the sweep kernel reads ahead only the entries of varying vertices: a
+  // fixed-sign vertex's entry is read under its flag, which is mostly off)
+  for (int v = 0; v < std::min(kAhead, nV); ++v)
+    if (!vary || (*vary)[v]) o << "    const uint32_t e" << v << " = E::ent(L, " << v << ");\n";
   if (!vary) {
     for (int v = 0; v < nV; ++v) {
       const int t = tree_parent(P, v);
@@ -96,9 +99,11 @@ void emit_tail(std::ostringstream& o, const HostProgram& P, Skip skip_pair, cons
   };
   for (int v = 0; v < nV; ++v) {
     const int t = tree_parent(P, v);
-    if (v + kAhead < nV) o << "    const uint32_t e" << v + kAhead << " = E::ent(L, " << v + kAhead << ");\n";
+    if (v + kAhead < nV && (*vary)[v + kAhead])
+      o << "    const uint32_t e" << v + kAhead << " = E::ent(L, " << v + kAhead << ");\n";
+    const std::string ev = (*vary)[v] ? "e" + std::to_string(v) : "E::ent(L, " + std::to_string(v) + ")";
     const std::string step = "E::vertex3c(L, " + std::to_string(v) + ", " + (t >= 0 ? region_of(t) : "-1") + ", " +
-                             crossed(v, t) + ", e" + std::to_string(v) + ", nR, roots);";
+                             crossed(v, t) + ", " + ev + ", nR, roots);";
     if ((*vary)[v])
       o << "    " << step << "\n";
     else
