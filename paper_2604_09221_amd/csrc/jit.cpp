@@ -170,49 +170,87 @@ std::string jit_source(const HostProgram& P) {
         adj[u].push_back(v);
       }
     }
-    o << "struct JitSnap {\n  using E = Eval<" << d << ">;\n";
-    o << "  // the edges between vertices of fixed sign; roots into the snapshot row\n";
-    o << "  __device__ __forceinline__ void snapshot(Cfg<" << d
-      << ">::Mask m, const Lane& L, uint8_t* snap, int lane) const {\n";
-    for (int v = 0; v < nV; ++v) {
-      if (vary[v]) continue;
-      const uint32_t rec = P.words[v];
-      const int n = (rec >> 8) & 0xFF, off = rec >> 16;
-      o << "    uint32_t r" << v << " = " << v << "u; { const uint32_t sv = " << sign_expr(P, v) << ";";
-      for (int k = 0; k < n; ++k) {
-        const int u = (int)P.words[nV + off + k];
-        if (vary[u]) continue;
-        o << " E::edge_r(L, sv, " << sign_expr(P, u) << ", " << v << ", r" << v << ", r" << u << ");";
-      }
-      o << " E::close(L, " << v << ", r" << v << "); }\n";
-    }
-    // For odd d the antipodal identification is a plain union (no parity),
-    // and the regions do not depend on the order of unions: the pairs of
-    // fixed-sign vertices are merged here, once per chunk.
+    // The snapshot: the components of the fixed-sign part (for odd d with
+    // the antipodal pairs of fixed-sign vertices merged too: that is a plain
+    // union, and the regions do not depend on the order of unions).  Every
+    // lane would compute the same union-find, so the wave shares one label
+    // row instead: lane l owns the vertices l + 64 k, and min-label
+    // propagation with pointer jumping over the links below reaches, for
+    // each vertex, the smallest vertex of its component -- the root the
+    // union-find would give (links always point to the smaller root).  A
+    // varying vertex (and the padding after vertex NV-1) keeps its own
+    // index, its entry before its edges are added.
     const int nE = P.nE;
     auto fixed_pair = [&](int t) {
       const uint32_t pr = P.words[nV + nE + t];
       return (d % 2 == 1) && !vary[pr & 0xFFFF] && !vary[pr >> 16];
     };
+    const int nw = (nV + 63) / 64;
+    // links of each fixed-sign vertex: same-sign neighbours (packed: u,
+    // lattice bits of u and v, flip difference) and antipodal partners
+    std::vector<std::vector<uint32_t>> links(nV);
+    auto bit_of = [&](int x) { return (uint32_t)lattice_bit(P, x); };
+    auto flip_of = [&](int x) { return (uint32_t)((P.words[x] >> 7) & 1); };
+    for (int v = 0; v < nV; ++v) {
+      if (vary[v]) continue;
+      for (int u : adj[v])
+        if (!vary[u])
+          links[v].push_back((uint32_t)u | bit_of(u) << 8 | (flip_of(u) ^ flip_of(v)) << 15 | bit_of(v) << 16 | 1u << 24);
+    }
     for (int t = 0; t < P.nP; ++t)
       if (fixed_pair(t)) {
         const uint32_t pr = P.words[nV + nE + t];
-        o << "    E::pair(L, " << (pr & 0xFFFF) << ", " << (pr >> 16) << ");\n";
+        const int a = (int)(pr & 0xFFFF), b = (int)(pr >> 16);
+        links[a].push_back((uint32_t)b | 1u << 23 | 1u << 24);
+        links[b].push_back((uint32_t)a | 1u << 23 | 1u << 24);
       }
-    // Every lane holds the same union-find of the fixed-sign part: lane l
-    // writes the row entries l, l + 64, ...; a varying vertex (and the
-    // padding after vertex NV-1) gets its own index, its entry before its
-    // edges are added.
-    o << "    E::Ent* row = reinterpret_cast<E::Ent*>(snap);\n";
-    o << "    constexpr int kRow = Cfg<" << d << ">::SNAP_WORDS * 4 / Cfg<" << d << ">::EB;\n";
-    for (int k = 0; k * 64 < nV; ++k) {
-      uint64_t fixed = 0;
-      for (int j = 0; j < 64 && 64 * k + j < nV; ++j)
-        if (!vary[64 * k + j]) fixed |= 1ull << j;
-      o << "    { const int v = lane + " << 64 * k << "; if (v < kRow) row[v] = (E::Ent)(((0x" << std::hex << fixed
-        << std::dec << "ull >> lane) & 1) ? E::root(L, (uint32_t)v) : (uint32_t)v); }\n";
-    }
-    o << "  }\n";
+    size_t slots = 1;
+    for (const auto& l : links) slots = std::max(slots, l.size());
+    o << "// per owned vertex (lane + 64 k) and slot: bits 0-7 the linked vertex,\n"
+         "// 8-14 its lattice bit, 15 the flip difference, 16-22 the owner's\n"
+         "// lattice bit, 23 unconditional (antipodal pair), 24 present\n";
+    o << "__device__ const uint32_t kSnapLinks[" << nw * 64 * slots << "] = {";
+    for (int v = 0; v < nw * 64; ++v)
+      for (size_t j = 0; j < slots; ++j) {
+        const uint32_t x = (v < nV && j < links[v].size()) ? links[v][j] : 0u;
+        o << (v || j ? "," : "") << (j == 0 ? "\n  " : " ") << "0x" << std::hex << x << std::dec << "u";
+      }
+    o << "};\n";
+    o << "struct JitSnap {\n  using E = Eval<" << d << ">;\n";
+    o << "  static constexpr int kNW = " << nw << ", kSlots = " << slots << ";\n";
+    o << "  static constexpr int kRow = Cfg<" << d << ">::SNAP_WORDS * 4 / Cfg<" << d << ">::EB;\n";
+    o << "  // the row offsets a lane takes the minimum over (its own vertex where\n"
+         "  // a link is absent or inactive in this chunk)\n";
+    o << "  struct Links {\n    uint32_t a[kNW][kSlots];\n  };\n";
+    o << "  __device__ __forceinline__ static void snap_init(uint8_t* snap, int lane) {\n"
+         "    E::Ent* row = reinterpret_cast<E::Ent*>(snap);\n"
+         "    for (int k = 0; k < kNW; ++k) {\n      const int v = lane + 64 * k;\n"
+         "      if (v < kRow) row[v] = (E::Ent)v;\n    }\n  }\n";
+    o << "  __device__ __forceinline__ static Links snap_links(uint64_t m0, int lane) {\n    Links ln;\n"
+         "    for (int k = 0; k < kNW; ++k) {\n      const uint32_t v = (uint32_t)(lane + 64 * k);\n"
+         "      for (int j = 0; j < kSlots; ++j) {\n"
+         "        const uint32_t x = kSnapLinks[v * kSlots + j];\n"
+         "        const uint32_t same = (uint32_t)((m0 >> ((x >> 8) & 0x7F)) ^ (m0 >> ((x >> 16) & 0x7F))) & 1u;\n"
+         "        const bool on = ((x >> 24) & 1u) && (((x >> 23) & 1u) || same == ((x >> 15) & 1u));\n"
+         "        ln.a[k][j] = on ? (x & 0xFFu) : v;\n      }\n    }\n    return ln;\n  }\n";
+    o << "  // one round over the lane's vertices; true if a label went down\n";
+    o << "  __device__ __forceinline__ static bool snap_step(const Links& ln, uint8_t* snap, int lane) {\n"
+         "    E::Ent* row = reinterpret_cast<E::Ent*>(snap);\n    bool changed = false;\n"
+         "    for (int k = 0; k < kNW; ++k) {\n      const int v = lane + 64 * k;\n"
+         "      if (v >= Cfg<" << d << ">::NV) continue;\n"
+         "      const uint32_t cur = row[v];\n      uint32_t mn = cur;\n"
+         "      for (int j = 0; j < kSlots; ++j) {\n        const uint32_t y = row[ln.a[k][j]];\n"
+         "        mn = y < mn ? y : mn;\n      }\n"
+         "      const uint32_t z = row[mn];  // pointer jumping: a label's own label is no larger\n"
+         "      mn = z < mn ? z : mn;\n"
+         "      if (mn < cur) {\n        row[v] = (E::Ent)mn;\n        changed = true;\n      }\n    }\n"
+         "    return changed;\n  }\n";
+    o << "  __device__ __forceinline__ void snapshot(Cfg<" << d
+      << ">::Mask m, const Lane& L, uint8_t* snap, int lane) const {\n"
+         "    (void)L;\n    snap_init(snap, lane);\n    const Links ln = snap_links(uniform_mask(m), lane);\n"
+         "    // labels only go down: at most NV rounds (the bound is never reached)\n"
+         "    for (int round = 0; round <= Cfg<"
+      << d << ">::NV; ++round)\n      if (__builtin_amdgcn_ballot_w64(snap_step(ln, snap, lane)) == 0) break;\n  }\n";
     // The edges of phase 1 between a varying vertex and a fixed-sign
     // neighbour, in the order the batch adds them; such an edge is a
     // duplicate when an earlier fixed-sign neighbour of the same vertex has
@@ -237,7 +275,6 @@ std::string jit_source(const HostProgram& P) {
     const int nd = std::max(1, (n_fixed_edges + 63) / 64);
     // the wave-uniform flags of a chunk, from the snapshot row (entry v
     // is v: v is a root of the fixed-sign part) and from m0
-    const int nw = (nV + 63) / 64;
     o << "  struct Flags {\n    uint64_t fr[" << nw << "];  // fixed-sign vertices that are snapshot roots\n"
       << "    uint64_t cr[" << nw << "];  // fixed-sign vertices whose tree edge (both ends fixed) is crossed\n"
       << "    uint64_t dp[" << nd << "];  // duplicate phase-1 edges to fixed-sign neighbours\n  };\n";

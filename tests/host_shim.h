@@ -32,6 +32,7 @@ template <class T> static inline T atomicAdd(T*, T) { emu_unsupported(); }
 template <class T> static inline T atomicMin(T*, T) { emu_unsupported(); }
 template <class T> static inline T atomicOr(T*, T) { emu_unsupported(); }
 static inline uint64_t __ballot(int) { emu_unsupported(); }
+static inline uint64_t __builtin_amdgcn_ballot_w64(bool) { emu_unsupported(); }
 static inline int emu_readlane(int, int) { emu_unsupported(); }
 #define __builtin_amdgcn_readlane(a, b) emu_readlane(a, b)
 #define __builtin_amdgcn_readfirstlane(a) ((int)(a))  // returns int on the device too

@@ -66,17 +66,20 @@ int main(int argc, char** argv) {
     // from m only in the varying bits 1..9
     typename C::Mask m1 = m ^ (typename C::Mask)((((uint64_t)i * 0x9E3779B97F4A7C15ull) >> 40) & 0x3FEull);
     alignas(16) static uint8_t srow[C::SNAP_BYTES];
-    for (int j = 0; j < 64; ++j) {
-      threadIdx.x = j;
-      const pw::Lane Lj = pw::lane_memory<DEG>(smem, C::LANE_WORDS);
-      const bool check = i < 2;
-      if (check) {
-        own_bytes(j, own);
-        memcpy(before.data(), smem, kBytes);
-      }
-      pw::JitSnap{}.snapshot((m1 & ~(typename C::Mask)0x7E) | (typename C::Mask)(j << 1), Lj, srow, j);
-      if (check && foreign_write(own, before, smem)) ++foreign;
+    // the wave's lanes build the snapshot row together; here one lane
+    // after the other, round by round, until no label goes down (the same
+    // fixed point as in lockstep: labels only decrease)
+    const std::vector<unsigned char> before_snap((unsigned char*)smem, (unsigned char*)smem + kBytes);
+    using S = pw::JitSnap;
+    std::vector<S::Links> links;
+    for (int j = 0; j < 64; ++j) S::snap_init(srow, j);
+    for (int j = 0; j < 64; ++j)
+      links.push_back(S::snap_links((uint64_t)((m1 & ~(typename C::Mask)0x7E) | (typename C::Mask)(j << 1)), j));
+    for (bool any = true; any;) {
+      any = false;
+      for (int j = 0; j < 64; ++j) any = S::snap_step(links[j], srow, j) || any;
     }
+    if (memcmp(before_snap.data(), smem, kBytes) != 0) ++foreign;  // the snapshot uses its own row only
 #endif
     threadIdx.x = lane;
     const pw::Lane L = pw::lane_memory<DEG>(smem, C::LANE_WORDS);
