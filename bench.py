@@ -197,10 +197,11 @@ def bench_learned(args):
     res = [Lr.run_uniform(tri, d, budget)]
     per_round = max(1 << 20, budget >> 8)
     target = res[0]["distinct"]
+    t_uniform = res[0]["gpu_seconds"]
     res.append(Lr.run_search(tri, d, budget, use_net=True, train_n=min(1 << 24, budget // 4), per_round=per_round,
-                             log=log, target=target))
+                             log=log, target=target, time_budget=t_uniform))
     res.append(Lr.run_search(tri, d, budget, use_net=False, train_n=min(1 << 24, budget // 4), per_round=per_round,
-                             log=log, target=target))
+                             log=log, target=target, time_budget=t_uniform))
     # the same uniform stream again, untimed, for its curve
     res[0]["curve"] = Lr.run_uniform(tri, d, budget, curve=True)["curve"]
     for r in res:
@@ -210,6 +211,13 @@ def bench_learned(args):
     # distinct, seconds since the start, training included)
     for r in res[1:]:
         r["seconds_to_uniform_count"] = r.pop("seconds_to_target")
+    # equal GPU time: the schemes each search had seen within the seconds
+    # uniform sampling needs for the whole budget, per GPU-second
+    res[0]["distinct_within_uniform_seconds"] = res[0]["distinct"]
+    for r in res[1:]:
+        r["distinct_within_uniform_seconds"] = r.pop("distinct_within_time_budget")
+    for r in res:
+        r["distinct_per_gpu_second_equal_time"] = r["distinct_within_uniform_seconds"] / t_uniform
     # roofline of the dominant contraction: the 512 x 512 hidden layer of the
     # forward pass (k_gemm_bf16, 128 x 128 tiles), timed with HIP events on
     # the stream it runs on
@@ -236,14 +244,98 @@ def bench_learned(args):
     flops = 2.0 * rows * Lr.HIDDEN * Lr.HIDDEN
     return {
         "metric": "distinct real schemes found per GPU-second at d=8",
-        "value": res[1]["distinct_per_gpu_second"], "unit": "schemes/s", "n_gpus": 1, "steps": 1, "warmup": 0,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16+u64", "data": "synthetic",
-        "config": {"workload": f"d=8 standard triangulation, {budget} judged masks per method", "results": res},
+        "value": res[1]["distinct_per_gpu_second_equal_time"], "unit": "schemes/s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16+u64",
+        "data": "synthetic",
+        "config": {"workload": f"d=8 standard triangulation, {budget} judged masks per method",
+                   "value": "learned proposal: distinct schemes seen within the GPU time uniform sampling takes for "
+                            "the whole budget, per GPU-second (equal-time); uniform's equal-time rate: "
+                            f"{res[0]['distinct_per_gpu_second_equal_time']:.1f}; each method's rate over its own "
+                            "whole budget: distinct_per_gpu_second in results",
+                   "results": res},
         "roofline": {"bound": "mfma", "achieved": flops / gemm_s / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": flops / gemm_s / 2.5e15, "traffic": None,
                      "kernel": "pw::k_gemm_bf16<128,128> (hidden layer 512x512, forward, 2^18 rows)",
                      "avg_launch_ms": gemm_s * 1e3},
     }
+
+
+FIG2 = {"bow_tie": 123, "rank016": 359, "rank015": 353}  # distinct real schemes printed with Fig. 2
+
+
+def fig2_fixed_bits(d):
+    """Class representatives of the (Z/2)^3 action sigma -> sigma + a + b i +
+    c j: sigma fixed to '+' at (0,0), (1,1) and (2,1), whose parity vectors
+    (i, j mod 2) are (0,0), (1,1), (0,1) -- one mask per orbit, and the
+    lattice bits 1..9 stay free (the sweep kernel's shared snapshot)."""
+    def k(i, j):
+        return j * (d + 1) - j * (j - 1) // 2 + i
+    return (1 << k(0, 0)) | (1 << k(1, 1)) | (1 << k(2, 1))
+
+
+def bench_fig2(args):
+    """Part of the exhaustive class-representative sweep of one Fig. 2
+    triangulation (d = 8, 2^42 classes): index range [part, part + 1) *
+    2^42 / parts, in launches of 2^36 masks; the histogram goes out as
+    (code, count) pairs for merging (--config fig2-check)."""
+    import torch
+
+    from paper_2604_09221_amd import patchwork as pw
+
+    d = 8
+    E = np.loadtxt(os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                                f"fig2_{args.tri}.edges"), dtype=np.int32)
+    tri = pw.Triangulation(d, E).specialize()
+    fz = fig2_fixed_bits(d)
+    total = 1 << (45 - 3)
+    span = total // args.parts
+    first, end = args.part * span, (args.part + 1) * span
+    step = 1 << 36
+    hist = pw.Histogram(4096)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a in range(first, end, step):
+        tri.enumerate_range(a, min(step, end - a), hist, fixed_zero_bits=fz)
+        torch.cuda.synchronize()
+        print(f"{args.tri}: {a + step - first} of {end - first} masks, {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
+    dt = time.perf_counter() - t0
+    h = hist.read()
+    return {"metric": "Fig. 2 class sweep (d=8)", "tri": args.tri, "first": first, "count": end - first,
+            "seconds": dt, "masks_per_s": (end - first) / dt, "errors": tri.errors(),
+            "hist": [[str(code), c] for code, (c, _) in sorted(h.items())]}
+
+
+def fig2_check(paths):
+    """Merge the parts of one triangulation's sweep and compare with the
+    printed Fig. 2 data: the number of distinct schemes and the percentage
+    of classes with k ovals (printed to 4 decimals)."""
+    parts = [json.loads(open(p).read().strip().splitlines()[-1]) for p in paths]
+    tri = parts[0]["tri"]
+    counts = {}
+    masks = 0
+    for q in parts:
+        assert q["tri"] == tri and q["errors"] == 0
+        masks += q["count"]
+        for code, c in q["hist"]:
+            counts[int(code)] = counts.get(int(code), 0) + c
+    ranges = sorted((q["first"], q["first"] + q["count"]) for q in parts)
+    whole = ranges[0][0] == 0 and ranges[-1][1] == 1 << 42 and all(a[1] == b[0] for a, b in zip(ranges, ranges[1:]))
+    by_ovals = {}
+    for code, c in counts.items():
+        ovals = (code.bit_length() - 1) // 2  # code = 2^|W| + W, |W| = 2 * ovals (no J at even d)
+        by_ovals[ovals] = by_ovals.get(ovals, 0) + c
+    printed = np.loadtxt(os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                                      f"fig2_{tri}.hist"))
+    rows, worst = [], 0.0
+    for k, pct in printed:
+        ours = 100.0 * by_ovals.get(int(k), 0) / masks
+        worst = max(worst, abs(round(ours, 4) - pct))
+        rows.append([int(k), pct, ours])
+    return {"metric": "Fig. 2 replication (d=8, all 2^42 classes)", "tri": tri, "whole_sweep": whole,
+            "classes": masks, "sum_counts": sum(counts.values()), "distinct": len(counts), "printed_distinct": FIG2[tri],
+            "max_abs_diff_pp_after_rounding": worst, "ovals": rows,
+            "seconds": sum(q["seconds"] for q in parts)}
 
 
 def main():
@@ -253,7 +345,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=1 << 24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--config", choices=("d7", "multi", "learned", "copyprobe"), default="d7")
+    ap.add_argument("--config", choices=("d7", "multi", "learned", "copyprobe", "fig2", "fig2-check"), default="d7")
+    ap.add_argument("--tri", choices=sorted(FIG2), default="rank016", help="--config fig2: the triangulation")
+    ap.add_argument("--part", type=int, default=0, help="--config fig2: which part of the sweep")
+    ap.add_argument("--parts", type=int, default=2, help="--config fig2: parts of the 2^42 sweep")
+    ap.add_argument("inputs", nargs="*", help="--config fig2-check: the parts' JSON outputs")
     ap.add_argument("--slots", type=int, default=4096)
     ap.add_argument("--varied", action="store_true")
     ap.add_argument("--tune", action="store_true")
@@ -265,6 +361,12 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(sharding is one histogram merge; see the design notes).", file=sys.stderr)
         sys.exit(2)
+    if args.config == "fig2-check":
+        print(json.dumps(fig2_check(args.inputs)), flush=True)
+        return
+    if args.config == "fig2":
+        print(json.dumps(bench_fig2(args)), flush=True)
+        return
     if args.config == "multi":
         print(json.dumps(bench_multi(args)), flush=True)
         return

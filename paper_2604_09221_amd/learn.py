@@ -389,7 +389,7 @@ def run_uniform(tri, d, budget, chunk=1 << 22, seed=1, curve=False):
 
 
 def run_search(tri, d, budget, use_net=True, train_n=1 << 24, epochs=1, batch=1 << 16, lr=3e-3, per_round=1 << 22,
-               n_elite=4096, temp=0.25, explore=0.1, seed=7, log=None, target=None):
+               n_elite=4096, temp=0.25, explore=0.1, seed=7, log=None, target=None, time_budget=None):
     """Mutation search from the witnesses of the rarest schemes seen.
 
     With use_net, the network (trained first on train_n uniform masks
@@ -401,7 +401,9 @@ def run_search(tri, d, budget, use_net=True, train_n=1 << 24, epochs=1, batch=1 
     kernel (histogram mode; witnesses index a device archive of the judged
     masks); the training masks count against the budget.  With `target`,
     the result also holds the seconds (training included) until at least
-    that many distinct schemes had been seen."""
+    that many distinct schemes had been seen; with `time_budget`, the
+    number of distinct schemes seen within that many seconds (read at the
+    start of each round)."""
     import torch
 
     nA = (d + 1) * (d + 2) // 2
@@ -458,7 +460,10 @@ def run_search(tri, d, budget, use_net=True, train_n=1 << 24, epochs=1, batch=1 
     if target is not None:
         hit = [c for c in curve if c[1] >= target]
         reach = hit[0][2] if hit else None
+    within = None
+    if time_budget is not None:
+        within = max([c[1] for c in curve if c[2] <= time_budget], default=0)
     return {"method": "learned" if use_net else "ablation (uniform flips)", "evaluations": used,
-            "seconds_to_target": reach,
+            "seconds_to_target": reach, "distinct_within_time_budget": within,
             "distinct": final, "gpu_seconds": dt, "train_seconds": train_s, "rounds": rnd,
             "curve": curve[:: max(1, len(curve) // 32)] + ([curve[-1]] if len(curve) > 32 else [])}

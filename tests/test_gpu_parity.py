@@ -244,6 +244,24 @@ def test_edge_cases(pw):
 
 # ------------------------------------------------- specialised kernels (hipRTC)
 
+def test_class_representative_sweep(pw):
+    """The Fig. 2 sweep's enumeration (d = 8, sigma fixed at (0,0), (1,1),
+    (2,1)): histograms of index ranges -- chunk-aligned, ragged and near the
+    end of the 2^42 classes -- bit-exact against the oracle."""
+    import bench
+
+    fz = bench.fig2_fixed_bits(8)
+    for name in ("rank016", "bow_tie"):
+        E = fig2_edges(name)
+        tri = pw.Triangulation(8, E).specialize()
+        for first, n in [(0, 1 << 15), (777, 20001), ((1 << 42) - 3000, 3000)]:
+            h = pw.Histogram(1024)
+            tri.enumerate_range(first, n, h, fixed_zero_bits=fz)
+            want = oracle.scheme_many(8, E, enum_masks(first, n, fixed=fz, nA=45), threads=THREADS)
+            assert h.read() == oracle_hist(want, index_of=np.arange(first, first + n, dtype=np.uint64))
+        assert tri.errors() == 0
+
+
 def test_specialized_kernels_match_oracle(pw):
     """Kernels generated for one triangulation: codes, histograms and
     witnesses bit-exact against the oracle (and hence the generic path)."""
