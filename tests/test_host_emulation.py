@@ -118,7 +118,8 @@ def _compile(tmp_path, d, edges, snap):
                                                  (6, 1.0, 3, 2000, False), (7, None, 0, 3000, False),
                                                  (7, 1.0, 4, 2000, False), (9, None, 0, 600, False),
                                                  (6, 1.0, 5, 2000, True), (5, 1.0, 2, 2000, True), (7, None, 0, 3000, True),
-                                                 (7, 1.0, 6, 2000, True), (9, None, 0, 600, True)])
+                                                 (7, 1.0, 6, 2000, True), (8, None, 0, 600, True),
+                                                 (9, None, 0, 600, True)])
 def test_evaluator_on_host_matches_oracle(tmp_path, d, noise, seed, n, snap):
     edges = I.standard_triangulation(d) if noise is None else I.lift_triangulation(d, seed, noise=noise)
     exe = _compile(tmp_path, d, edges, snap)
