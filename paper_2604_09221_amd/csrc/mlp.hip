@@ -3,7 +3,7 @@
 // trained on masks labelled by the exact scheme kernels, then used to rank
 // mutated candidate masks before the exact kernels judge them.
 //
-// Dense products use gfx950 matrix cores (v_mfma_f32_16x16x16_bf16: BF16
+// Dense products use gfx950 matrix cores (v_mfma_f32_16x16x32_bf16: BF16
 // operands, FP32 accumulation).  Everything else is elementwise or a small
 // reduction on the vector units.  bfloat16 values are kept as uint16_t bit
 // patterns; conversion rounds to nearest-even from the IEEE-754 binary32
@@ -41,12 +41,15 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
 // into C32 with FP32 atomics.
 //
 // gfx950 MFMA v_mfma_f32_16x16x32_bf16 operand layout (l = lane):
-//   A: lane l holds A[l % 16][8 (l / 16) + 0..7]
-//   B: lane l holds B[8 (l / 16) + 0..7][l % 16]
-//   C: lane l holds C[4 (l / 16) + 0..3][l % 16]
+//   X: lane l holds X[l % 16][8 (l / 16) + 0..7]
+//   Y: lane l holds Y[8 (l / 16) + 0..7][l % 16]
+//   Z: lane l holds Z[4 (l / 16) + 0..3][l % 16]     (Z = X Y)
 // Both tiles sit in LDS k-contiguous ([m][k] and [n][k]), so each operand
-// fragment is one 16-byte LDS read.  Epilogue per element: + bias[n],
-// ReLU, times [gate > 0], stored as fp32 and/or bf16.
+// fragment is one 16-byte LDS read.  The product is issued as C^T = B^T A^T
+// (X = the B fragment, Y = the A fragment): lane l then holds
+// C[l % 16][4 (l / 16) + 0..3], four consecutive columns of one row, and
+// the epilogue (+ bias[n], ReLU, times [gate > 0], fp32 and/or bf16
+// stores) moves 4 columns per access.
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
@@ -70,6 +73,7 @@ struct GemmArgs {
   int accumulate;  // C32 += result
   int atomic;      // partial tiles of a split K: C32 += result atomically
   float* colsum;   // N or null: colsum[n] += sum over m of the final C[m][n]
+  int vec;         // bias, gate, C32 and C16 allow 4-column vector accesses
 };
 
 // One ROWS x TBK slab of an operand X (element (r, k) at X[r s_row + k s_k])
@@ -164,42 +168,83 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
 #pragma unroll
     for (int a = 0; a < FM; ++a)
 #pragma unroll
-      for (int b = 0; b < FN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+      for (int b = 0; b < FN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[b], af[a], acc[a][b], 0, 0, 0);
     __syncthreads();
   }
-  float csum[FN];
+  // lane: row m = m0 + wm + 16 a + (lane % 16), columns n .. n + 3 with
+  // n = n0 + wn + 16 b + 4 (lane / 16)
+  float4_t csum[FN];
 #pragma unroll
-  for (int b = 0; b < FN; ++b) csum[b] = 0.f;
+  for (int b = 0; b < FN; ++b) csum[b] = float4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int a = 0; a < FM; ++a)
-#pragma unroll
-    for (int b = 0; b < FN; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm + 16 * a + 4 * (lane >> 4) + r;
-        const int n = n0 + wn + 16 * b + (lane & 15);
-        float v = acc[a][b][r];
-        if (g.atomic) {
-          unsafeAtomicAdd(&g.C32[(int64_t)m * g.c_m + n], v);
-          continue;
-        }
-        if (g.bias) v += g.bias[n];
-        if (g.relu) v = v > 0.f ? v : 0.f;
-        if (g.gate && !(bf16_to_f32(g.gate[(int64_t)m * g.g_m + n]) > 0.f)) v = 0.f;
-        csum[b] += v;
-        if (g.C32) {
-          float* o = &g.C32[(int64_t)m * g.c_m + n];
-          *o = g.accumulate ? *o + v : v;
-        }
-        if (g.C16) g.C16[(int64_t)m * g.c_m + n] = f32_to_bf16(v);
-      }
-  if (g.colsum) {  // lanes l, l^16, l^32, l^48 hold the same column
+  for (int a = 0; a < FM; ++a) {
+    const int m = m0 + wm + 16 * a + (lane & 15);
 #pragma unroll
     for (int b = 0; b < FN; ++b) {
-      float v = csum[b];
-      v += __shfl_xor(v, 16);
-      v += __shfl_xor(v, 32);
-      if (lane < 16) unsafeAtomicAdd(&g.colsum[n0 + wn + 16 * b + lane], v);
+      const int n = n0 + wn + 16 * b + 4 * (lane >> 4);
+      float4_t v = acc[a][b];
+      if (g.atomic) {
+        float* o = g.C32 + (int64_t)m * g.c_m + n;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) unsafeAtomicAdd(o + r, v[r]);
+        continue;
+      }
+      if (g.vec) {
+        if (g.bias) v += *reinterpret_cast<const float4_t*>(g.bias + n);
+        if (g.relu) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) v[r] = v[r] > 0.f ? v[r] : 0.f;
+        }
+        if (g.gate) {
+          const uint2 q = *reinterpret_cast<const uint2*>(g.gate + (int64_t)m * g.g_m + n);
+          const uint32_t h[4] = {q.x << 16, q.x & 0xFFFF0000u, q.y << 16, q.y & 0xFFFF0000u};
+#pragma unroll
+          for (int r = 0; r < 4; ++r) v[r] = __uint_as_float(h[r]) > 0.f ? v[r] : 0.f;
+        }
+        csum[b] += v;
+        if (g.C32) {
+          float4_t* o = reinterpret_cast<float4_t*>(g.C32 + (int64_t)m * g.c_m + n);
+          *o = g.accumulate ? *o + v : v;
+        }
+        if (g.C16) {
+          uint2 q;
+          q.x = (uint32_t)f32_to_bf16(v[0]) | ((uint32_t)f32_to_bf16(v[1]) << 16);
+          q.y = (uint32_t)f32_to_bf16(v[2]) | ((uint32_t)f32_to_bf16(v[3]) << 16);
+          *reinterpret_cast<uint2*>(g.C16 + (int64_t)m * g.c_m + n) = q;
+        }
+        continue;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float x = v[r];
+        if (g.bias) x += g.bias[n + r];
+        if (g.relu) x = x > 0.f ? x : 0.f;
+        if (g.gate && !(bf16_to_f32(g.gate[(int64_t)m * g.g_m + n + r]) > 0.f)) x = 0.f;
+        csum[b][r] += x;
+        if (g.C32) {
+          float* o = &g.C32[(int64_t)m * g.c_m + n + r];
+          *o = g.accumulate ? *o + x : x;
+        }
+        if (g.C16) g.C16[(int64_t)m * g.c_m + n + r] = f32_to_bf16(x);
+      }
+    }
+  }
+  if (g.colsum) {  // the 16 lanes with one lane / 16 hold the same 4 columns
+#pragma unroll
+    for (int b = 0; b < FN; ++b) {
+      float4_t v = csum[b];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        v[r] += __shfl_xor(v[r], 1);
+        v[r] += __shfl_xor(v[r], 2);
+        v[r] += __shfl_xor(v[r], 4);
+        v[r] += __shfl_xor(v[r], 8);
+      }
+      if ((lane & 15) == 0) {
+        const int n = n0 + wn + 16 * b + 4 * (lane >> 4);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) unsafeAtomicAdd(&g.colsum[n + r], v[r]);
+      }
     }
   }
 }
@@ -533,9 +578,12 @@ pw_status pw_mlp_gemm(const uint16_t* A, int64_t a_m, int64_t a_k, const uint16_
   if (M <= 0 || N <= 0 || K <= 0 || M % 64 || N % 64 || K % TBK)
     return set_err(PW_ERR_ARG, "gemm sizes must be positive multiples of 64 (M, N) and 32 (K): %d %d %d", M, N, K);
   if (accumulate && !C32) return set_err(PW_ERR_ARG, "accumulate needs the fp32 output");
-  GemmArgs g{A, a_m, a_k, B, b_k, b_n, M, N, K, K, bias, gate, g_m, relu, C32, C16, c_m, accumulate, 0, colsum};
+  GemmArgs g{A, a_m, a_k, B, b_k, b_n, M, N, K, K, bias, gate, g_m, relu, C32, C16, c_m, accumulate, 0, colsum, 0};
   // 16-byte staging needs 8-element alignment of the base and the strides
   auto al = [](const void* p, int64_t s1) { return ((uintptr_t)p % 16 == 0) && (s1 % 8 == 0); };
+  // 4-column epilogue accesses: 16 bytes of fp32, 8 bytes of bf16
+  g.vec = (!bias || (uintptr_t)bias % 16 == 0) && (!gate || ((uintptr_t)gate % 8 == 0 && g_m % 4 == 0)) &&
+          (!C32 || ((uintptr_t)C32 % 16 == 0 && c_m % 4 == 0)) && (!C16 || ((uintptr_t)C16 % 8 == 0 && c_m % 4 == 0));
   const int am = (a_k == 1 && al(A, a_m)) ? 1 : ((a_m == 1 && al(A, a_k)) ? 2 : 0);
   const int bm = (b_k == 1 && al(B, b_n)) ? 1 : ((b_n == 1 && al(B, b_k)) ? 2 : 0);
   const int tm = M % 128 == 0 ? 128 : 64, tn = N % 128 == 0 ? 128 : 64;
