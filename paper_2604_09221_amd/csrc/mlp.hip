@@ -34,7 +34,8 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
 // C[M x N] = A[M x K] * B[K x N] with arbitrary element strides (so the
 // same kernel serves X W, dY W^T and X^T dY).  A block of four waves owns a
 // BM x BN tile (BM, BN in {64, 128}); each wave a (BM/2) x (BN/2) quarter
-// made of 16 x 16 MFMA tiles.  K advances TBK = 32 at a time through LDS,
+// made of 16 x 16 MFMA tiles.  K advances TK = 64 (or 32 where K is not a
+// multiple of 64) at a time through LDS,
 // the next slab being fetched into registers while the current one is
 // multiplied.  Tall-K products with few output tiles (the weight gradients
 // X^T dY, K = batch) split K over blockIdx.z and add their partial tiles
@@ -53,8 +54,7 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
-constexpr int TBK = 32;
-constexpr int LDK = TBK + 8;  // padded LDS row: 80 bytes
+constexpr int TBK = 32;  // K granularity of the API; slabs of TK = 32 or 64
 
 struct GemmArgs {
   const uint16_t* A;
@@ -62,7 +62,7 @@ struct GemmArgs {
   const uint16_t* B;
   int64_t b_k, b_n;
   int M, N, K;
-  int k_split;           // K range of one blockIdx.z (multiple of TBK)
+  int k_split;           // K range of one blockIdx.z (multiple of the slab width)
   const float* bias;     // N or null
   const uint16_t* gate;  // M x N (ld g_m) or null: multiply by [gate > 0]
   int64_t g_m;
@@ -76,7 +76,7 @@ struct GemmArgs {
   int vec;         // bias, gate, C32 and C16 allow 4-column vector accesses
 };
 
-// One ROWS x TBK slab of an operand X (element (r, k) at X[r s_row + k s_k])
+// One ROWS x TK slab of an operand X (element (r, k) at X[r s_row + k s_k])
 // moves HBM -> registers -> LDS tile T[ROWS][LDK] in 16-byte chunks.
 // MODE 1: contiguous along k (s_k == 1): a chunk is 8 consecutive k of one
 // row.  MODE 2: contiguous along r (s_row == 1): a chunk is 8 consecutive
@@ -87,9 +87,11 @@ __device__ __forceinline__ uint16_t half_of(const u32x4_t& q, int e) {
   return (uint16_t)(q[e >> 1] >> (16 * (e & 1)));
 }
 
-template <int ROWS, int MODE>
+template <int ROWS, int MODE, int TK>
 struct Slab {
-  static constexpr int CHUNKS = ROWS * TBK / 8 / 256;  // per thread
+  static constexpr int CHUNKS = ROWS * TK / 8 / 256;  // per thread
+  static constexpr int CPR = TK / 8;                  // 16-byte chunks per row
+  static constexpr int LDK = TK + 8;                  // padded LDS row
   u32x4_t q[CHUNKS];
 
   __device__ __forceinline__ void load(const uint16_t* __restrict__ X, int64_t s_row, int64_t s_k, int r0, int k0,
@@ -101,7 +103,7 @@ struct Slab {
         const int k = id / (ROWS / 8), r = (id % (ROWS / 8)) * 8;
         q[c] = *reinterpret_cast<const u32x4_t*>(&X[(int64_t)(k0 + k) * s_k + (int64_t)(r0 + r)]);
       } else {
-        const int r = id >> 2, k = (id & 3) * 8;
+        const int r = id / CPR, k = (id % CPR) * 8;
         if (MODE == 1) {
           q[c] = *reinterpret_cast<const u32x4_t*>(&X[(int64_t)(r0 + r) * s_row + (int64_t)(k0 + k)]);
         } else {
@@ -123,16 +125,17 @@ struct Slab {
 #pragma unroll
         for (int e = 0; e < 8; ++e) T[r + e][k] = half_of(q[c], e);
       } else {
-        const int r = id >> 2, k = (id & 3) * 8;
+        const int r = id / CPR, k = (id % CPR) * 8;
         *reinterpret_cast<u32x4_t*>(&T[r][k]) = q[c];
       }
     }
   }
 };
 
-template <int BM, int BN, int AM, int BM_>
+template <int BM, int BN, int AM, int BM_, int TK>
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
   constexpr int FM = BM / 32, FN = BN / 32;  // 16 x 16 tiles per wave along m and n
+  constexpr int LDK = TK + 8;
   __shared__ __attribute__((aligned(16))) uint16_t As[BM][LDK];  // [m][k]
   __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][LDK];  // [n][k]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -145,30 +148,34 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
   for (int a = 0; a < FM; ++a)
 #pragma unroll
     for (int b = 0; b < FN; ++b) acc[a][b] = float4_t{0.f, 0.f, 0.f, 0.f};
-  Slab<BM, AM> sa;
-  Slab<BN, BM_> sb;
+  Slab<BM, AM, TK> sa;
+  Slab<BN, BM_, TK> sb;
   if (kb < ke) {
     sa.load(g.A, g.a_m, g.a_k, m0, kb, tid);
     sb.load(g.B, g.b_n, g.b_k, n0, kb, tid);
   }
-  for (int k0 = kb; k0 < ke; k0 += TBK) {
+  for (int k0 = kb; k0 < ke; k0 += TK) {
     sa.store(As, tid);
     sb.store(Bs, tid);
     __syncthreads();
-    if (k0 + TBK < ke) {  // next slab in flight during the products
-      sa.load(g.A, g.a_m, g.a_k, m0, k0 + TBK, tid);
-      sb.load(g.B, g.b_n, g.b_k, n0, k0 + TBK, tid);
+    if (k0 + TK < ke) {  // next slab in flight during the products
+      sa.load(g.A, g.a_m, g.a_k, m0, k0 + TK, tid);
+      sb.load(g.B, g.b_n, g.b_k, n0, k0 + TK, tid);
     }
-    const int kk = 8 * (lane >> 4);
-    bf16x8_t af[FM], bfr[FN];
 #pragma unroll
-    for (int a = 0; a < FM; ++a) af[a] = *reinterpret_cast<const bf16x8_t*>(&As[wm + 16 * a + (lane & 15)][kk]);
+    for (int ks = 0; ks < TK; ks += 32) {
+      const int kk = ks + 8 * (lane >> 4);
+      bf16x8_t af[FM], bfr[FN];
 #pragma unroll
-    for (int b = 0; b < FN; ++b) bfr[b] = *reinterpret_cast<const bf16x8_t*>(&Bs[wn + 16 * b + (lane & 15)][kk]);
+      for (int a = 0; a < FM; ++a) af[a] = *reinterpret_cast<const bf16x8_t*>(&As[wm + 16 * a + (lane & 15)][kk]);
 #pragma unroll
-    for (int a = 0; a < FM; ++a)
+      for (int b = 0; b < FN; ++b) bfr[b] = *reinterpret_cast<const bf16x8_t*>(&Bs[wn + 16 * b + (lane & 15)][kk]);
 #pragma unroll
-      for (int b = 0; b < FN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[b], af[a], acc[a][b], 0, 0, 0);
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[b], af[a], acc[a][b], 0, 0, 0);
+    }
     __syncthreads();
   }
   // lane: row m = m0 + wm + 16 a + (lane % 16), columns n .. n + 3 with
@@ -590,12 +597,14 @@ pw_status pw_mlp_gemm(const uint16_t* A, int64_t a_m, int64_t a_k, const uint16_
   const int tiles = (M / tm) * (N / tn);
   // split K when the output has too few tiles to fill 256 CUs and there is
   // no element-wise epilogue (partial sums are added atomically)
+  // K slabs of 64 where K allows (half the global round trips), else 32
+  const int tk = K % 64 == 0 ? 64 : 32;
   int splits = 1;
-  const int ksteps = K / TBK;
+  const int ksteps = K / tk;
   if (C32 && !C16 && !bias && !gate && !relu && !colsum && tiles < 512 && ksteps >= 8) {
     splits = std::min(ksteps / 4, (1024 + tiles - 1) / tiles);
     const int per = (ksteps + splits - 1) / splits;
-    g.k_split = per * TBK;
+    g.k_split = per * tk;
     splits = (ksteps + per - 1) / per;
   }
   if (splits > 1) {
@@ -605,17 +614,23 @@ pw_status pw_mlp_gemm(const uint16_t* A, int64_t a_m, int64_t a_k, const uint16_
     }
   }
   const dim3 grid(N / tn, M / tm, splits);
-#define PW_GEMM_CASES(BM_, BN_)                                                                   \
-  switch (am * 3 + bm) {                                                                          \
-    case 0: hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, 0, 0>), grid, dim3(256), 0, s, g); break; \
-    case 1: hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, 0, 1>), grid, dim3(256), 0, s, g); break; \
-    case 2: hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, 0, 2>), grid, dim3(256), 0, s, g); break; \
-    case 3: hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, 1, 0>), grid, dim3(256), 0, s, g); break; \
-    case 4: hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, 1, 1>), grid, dim3(256), 0, s, g); break; \
-    case 5: hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, 1, 2>), grid, dim3(256), 0, s, g); break; \
-    case 6: hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, 2, 0>), grid, dim3(256), 0, s, g); break; \
-    case 7: hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, 2, 1>), grid, dim3(256), 0, s, g); break; \
-    default: hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, 2, 2>), grid, dim3(256), 0, s, g); break; \
+#define PW_GEMM_MODES(BM_, BN_, TK_)                                                                   \
+  switch (am * 3 + bm) {                                                                               \
+    case 0: hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, 0, 0, TK_>), grid, dim3(256), 0, s, g); break; \
+    case 1: hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, 0, 1, TK_>), grid, dim3(256), 0, s, g); break; \
+    case 2: hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, 0, 2, TK_>), grid, dim3(256), 0, s, g); break; \
+    case 3: hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, 1, 0, TK_>), grid, dim3(256), 0, s, g); break; \
+    case 4: hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, 1, 1, TK_>), grid, dim3(256), 0, s, g); break; \
+    case 5: hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, 1, 2, TK_>), grid, dim3(256), 0, s, g); break; \
+    case 6: hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, 2, 0, TK_>), grid, dim3(256), 0, s, g); break; \
+    case 7: hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, 2, 1, TK_>), grid, dim3(256), 0, s, g); break; \
+    default: hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, 2, 2, TK_>), grid, dim3(256), 0, s, g); break; \
+  }
+#define PW_GEMM_CASES(BM_, BN_)    \
+  if (tk == 64) {                  \
+    PW_GEMM_MODES(BM_, BN_, 64)    \
+  } else {                         \
+    PW_GEMM_MODES(BM_, BN_, 32)    \
   }
   if (tm == 128 && tn == 128) {
     PW_GEMM_CASES(128, 128)
@@ -627,6 +642,7 @@ pw_status pw_mlp_gemm(const uint16_t* A, int64_t a_m, int64_t a_k, const uint16_
     PW_GEMM_CASES(64, 64)
   }
 #undef PW_GEMM_CASES
+#undef PW_GEMM_MODES
   PW_HIP(hipGetLastError());
   return PW_OK;
 }
