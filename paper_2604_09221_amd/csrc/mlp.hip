@@ -79,55 +79,73 @@ struct GemmArgs {
 // One ROWS x TK slab of an operand X (element (r, k) at X[r s_row + k s_k])
 // moves HBM -> registers -> LDS tile T[ROWS][LDK] in 16-byte chunks.
 // MODE 1: contiguous along k (s_k == 1): a chunk is 8 consecutive k of one
-// row.  MODE 2: contiguous along r (s_row == 1): a chunk is 8 consecutive
-// rows of one k, scattered into 8 LDS rows.  MODE 0: element by element.
+// row.  MODE 2: contiguous along r (s_row == 1): chunks of 8 consecutive
+// rows of one k, four k at a time, transposed in registers (below).  MODE
+// 0: element by element.
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));  // 8 bf16
-
-__device__ __forceinline__ uint16_t half_of(const u32x4_t& q, int e) {
-  return (uint16_t)(q[e >> 1] >> (16 * (e & 1)));
-}
 
 template <int ROWS, int MODE, int TK>
 struct Slab {
   static constexpr int CHUNKS = ROWS * TK / 8 / 256;  // per thread
   static constexpr int CPR = TK / 8;                  // 16-byte chunks per row
   static constexpr int LDK = TK + 8;                  // padded LDS row
-  u32x4_t q[CHUNKS];
+  // MODE 2: a thread takes a group of 4 k x 8 r (four 16-byte loads, one
+  // per k), transposes it in registers and stores 8 rows of 4 consecutive
+  // k (8 bytes each); consecutive lanes take consecutive k quads, so a
+  // store instruction covers whole bank rows
+  static constexpr int KQ = TK / 4, GROUPS = KQ * (ROWS / 8);
+  static_assert(MODE != 2 || GROUPS <= 256, "one group per thread");
+  static constexpr int NQ = MODE == 2 ? 4 : CHUNKS;
+  u32x4_t q[NQ];
 
   __device__ __forceinline__ void load(const uint16_t* __restrict__ X, int64_t s_row, int64_t s_k, int r0, int k0,
                                        int tid) {
+    if (MODE == 2) {
+      if (tid < GROUPS) {
+        const int k = 4 * (tid % KQ), r = 8 * (tid / KQ);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+          q[kk] = *reinterpret_cast<const u32x4_t*>(&X[(int64_t)(k0 + k + kk) * s_k + (int64_t)(r0 + r)]);
+      }
+      return;
+    }
 #pragma unroll
     for (int c = 0; c < CHUNKS; ++c) {
       const int id = tid + 256 * c;
-      if (MODE == 2) {
-        const int k = id / (ROWS / 8), r = (id % (ROWS / 8)) * 8;
-        q[c] = *reinterpret_cast<const u32x4_t*>(&X[(int64_t)(k0 + k) * s_k + (int64_t)(r0 + r)]);
+      const int r = id / CPR, k = (id % CPR) * 8;
+      if (MODE == 1) {
+        q[c] = *reinterpret_cast<const u32x4_t*>(&X[(int64_t)(r0 + r) * s_row + (int64_t)(k0 + k)]);
       } else {
-        const int r = id / CPR, k = (id % CPR) * 8;
-        if (MODE == 1) {
-          q[c] = *reinterpret_cast<const u32x4_t*>(&X[(int64_t)(r0 + r) * s_row + (int64_t)(k0 + k)]);
-        } else {
-          const uint16_t* x = &X[(int64_t)(r0 + r) * s_row + (int64_t)k0 * s_k];
+        const uint16_t* x = &X[(int64_t)(r0 + r) * s_row + (int64_t)k0 * s_k];
 #pragma unroll
-          for (int e = 0; e < 4; ++e)
-            q[c][e] = (uint32_t)x[(k + 2 * e) * s_k] | ((uint32_t)x[(k + 2 * e + 1) * s_k] << 16);
-        }
+        for (int e = 0; e < 4; ++e)
+          q[c][e] = (uint32_t)x[(k + 2 * e) * s_k] | ((uint32_t)x[(k + 2 * e + 1) * s_k] << 16);
       }
     }
   }
 
   __device__ __forceinline__ void store(uint16_t (*T)[LDK], int tid) const {
+    if (MODE == 2) {
+      if (tid < GROUPS) {
+        const int k = 4 * (tid % KQ), r = 8 * (tid / KQ);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          // row r + e: the low (e even) or high (e odd) halves of word e / 2
+          // of the four k loads, paired k, k+1 and k+2, k+3
+          const uint32_t sel = (e & 1) ? 0x07060302u : 0x05040100u;
+          uint2 d;
+          d.x = __builtin_amdgcn_perm(q[1][e >> 1], q[0][e >> 1], sel);
+          d.y = __builtin_amdgcn_perm(q[3][e >> 1], q[2][e >> 1], sel);
+          *reinterpret_cast<uint2*>(&T[r + e][k]) = d;
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int c = 0; c < CHUNKS; ++c) {
       const int id = tid + 256 * c;
-      if (MODE == 2) {
-        const int k = id / (ROWS / 8), r = (id % (ROWS / 8)) * 8;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) T[r + e][k] = half_of(q[c], e);
-      } else {
-        const int r = id / CPR, k = (id % CPR) * 8;
-        *reinterpret_cast<u32x4_t*>(&T[r][k]) = q[c];
-      }
+      const int r = id / CPR, k = (id % CPR) * 8;
+      *reinterpret_cast<u32x4_t*>(&T[r][k]) = q[c];
     }
   }
 };
