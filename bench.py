@@ -275,8 +275,8 @@ def fig2_fixed_bits(d):
 
 def bench_fig2(args):
     """Part of the exhaustive class-representative sweep of one Fig. 2
-    triangulation (d = 8, 2^42 classes): index range [part, part + 1) *
-    2^42 / parts, in launches of 2^36 masks; the histogram goes out as
+    triangulation (d = 8, 2^42 classes): index range [part * 2^42 / parts,
+    (part + 1) * 2^42 / parts), in launches of 2^36 masks; the histogram goes out as
     (code, count) pairs for merging (--config fig2-check)."""
     import torch
 
@@ -288,8 +288,7 @@ def bench_fig2(args):
     tri = pw.Triangulation(d, E).specialize()
     fz = fig2_fixed_bits(d)
     total = 1 << (45 - 3)
-    span = total // args.parts
-    first, end = args.part * span, (args.part + 1) * span
+    first, end = args.part * total // args.parts, (args.part + 1) * total // args.parts
     step = 1 << 36
     hist = pw.Histogram(4096)
     torch.cuda.synchronize()
