@@ -296,7 +296,7 @@ def bench_fig2(args):
     for a in range(first, end, step):
         tri.enumerate_range(a, min(step, end - a), hist, fixed_zero_bits=fz)
         torch.cuda.synchronize()
-        print(f"{args.tri}: {a + step - first} of {end - first} masks, {time.perf_counter() - t0:.1f} s",
+        print(f"{args.tri}: {min(a + step, end) - first} of {end - first} masks, {time.perf_counter() - t0:.1f} s",
               file=sys.stderr, flush=True)
     dt = time.perf_counter() - t0
     h = hist.read()
