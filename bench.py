@@ -218,9 +218,31 @@ def bench_learned(args):
         r["distinct_within_uniform_seconds"] = r.pop("distinct_within_time_budget")
     for r in res:
         r["distinct_per_gpu_second_equal_time"] = r["distinct_within_uniform_seconds"] / t_uniform
-    # roofline of the dominant contraction: the 512 x 512 hidden layer of the
-    # forward pass (k_gemm_bf16, 128 x 128 tiles), timed with HIP events on
-    # the stream it runs on
+    roof = gemm_roofline()
+    return {
+        "metric": "distinct real schemes found per GPU-second at d=8",
+        "value": res[1]["distinct_per_gpu_second_equal_time"], "unit": "schemes/s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16+u64",
+        "data": "synthetic",
+        "config": {"workload": f"d=8 standard triangulation, {budget} judged masks per method",
+                   "value": "learned proposal: distinct schemes seen within the GPU time uniform sampling takes for "
+                            "the whole budget, per GPU-second (equal-time); uniform's equal-time rate: "
+                            f"{res[0]['distinct_per_gpu_second_equal_time']:.1f}; each method's rate over its own "
+                            "whole budget: distinct_per_gpu_second in results",
+                   "results": res},
+        "roofline": roof,
+    }
+
+
+def gemm_roofline():
+    """Roofline of the learned proposal's dominant contraction: the 512 x 512
+    hidden layer of the forward pass (k_gemm_bf16, 128 x 128 tiles, bias +
+    ReLU epilogue, bf16 out) on 2^18 rows, timed with HIP events on the
+    stream it runs on (20 launches after 3 warm-up launches)."""
+    import torch
+
+    from paper_2604_09221_amd import learn as Lr
+
     rows = 1 << 18
     net = Lr.MLP(n_in=45, seed=1)
     H1 = torch.zeros((rows, Lr.HIDDEN), dtype=torch.int16, device="cuda")
@@ -242,22 +264,10 @@ def bench_learned(args):
     torch.cuda.synchronize()
     gemm_s = e0.elapsed_time(e1) / 1e3 / reps
     flops = 2.0 * rows * Lr.HIDDEN * Lr.HIDDEN
-    return {
-        "metric": "distinct real schemes found per GPU-second at d=8",
-        "value": res[1]["distinct_per_gpu_second_equal_time"], "unit": "schemes/s", "n_gpus": 1, "steps": 1,
-        "warmup": 0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16+u64",
-        "data": "synthetic",
-        "config": {"workload": f"d=8 standard triangulation, {budget} judged masks per method",
-                   "value": "learned proposal: distinct schemes seen within the GPU time uniform sampling takes for "
-                            "the whole budget, per GPU-second (equal-time); uniform's equal-time rate: "
-                            f"{res[0]['distinct_per_gpu_second_equal_time']:.1f}; each method's rate over its own "
-                            "whole budget: distinct_per_gpu_second in results",
-                   "results": res},
-        "roofline": {"bound": "mfma", "achieved": flops / gemm_s / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
-                     "frac": flops / gemm_s / 2.5e15, "traffic": None,
-                     "kernel": "pw::k_gemm_bf16<128,128> (hidden layer 512x512, forward, 2^18 rows)",
-                     "avg_launch_ms": gemm_s * 1e3},
-    }
+    return {"bound": "mfma", "achieved": flops / gemm_s / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
+            "frac": flops / gemm_s / 2.5e15, "traffic": None,
+            "kernel": "pw::k_gemm_bf16<128,128> (hidden layer 512x512, forward, 2^18 rows)",
+            "avg_launch_ms": gemm_s * 1e3}
 
 
 FIG2 = {"bow_tie": 123, "rank016": 359, "rank015": 353}  # distinct real schemes printed with Fig. 2
@@ -344,7 +354,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=1 << 24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--config", choices=("d7", "multi", "learned", "copyprobe", "fig2", "fig2-check"), default="d7")
+    ap.add_argument("--config", choices=("d7", "multi", "learned", "gemm", "copyprobe", "fig2", "fig2-check"),
+                    default="d7")
     ap.add_argument("--tri", choices=sorted(FIG2), default="rank016", help="--config fig2: the triangulation")
     ap.add_argument("--part", type=int, default=0, help="--config fig2: which part of the sweep")
     ap.add_argument("--parts", type=int, default=2, help="--config fig2: parts of the 2^42 sweep")
@@ -360,6 +371,13 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(sharding is one histogram merge; see the design notes).", file=sys.stderr)
         sys.exit(2)
+    if args.config == "gemm":
+        import torch
+
+        torch.cuda.set_device(0)
+        print(json.dumps({"metric": "bf16 GEMM throughput (learned proposal's hidden layer)",
+                          "roofline": gemm_roofline()}), flush=True)
+        return
     if args.config == "fig2-check":
         print(json.dumps(fig2_check(args.inputs)), flush=True)
         return
