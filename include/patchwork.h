@@ -180,6 +180,24 @@ pw_status patchwork_scheme_enumerate_range(pw_tri_t tri, uint64_t first, uint64_
                                            hipStream_t stream);
 
 /*
+ * The same histogram as patchwork_scheme_enumerate_range(first, count), as
+ * a chunked sweep: ceil(count / chunk) launches of at most `chunk` masks
+ * each, captured once into a HIP graph and launched as one graph on
+ * `stream` (a sweep issued in many short launches pays one host submission
+ * instead of one per launch; Sec. 3 exhaustive search at scale).  The
+ * triangulation handle owns the graph and keeps it for the last argument
+ * set (first, count, chunk, fixed bits, hist): calling again with the same
+ * arguments launches the kept graph again (the histogram accumulates once
+ * more), other arguments capture a new one.  Capture happens on a stream of
+ * the handle's own, so `stream` may be the default stream.  Errors: as
+ * patchwork_scheme_enumerate_range, plus PW_ERR_ARG for chunk == 0 or more
+ * than 2^16 launches, PW_ERR_HIP if the capture fails.  Not for concurrent
+ * use of one handle from several threads.
+ */
+pw_status patchwork_scheme_sweep_graph(pw_tri_t tri, uint64_t first, uint64_t count, uint64_t chunk,
+                                       const uint64_t fixed_zero_bits[2], pw_hist_t hist, hipStream_t stream);
+
+/*
  * Many triangulations of uneven degree in one persistent launch (Sec. 3:
  * the second search mode sweeps many triangulations; kernel dispatch and
  * histogram aggregation are the costs at scale).

@@ -18,6 +18,11 @@ struct pw_tri {
   hipModule_t jit_mod = nullptr;
   hipFunction_t jit_codes = nullptr, jit_hist = nullptr, jit_enum = nullptr;
   hipFunction_t jit_enum_snap = nullptr;  // sweep kernel with a shared snapshot, or null
+  // the chunked sweep captured by patchwork_scheme_sweep_graph, its
+  // arguments and the stream it is captured on
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t sweep_exec = nullptr;
+  uint64_t sweep_key[6] = {0, 0, 0, 0, 0, 0};
 };
 
 struct pw_hist {

@@ -242,6 +242,8 @@ pw_status pw_tri_create(int32_t d, const int16_t* edges_ij, int32_t n_edges, pw_
 
 pw_status pw_tri_destroy(pw_tri_t t) {
   if (!t) return PW_OK;
+  if (t->sweep_exec) (void)hipGraphExecDestroy(t->sweep_exec);
+  if (t->cap_stream) (void)hipStreamDestroy(t->cap_stream);
   if (t->jit_mod) (void)hipModuleUnload(t->jit_mod);
   (void)hipFree(t->d_prog);
   (void)hipFree(t->d_err);
@@ -382,11 +384,10 @@ pw_status patchwork_scheme_histogram(pw_tri_t t, const void* masks, int64_t n, u
   PW_DISPATCH(t->prog.d, launch_hist, t, masks, n, index_base, h, s);
 }
 
-pw_status patchwork_scheme_enumerate_range(pw_tri_t t, uint64_t first, uint64_t count,
-                                           const uint64_t fixed_zero_bits[2], pw_hist_t h, hipStream_t s) {
-  if (!t || !h || !fixed_zero_bits) return set_err(PW_ERR_ARG, "null argument");
+// The runs of free bits for an enumeration and the check of its range.
+static pw_status enum_plan(const pw_tri* t, uint64_t first, uint64_t count, const uint64_t fixed_zero_bits[2], Runs& runs) {
   const int nA = t->prog.nA;
-  Runs runs{};
+  runs = Runs{};
   int nfree = 0;
   for (int b = 0; b < nA;) {
     const bool fixed = (fixed_zero_bits[b / 64] >> (b % 64)) & 1;
@@ -418,7 +419,59 @@ pw_status patchwork_scheme_enumerate_range(pw_tri_t t, uint64_t first, uint64_t 
   } else if (first + count < first) {
     return set_err(PW_ERR_RANGE, "range wraps around 2^64");
   }
+  return PW_OK;
+}
+
+pw_status patchwork_scheme_enumerate_range(pw_tri_t t, uint64_t first, uint64_t count,
+                                           const uint64_t fixed_zero_bits[2], pw_hist_t h, hipStream_t s) {
+  if (!t || !h || !fixed_zero_bits) return set_err(PW_ERR_ARG, "null argument");
+  Runs runs{};
+  const pw_status st = enum_plan(t, first, count, fixed_zero_bits, runs);
+  if (st != PW_OK || count == 0) return st;
   PW_DISPATCH(t->prog.d, launch_enum, t, first, count, runs, h, s);
+}
+
+pw_status patchwork_scheme_sweep_graph(pw_tri_t t, uint64_t first, uint64_t count, uint64_t chunk,
+                                       const uint64_t fixed_zero_bits[2], pw_hist_t h, hipStream_t s) {
+  if (!t || !h || !fixed_zero_bits) return set_err(PW_ERR_ARG, "null argument");
+  if (chunk == 0) return set_err(PW_ERR_ARG, "chunk must be positive");
+  if (count == 0) return PW_OK;
+  const uint64_t launches = (count - 1) / chunk + 1;
+  if (launches > (1u << 16)) return set_err(PW_ERR_ARG, "%llu launches (at most 65536)", (unsigned long long)launches);
+  const uint64_t key[6] = {first, count, chunk, fixed_zero_bits[0], fixed_zero_bits[1], (uint64_t)(uintptr_t)h};
+  if (!t->sweep_exec || std::memcmp(key, t->sweep_key, sizeof key) != 0) {
+    if (t->sweep_exec) {
+      PW_HIP(hipGraphExecDestroy(t->sweep_exec));
+      t->sweep_exec = nullptr;
+    }
+    if (!t->cap_stream) PW_HIP(hipStreamCreateWithFlags(&t->cap_stream, hipStreamNonBlocking));
+    // the range is checked before the capture (a launch failing inside it
+    // would leave no graph)
+    Runs runs{};
+    pw_status st = enum_plan(t, first, count, fixed_zero_bits, runs);
+    if (st != PW_OK) return st;
+    PW_HIP(hipStreamBeginCapture(t->cap_stream, hipStreamCaptureModeRelaxed));
+    for (uint64_t a = 0; a < count && st == PW_OK; a += chunk) {
+      const uint64_t n = count - a < chunk ? count - a : chunk;
+      st = patchwork_scheme_enumerate_range(t, first + a, n, fixed_zero_bits, h, t->cap_stream);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(t->cap_stream, &g);
+    if (st != PW_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return set_err(PW_ERR_HIP, "hipStreamEndCapture: %s (code %d)", hipGetErrorString(e), (int)e);
+    const hipError_t ei = hipGraphInstantiate(&t->sweep_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      t->sweep_exec = nullptr;
+      return set_err(PW_ERR_HIP, "hipGraphInstantiate: %s (code %d)", hipGetErrorString(ei), (int)ei);
+    }
+    std::memcpy(t->sweep_key, key, sizeof key);
+  }
+  PW_HIP(hipGraphLaunch(t->sweep_exec, s));
+  return PW_OK;
 }
 
 }  // extern "C"

@@ -66,6 +66,7 @@ def lib():
     L.pw_hist_destroy.argtypes = [vp]
     L.patchwork_scheme_histogram.argtypes = [vp, vp, i64, u64, vp, vp]
     L.patchwork_scheme_enumerate_range.argtypes = [vp, u64, u64, u64p, vp, vp]
+    L.patchwork_scheme_sweep_graph.argtypes = [vp, u64, u64, u64, u64p, vp, vp]
     L.pw_tri_specialize.argtypes = [vp]
     i16p = ctypes.POINTER(ctypes.c_int16)
     L.pw_jit_source.argtypes = [i32, i16p, i32, ctypes.c_char_p, i64, ctypes.POINTER(ctypes.c_int64)]
@@ -74,7 +75,8 @@ def lib():
                                                ctypes.POINTER(vp), vp, ctypes.POINTER(MultiConfig), vp]
     for name in ("pw_tri_create", "pw_tri_destroy", "pw_tri_info", "pw_tri_errors", "patchwork_scheme_batch",
                  "pw_hist_create", "pw_hist_reset", "pw_hist_read", "pw_hist_destroy",
-                 "patchwork_scheme_histogram", "patchwork_scheme_enumerate_range", "patchwork_scheme_batch_multi",
+                 "patchwork_scheme_histogram", "patchwork_scheme_enumerate_range", "patchwork_scheme_sweep_graph",
+                 "patchwork_scheme_batch_multi",
                  "pw_tri_specialize", "pw_jit_source", "pw_jit_compile"):
         getattr(L, name).restype = i32
     _lib = L
@@ -185,6 +187,14 @@ class Triangulation:
         fz = (ctypes.c_uint64 * 2)(fixed_zero_bits & 0xFFFFFFFFFFFFFFFF, fixed_zero_bits >> 64)
         check(lib().patchwork_scheme_enumerate_range(self.handle, int(first), int(count), fz, hist.handle,
                                                      _stream(stream)))
+
+    def sweep_graph(self, first: int, count: int, chunk: int, hist: "Histogram", fixed_zero_bits: int = 1,
+                    stream=None):
+        """enumerate_range as a chunked sweep captured into a HIP graph
+        (kept by the handle and launched again for the same arguments)."""
+        fz = (ctypes.c_uint64 * 2)(fixed_zero_bits & 0xFFFFFFFFFFFFFFFF, fixed_zero_bits >> 64)
+        check(lib().patchwork_scheme_sweep_graph(self.handle, int(first), int(count), int(chunk), fz, hist.handle,
+                                                 _stream(stream)))
 
 
 def _edges16(edges):

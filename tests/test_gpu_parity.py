@@ -242,6 +242,44 @@ def test_edge_cases(pw):
     assert tri.errors() == 0
 
 
+# ------------------------------------------------- graph-captured chunked sweep
+
+def test_sweep_graph_replays_match_eager(pw):
+    """patchwork_scheme_sweep_graph: a range swept in chunks through a HIP
+    graph gives the eager histogram; the kept graph launched again adds the
+    same counts (three launches, with eager work and synchronisation in
+    between, each checked), and new arguments capture a new graph."""
+    for d, spec in ((7, True), (6, False)):
+        E = I.standard_triangulation(d)
+        tri = pw.Triangulation(d, E)
+        if spec:
+            tri.specialize()
+        first, n, chunk = 777, (1 << 18) + 4321, 1 << 15
+        h_eager = pw.Histogram(512)
+        tri.enumerate_range(first, n, h_eager)
+        want = h_eager.read()
+        ref = oracle_hist(oracle.scheme_many(d, E, enum_masks(first, n, nA=I.n_points(d)), threads=THREADS),
+                          index_of=np.arange(first, first + n, dtype=np.uint64))
+        assert want == ref
+        h = pw.Histogram(512)
+        for rep in range(1, 4):
+            tri.sweep_graph(first, n, chunk, h)
+            torch.cuda.synchronize()
+            got = h.read()
+            assert got == {c: (k * rep, w) for c, (k, w) in want.items()}
+            tri.enumerate_range(0, 1000, pw.Histogram(64))     # eager work between the launches
+            torch.cuda.synchronize()
+        h2 = pw.Histogram(512)
+        tri.sweep_graph(first + 5, 2 * chunk + 1, chunk, h2)   # other arguments: a new capture
+        torch.cuda.synchronize()
+        h3 = pw.Histogram(512)
+        tri.enumerate_range(first + 5, 2 * chunk + 1, h3)
+        assert h2.read() == h3.read()
+        with pytest.raises(RuntimeError):
+            tri.sweep_graph(first, n, 0, h)
+        assert tri.errors() == 0
+
+
 # ------------------------------------------------- specialised kernels (hipRTC)
 
 def test_class_representative_sweep(pw):
