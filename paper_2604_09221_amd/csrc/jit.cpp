@@ -5,11 +5,15 @@
 // evaluation of Alg. 1 for that triangulation as straight-line code -- one
 // block per diamond vertex with its earlier neighbours and its spanning-tree
 // parent as literals, one call per antipodal pair -- compiles it with hipRTC
-// for gfx950 and loads it.  The steps it calls (Eval<D>::edge, pair, vertex3,
-// finish) and the kernel bodies are the same device functions the generic
-// kernels use; only the walk over the program is unrolled, so every LDS
-// offset becomes an immediate and no scalar decoding or loop control is
-// left.
+// for gfx950 and loads it.  The steps it calls (Eval<D>::edge_r, pair,
+// vertex3e, finish) and the kernel bodies are the same device functions the
+// generic kernels use; only the walk over the program is unrolled, so every
+// LDS offset becomes an immediate and no scalar decoding or loop control is
+// left.  For sweeps with only sigma(0,0) fixed it also writes the sweep
+// evaluator JitSnap: a snapshot of the fixed-sign part shared by the wave
+// per chunk of 512 masks (built by label propagation over a per-triangulation
+// link table), wave-uniform flags derived from it, and the per-batch work on
+// the 9 varying lattice bits.
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
