@@ -150,8 +150,13 @@ struct Slab {
   }
 };
 
+// (compiled for 3 waves per SIMD -- at most 168 registers -- when both
+// operands move in 16-byte chunks: those tiles fit without spilling, and two
+// waves left the matrix cores idle more often; the element-wise staging of
+// unaligned operands keeps 2)
 template <int BM, int BN, int AM, int BM_, int TK>
-__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((AM != 0 && BM_ != 0) ? 3 : 2))) void k_gemm_bf16(
+    GemmArgs g) {
   constexpr int FM = BM / 32, FN = BN / 32;  // 16 x 16 tiles per wave along m and n
   constexpr int LDK = TK + 8;
   __shared__ __attribute__((aligned(16))) uint16_t As[BM][LDK];  // [m][k]
