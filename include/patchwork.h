@@ -198,9 +198,9 @@ pw_status patchwork_scheme_sweep_graph(pw_tri_t tri, uint64_t first, uint64_t co
                                        const uint64_t fixed_zero_bits[2], pw_hist_t hist, hipStream_t stream);
 
 /*
- * Many triangulations of uneven degree in one persistent launch (Sec. 3:
- * the second search mode sweeps many triangulations; kernel dispatch and
- * histogram aggregation are the costs at scale).
+ * Many triangulations of uneven degree in one call (Sec. 3: the second
+ * search mode sweeps many triangulations; kernel dispatch and histogram
+ * aggregation are the costs at scale).
  *   tris      n_tris handles (host array), any mix of degrees.
  *   d_masks   one array of 128-bit masks (two uint64 per mask, whatever the
  *             degree); triangulation t owns masks [offsets[t], offsets[t+1]).
@@ -210,11 +210,15 @@ pw_status patchwork_scheme_sweep_graph(pw_tri_t tri, uint64_t first, uint64_t co
  *   d_codes   NULL, or n x 2 uint64 codes written at the masks' positions.
  *   cfg       NULL for the defaults, or the tuned launch shape: masks per
  *             work item, waves per block (lowered until a block's LDS for
- *             the largest degree fits in 160 KiB), blocks per CU (0 = as
- *             many as the LDS allows).
- * Work items (chunks of one triangulation's masks) are taken from an atomic
- * queue in decreasing order of cost.  The call returns after the launch has
- * finished (its device tables are reused by the next call).
+ *             the largest degree of its class fits in 160 KiB), blocks per
+ *             CU (0 = as many as LDS and registers allow).
+ * Degrees are grouped into LDS classes (those whose per-wave areas allow
+ * the same number of resident blocks per CU); each class is one persistent
+ * launch, sized for its largest degree, and the launches run back to back
+ * on `stream`.  Within a launch, work items (chunks of one triangulation's
+ * masks) are taken from an atomic queue in decreasing order of cost.  The
+ * call returns after the last launch has finished (its device tables are
+ * reused by the next call).
  */
 typedef struct {
   int32_t chunk;

@@ -1,15 +1,18 @@
-// multi.hip -- one persistent launch over many triangulations of uneven
+// multi.hip -- persistent launches over many triangulations of uneven
 // degree (Sec. 3: the second search mode checks many triangulations against
 // sign distributions; the paper names kernel dispatch and histogram
 // aggregation as the costs at scale).
 //
-// The host cuts every triangulation's mask list into chunks, orders the
-// chunks by decreasing cost (chunk length x |E(T<>)|, longest processing
-// time first) and uploads them.  Resident waves take chunks from an atomic
-// ticket counter until none is left; each chunk is evaluated with the
-// degree-specialised Eval<D> and aggregated in the wave's register table,
-// which is flushed to that triangulation's histogram when the chunk ends.
-// The ticket counter only grows, so no launch ever has to reset it.
+// The host cuts every triangulation's mask list into chunks, groups the
+// chunks by LDS class (degrees whose per-wave areas allow the same number
+// of resident waves per CU), orders each group by decreasing cost (chunk
+// length x |E(T<>)|, longest processing time first) and uploads them.  Per
+// class one persistent launch, its LDS sized for the class's largest
+// degree: resident waves take chunks from an atomic ticket counter until
+// none is left; each chunk is evaluated with the degree-specialised Eval<D>
+// and aggregated in the wave's register table, which is flushed to that
+// triangulation's histogram when the chunk ends.  The ticket counter only
+// grows, so no launch ever has to reset it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -223,7 +226,6 @@ extern "C" pw_status patchwork_scheme_batch_multi(const pw_tri_t* tris, int32_t 
                    c.blocks_per_cu);
   std::vector<TriDesc> desc(n_tris);
   std::vector<Item> items;
-  int max_words = 0;
   for (int t = 0; t < n_tris; ++t) {
     if (!tris[t]) return set_err(PW_ERR_ARG, "null triangulation %d", t);
     if (offsets[t + 1] < offsets[t] || offsets[t] < 0) return set_err(PW_ERR_ARG, "offsets must not decrease");
@@ -234,14 +236,67 @@ extern "C" pw_status patchwork_scheme_batch_multi(const pw_tri_t* tris, int32_t 
     desc[t].hist = hists ? hists[t]->d_dev : nullptr;
     desc[t].d = d;
     desc[t].use_hist = hists ? 1 : 0;
-    max_words = std::max(max_words, lane_words_for(d));
     for (int64_t b = offsets[t]; b < offsets[t + 1]; b += c.chunk)
       items.push_back(Item{t, 0, b, std::min<int64_t>(c.chunk, offsets[t + 1] - b)});
   }
   if (items.empty()) return PW_OK;
   if (!d_masks) return set_err(PW_ERR_ARG, "null mask buffer");
-  // longest processing time first: cost ~ chunk length x diamond edges
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_multi),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (attr != hipSuccess) {
+    (void)hipGetLastError();
+    return set_err(PW_ERR_HIP, "hipFuncSetAttribute: %s (code %d)", hipGetErrorString(attr), (int)attr);
+  }
+  // One launch per LDS class.  A wave's area has to hold the largest degree
+  // it may meet, so a single launch would give every wave the area of the
+  // largest degree present (3 waves per CU at d = 12).  Degrees whose own
+  // areas allow the same number of resident blocks per CU (LDS, registers
+  // and the configured cap) share a launch sized for the largest of them;
+  // the launches follow each other on the stream.
+  struct Shape {
+    int words, wpb, per_cu;
+  };
+  auto shape_for = [&](int words) {
+    Shape s{words, c.waves_per_block, 1};
+    while (s.wpb > 1 && (size_t)words * 256 * s.wpb > 160 * 1024) --s.wpb;
+    const size_t lds = (size_t)words * 256 * s.wpb;
+    int per_cu = (int)((160 * 1024) / lds);
+    int by_regs = 0;  // resident blocks allowed by the register budget alone
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&by_regs, reinterpret_cast<const void*>(&k_multi), 64 * s.wpb,
+                                                     0) == hipSuccess) {
+      if (by_regs > 0) per_cu = std::min(per_cu, by_regs);
+    } else {
+      (void)hipGetLastError();
+    }
+    if (c.blocks_per_cu > 0) per_cu = std::min(per_cu, c.blocks_per_cu);
+    s.per_cu = std::max(1, std::min(per_cu, 32 / s.wpb));
+    return s;
+  };
+  int cls_of_deg[13];
+  std::vector<Shape> cls;
+  for (int d = 1; d <= 12; ++d) cls_of_deg[d] = -1;
+  for (const TriDesc& t : desc) {
+    if (t.d < 1 || t.d > 12) return set_err(PW_ERR_ARG, "degree %d outside 1..12", t.d);
+    if (cls_of_deg[t.d] >= 0) continue;
+    const Shape s = shape_for(lane_words_for(t.d));
+    if ((size_t)s.words * 256 * s.wpb > 160 * 1024)
+      return set_err(PW_ERR_ARG, "block needs %zu bytes of LDS", (size_t)s.words * 256 * s.wpb);
+    int k = 0;
+    while (k < (int)cls.size() && (cls[k].per_cu != s.per_cu || cls[k].wpb != s.wpb)) ++k;
+    if (k == (int)cls.size()) cls.push_back(s);
+    cls[k].words = std::max(cls[k].words, s.words);
+    cls_of_deg[t.d] = k;
+  }
+  // longest processing time first within a class: cost ~ chunk length x
+  // diamond edges; classes with the largest areas go first
+  std::vector<int> order(cls.size());
+  for (size_t k = 0; k < cls.size(); ++k) order[k] = (int)k;
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return cls[a].words > cls[b].words; });
+  std::vector<int> rank(cls.size());
+  for (size_t k = 0; k < order.size(); ++k) rank[order[k]] = (int)k;
   std::stable_sort(items.begin(), items.end(), [&](const Item& a, const Item& b) {
+    const int ra = rank[cls_of_deg[desc[a.tri].d]], rb = rank[cls_of_deg[desc[b.tri].d]];
+    if (ra != rb) return ra < rb;
     const int64_t ca = a.count * n_diamond_edges(desc[a.tri].d), cb = b.count * n_diamond_edges(desc[b.tri].d);
     return ca > cb;
   });
@@ -273,29 +328,28 @@ extern "C" pw_status patchwork_scheme_batch_multi(const pw_tri_t* tris, int32_t 
   // copies before returning so the host vectors may go away
   PW_HIP(hipMemcpyAsync(S.d_tris, desc.data(), sizeof(TriDesc) * desc.size(), hipMemcpyHostToDevice, stream));
   PW_HIP(hipMemcpyAsync(S.d_items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice, stream));
-  // fewer waves per block if the largest degree's LDS does not fit
-  while (c.waves_per_block > 1 && (size_t)max_words * 4 * 64 * c.waves_per_block > 160 * 1024) --c.waves_per_block;
-  const int threads = 64 * c.waves_per_block;
-  const size_t lds = (size_t)max_words * 4 * 64 * c.waves_per_block;
-  if (lds > 160 * 1024) return set_err(PW_ERR_ARG, "block needs %zu bytes of LDS", lds);
-  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_multi),
-                                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  if (attr != hipSuccess) {
-    (void)hipGetLastError();
-    return set_err(PW_ERR_HIP, "hipFuncSetAttribute: %s (code %d)", hipGetErrorString(attr), (int)attr);
-  }
-  int per_cu = (int)((160 * 1024) / lds);
-  if (c.blocks_per_cu > 0) per_cu = std::min(per_cu, c.blocks_per_cu);
-  per_cu = std::max(1, std::min(per_cu, 32 / c.waves_per_block));
-  const int64_t blocks = std::min<int64_t>((int64_t)cu_count() * per_cu, (int64_t)items.size());
-  const unsigned long long base = S.issued;
-  // every block takes one ticket past the end before it stops
-  S.issued += items.size() + (unsigned long long)blocks * c.waves_per_block;
   const Overflow ov{S.d_over, S.d_over_n, kOverflowCap};
-  hipLaunchKernelGGL(k_multi, dim3((unsigned)blocks), dim3(threads), lds, stream, S.d_tris, S.d_items,
-                     (int64_t)items.size(), S.d_ticket, base, static_cast<const uint64_t*>(d_masks), d_codes,
-                     max_words, ov);
-  PW_HIP(hipGetLastError());
+  size_t first = 0;
+  for (const int k : order) {
+    size_t last = first;
+    while (last < items.size() && cls_of_deg[desc[items[last].tri].d] == k) ++last;
+    const int64_t n = (int64_t)(last - first);
+    if (n == 0) continue;  // a class whose triangulations have no masks
+    const Shape& s = cls[k];
+    const size_t lds = (size_t)s.words * 256 * s.wpb;
+    const int64_t blocks = std::min<int64_t>((int64_t)cu_count() * s.per_cu, (n + s.wpb - 1) / s.wpb);
+    const unsigned long long base = S.issued;
+    // every wave takes one ticket past the end of its launch before it stops
+    S.issued += (unsigned long long)n + (unsigned long long)blocks * s.wpb;
+    hipLaunchKernelGGL(k_multi, dim3((unsigned)blocks), dim3(64 * s.wpb), lds, stream, S.d_tris, S.d_items + first,
+                       n, S.d_ticket, base, static_cast<const uint64_t*>(d_masks), d_codes, s.words, ov);
+    const hipError_t le = hipGetLastError();
+    if (le != hipSuccess) {
+      S.issued = base;  // a launch that failed took no tickets
+      return set_err(PW_ERR_HIP, "k_multi launch: %s (code %d)", hipGetErrorString(le), (int)le);
+    }
+    first = last;
+  }
   unsigned long long n_over = 0;
   PW_HIP(hipMemcpyAsync(&n_over, S.d_over_n, sizeof n_over, hipMemcpyDeviceToHost, stream));
   PW_HIP(hipStreamSynchronize(stream));

@@ -260,7 +260,8 @@ class Histogram:
 
 
 def batch_multi(tris, masks128, offsets, hists=None, codes=None, config=None, stream=None):
-    """One persistent launch over many triangulations (any mix of degrees).
+    """Many triangulations (any mix of degrees) in one call: one persistent
+    launch per LDS class of degrees, back to back on the stream.
 
     masks128: device int64 tensor holding two words per mask; triangulation
     t owns masks [offsets[t], offsets[t+1]).  hists: list of Histogram (one

@@ -91,6 +91,18 @@ def test_multi_literal_lift_slots_and_edge_cases(pw):
     assert np.array_equal(got2[a:b], oracle.scheme_many(int(degs[4]), edges[4], allm[a:b], threads=8))
     assert np.array_equal(got2[b:], got[b:])
     assert np.array_equal(got2[:a], got[:a])
+    # a call in which only slot 5 has masks: the launches of the other
+    # degrees' LDS classes have no items and are skipped
+    off4 = offsets.copy()
+    off4[:6] = offsets[5]
+    off4[6:] = offsets[6]
+    assert len({int(d) for d in degs}) > 1
+    codes4 = torch.zeros_like(codes)
+    pw.batch_multi(tris, mt, off4, codes=codes4)
+    got4 = codes4.cpu().numpy().view(np.uint64)
+    a, b = int(offsets[5]), int(offsets[6])
+    assert np.array_equal(got4[a:b], got[a:b])
+    assert not got4[:a].any() and not got4[b:].any()
     # ... decreasing offsets are not
     off3 = offsets.copy()
     off3[3] = off3[2] - 1
