@@ -15,7 +15,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.environ.get("PW_TUNE", os.path.join(HERE, "tune_cache_gfx950.json"))
 
-CHUNKS = (1024, 4096, 16384)
+CHUNKS = (1024, 2048, 4096, 16384)
 WAVES = (1, 2)
 BLOCKS_PER_CU = (0, 2)
 
