@@ -1,5 +1,5 @@
-"""GPU parity of the persistent multi-triangulation launch
-(patchwork_scheme_batch_multi): uneven degrees 4..12 in one launch, codes
+"""GPU parity of the batched multi-triangulation call
+(patchwork_scheme_batch_multi): uneven degrees 4..12 in one call, codes
 bit-exact against the oracle, per-triangulation histograms equal to the
 codes' histograms, and identical tables under different launch shapes."""
 from __future__ import annotations
@@ -150,3 +150,43 @@ def test_multi_many_regions_take_the_overflow_path(pw):
         if d >= 10:
             many += sum(oracle.n_ovals(int(lo) | (int(hi) << 64)) + 1 > 32 for lo, hi in want)
     assert many > 100   # the overflow path did run
+
+
+def test_multi_full_size_sampled(pw):
+    """The batched workload at full size, in the launch shape the benchmark
+    uses (the tuned shape for this degree mix): 4096 triangulations of
+    degrees 4..12 (literal lifts, seeds 0..4095), 2^16 generated masks each,
+    codes and per-triangulation histograms in one call.  Three masks per
+    triangulation (first, last, one inside) are checked against the oracle;
+    on a sample of triangulations the histogram counts every mask, holds each
+    sampled code, and names a witness no later than the sampled mask."""
+    import bench
+    from paper_2604_09221_amd import learn as Lr
+
+    n_tris, per = 4096, 1 << 16
+    degs = I.batched_degrees(n_tris, 0)
+    edges = [I.lift_triangulation(int(d), t, noise=0.05) for t, d in enumerate(degs)]
+    tris = [pw.Triangulation(int(d), E) for d, E in zip(degs, edges)]
+    masks = torch.empty((n_tris * per, 2), dtype=torch.int64, device="cuda")
+    for t, d in enumerate(degs):
+        masks[t * per:(t + 1) * per] = Lr.random_masks(t, 0, per, I.n_points(int(d)))
+    offsets = np.arange(n_tris + 1, dtype=np.int64) * per
+    hists = [pw.Histogram(bench.hist_capacity(int(d))) for d in degs]
+    codes = torch.zeros((n_tris * per, 2), dtype=torch.int64, device="cuda")
+    pw.batch_multi(tris, masks.view(-1), offsets, hists=hists, codes=codes)
+    rng = np.random.default_rng(5)
+    inner = rng.integers(1, per - 1, size=n_tris)
+    idx = np.stack([offsets[:-1], offsets[:-1] + inner, offsets[1:] - 1], axis=1)
+    sel = torch.from_numpy(idx.reshape(-1)).cuda()
+    got = codes[sel].cpu().numpy().view(np.uint64).reshape(n_tris, 3, 2)
+    m = masks[sel].cpu().numpy().view(np.uint64).reshape(n_tris, 3, 2)
+    for t, d in enumerate(degs):
+        want = oracle.scheme_many(int(d), edges[t], m[t])
+        assert np.array_equal(got[t], want), (t, int(d))
+        assert tris[t].errors() == 0
+    for t in rng.choice(n_tris, 48, replace=False):
+        h = hists[t].read()
+        assert sum(c for c, _ in h.values()) == per, t
+        for j in range(3):
+            code = int(got[t, j, 0]) | (int(got[t, j, 1]) << 64)
+            assert code in h and h[code][1] <= idx[t, j], (t, j)
