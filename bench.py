@@ -46,29 +46,35 @@ KERNEL_SOURCES = ("paper_2604_09221_amd/csrc/pw_device.h", "paper_2604_09221_amd
                   "paper_2604_09221_amd/csrc/jit.cpp", "paper_2604_09221_amd/csrc/scheme.hip",
                   "paper_2604_09221_amd/csrc/tri.cpp")
 TRAFFIC_PROFILE = "profiles/pw_jit_enum_snap_d7_sweep_counters.md"
+# the same for the batched call (its kernel, the program builder and the
+# tuned launch shape, which sets the number of histogram flushes)
+MULTI_SOURCES = ("paper_2604_09221_amd/csrc/pw_device.h", "paper_2604_09221_amd/csrc/pw_internal.h",
+                 "paper_2604_09221_amd/csrc/multi.hip", "paper_2604_09221_amd/csrc/tri.cpp",
+                 "paper_2604_09221_amd/tune_cache_gfx950.json")
+MULTI_TRAFFIC_PROFILE = "profiles/k_multi_batched_uneven_4096x2p16_counters.md"
 
 
-def kernel_sources_sha256():
+def kernel_sources_sha256(sources=KERNEL_SOURCES):
     import hashlib
 
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def profiled_traffic():
-    """HBM bytes per launch from the committed counter summary (FETCH_SIZE and
-    WRITE_SIZE scaled by a 1 GiB copy), or None if the kernel sources changed
-    since it was taken."""
+def profiled_traffic(profile=TRAFFIC_PROFILE, sources=KERNEL_SOURCES):
+    """HBM bytes per launch (per call for the batched call) from a committed
+    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy), or
+    None if the sources changed since it was taken."""
     try:
-        text = open(os.path.join(ROOT, TRAFFIC_PROFILE)).read()
+        text = open(os.path.join(ROOT, profile)).read()
     except OSError:
         return None
     vals = dict(line.split(": ", 1) for line in text.splitlines() if line.startswith(("traffic_bytes_per_launch: ",
                                                                                       "kernel_sources_sha256: ")))
-    if vals.get("kernel_sources_sha256") != kernel_sources_sha256():
+    if vals.get("kernel_sources_sha256") != kernel_sources_sha256(sources):
         return None
     return float(vals["traffic_bytes_per_launch"])
 
@@ -99,13 +105,6 @@ def cpu_baseline(d, E, n, codes_gpu_fn):
     }
 
 
-def _lift(args):
-    from paper_2604_09221_amd import inputs as I
-
-    d, seed, noise = args
-    return I.lift_triangulation(int(d), int(seed), noise=noise)
-
-
 def hist_capacity(d):
     return {4: 64, 5: 64, 6: 128, 7: 256, 8: 1024, 9: 4096}.get(d, 1 << 15)
 
@@ -116,8 +115,6 @@ def bench_multi(args):
     per 128-bit mask, bits >= |A| and bit 0 cleared), per-triangulation
     histograms; a step is one call, i.e. one persistent launch per LDS
     class of degrees."""
-    from multiprocessing import Pool
-
     import torch
 
     from paper_2604_09221_amd import inputs as I
@@ -128,8 +125,9 @@ def bench_multi(args):
     n_slots, per = args.slots, 1 << 16
     noise = 1.0 if args.varied else 0.05
     degs = I.batched_degrees(n_slots, 0)
-    with Pool(min(16, os.cpu_count() or 1)) as pool:
-        edges = pool.map(_lift, [(int(d), t, noise) for t, d in enumerate(degs)])
+    # in-process (a few seconds): forked workers would inherit a profiler
+    # loaded into this process, and their termination can block it
+    edges = [I.lift_triangulation(int(d), t, noise=noise) for t, d in enumerate(degs)]
     torch.cuda.set_device(0)
     tris = [pw.Triangulation(int(d), E) for d, E in zip(degs, edges)]
     masks = torch.empty((n_slots * per, 2), dtype=torch.int64, device="cuda")
@@ -174,7 +172,9 @@ def bench_multi(args):
                                f"(one persistent launch per LDS class)",
                    "launch_shape": list(cfg)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_INT_OPS / 1e12, "unit": "TOP/s",
-                     "frac": achieved * 1e12 / PEAK_INT_OPS, "traffic": None, "kernel": "pw::k_multi",
+                     "frac": achieved * 1e12 / PEAK_INT_OPS,
+                     "traffic": profiled_traffic(MULTI_TRAFFIC_PROFILE, MULTI_SOURCES)
+                     if n_slots == 4096 and not args.varied else None, "kernel": "pw::k_multi",
                      "per": "call (the class launches back to back)",
                      "avg_call_ms": sum(times) / len(times) * 1e3},
     }
