@@ -63,6 +63,15 @@ def test_multi_codes_and_histograms(pw):
     pw.batch_multi(tris, mt, offsets, hists=hists2, config=(4096, 2, 2))
     for h1, h2 in zip(hists, hists2):
         assert h1.read() == h2.read()
+    # four waves per block: each LDS class lowers it until its block fits
+    # (3 at d = 12, 4 at d = 11 and below)
+    assert {10, 11, 12} <= {int(d) for d in degs}
+    hists3 = [pw.Histogram(1024) for _ in tris]
+    codes3 = torch.zeros_like(codes)
+    pw.batch_multi(tris, mt, offsets, hists=hists3, codes=codes3, config=(512, 4, 0))
+    assert torch.equal(codes3, codes)
+    for h1, h3 in zip(hists, hists3):
+        assert h1.read() == h3.read()
 
 
 def test_multi_literal_lift_slots_and_edge_cases(pw):
