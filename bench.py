@@ -79,7 +79,13 @@ def profiled_traffic(profile=TRAFFIC_PROFILE, sources=KERNEL_SOURCES):
     return float(vals["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(d, E, n, codes_gpu_fn):
+def cpu_baseline(d, E, n, codes_gpu_fn, sweep_hist_fn=None):
+    """The oracle timed on the host's threads on n masks of the d=7 sweep
+    (SplitMix64 stream 7); the GPU codes of the same masks must be equal
+    (bit-exact), and, when sweep_hist_fn is given, so must the timed sweep
+    kernel's histograms of 64 whole 512-mask chunks and 16 ragged ranges at
+    random positions of the 2^35 indices (checked outside the timed region;
+    a mismatch raises)."""
     import numpy as np
 
     import oracle
@@ -94,14 +100,35 @@ def cpu_baseline(d, E, n, codes_gpu_fn):
     want = oracle.scheme_many(d, E, masks, threads=threads)
     dt = time.perf_counter() - t0
     got = codes_gpu_fn(masks)
+    if not np.array_equal(got, want):
+        bad = int(np.flatnonzero((got != want).any(axis=1))[0])
+        raise AssertionError(f"GPU code of subsample mask {bad} differs from the oracle")
+    sampled = ""
+    if sweep_hist_fn is not None:
+        rng = np.random.default_rng(20260)
+        ranges = [(int(rng.integers(0, TOTAL // 512)) * 512, 512) for _ in range(64)]
+        for _ in range(16):
+            k = int(rng.integers(1, 1536))
+            ranges.append((int(rng.integers(0, TOTAL - k)), k))
+        for a, k in ranges:
+            m = np.zeros((k, 2), dtype=np.uint64)
+            m[:, 0] = np.arange(a, a + k, dtype=np.uint64) << np.uint64(1)
+            ref = {}
+            for j, (lo, hi) in enumerate(oracle.scheme_many(d, E, m, threads=threads)):
+                c = int(lo) | (int(hi) << 64)
+                cnt, w = ref.get(c, (0, a + j))
+                ref[c] = (cnt + 1, min(w, a + j))
+            if sweep_hist_fn(a, k) != ref:
+                raise AssertionError(f"timed sweep kernel differs from the oracle on indices [{a}, {a + k})")
+        sampled = (f"; the timed sweep kernel's histograms of {len(ranges)} sampled ranges (64 whole 512-mask "
+                   f"chunks, 16 ragged) equal the oracle's")
     return {
         "value": n / dt,
         "unit": "masks/s",
         "cores": threads,
         "kind": "oracle",
         "sample": f"{n} masks of the d=7 sweep (SplitMix64 stream 7, idx = low 35 bits, mask = idx<<1), "
-                  f"plain C oracle on {threads} host threads; GPU codes for the same masks bit-exact: "
-                  f"{bool(np.array_equal(got, want))}",
+                  f"plain C oracle on {threads} host threads; GPU codes for the same masks bit-exact{sampled}",
     }
 
 
@@ -273,6 +300,35 @@ def gemm_roofline():
             "avg_launch_ms": gemm_s * 1e3}
 
 
+def full_sweep_checks(full, d, E):
+    """Checks of every whole pass over the 2^35 indices, outside the timed
+    region: the counts sum to 2^35; each count is divisible by 4 (sigma ->
+    sigma + b i + c j, (b, c) != 0, keeps sigma(0,0) and the scheme and has
+    no fixed point: a free (Z/2)^2 action on the swept masks, Sec. 3);
+    at most 121 schemes (Sec. 1); every pass gives the same histogram; and
+    that histogram equals one sweep of the generic kernel (the triangulation
+    program read from device memory, no snapshot), run here in 2^32-mask
+    launches."""
+    from paper_2604_09221_amd import patchwork as pw
+
+    for h_ in full:
+        assert sum(c for c, _ in h_.values()) == TOTAL
+        assert all(c % 4 == 0 for c, _ in h_.values()), "a count of a whole sweep is not divisible by 4"
+        assert len(h_) <= 121
+        assert h_ == full[0], "two whole sweeps differ"
+    gen = pw.Triangulation(d, E)
+    ref = pw.Histogram(1024)
+    t0 = time.perf_counter()
+    for a in range(0, TOTAL, 1 << 32):
+        gen.enumerate_range(a, 1 << 32, ref)
+    got = ref.read()
+    dt = time.perf_counter() - t0
+    assert gen.errors() == 0
+    assert got == full[0], "the sweep kernel's histogram differs from the generic kernel's"
+    return {"passes_checked": len(full), "sum": True, "counts_divisible_by_4": True, "at_most_121": True,
+            "equal_to_generic_kernel_sweep": True, "generic_sweep_seconds": dt}
+
+
 FIG2 = {"bow_tie": 123, "rank016": 359, "rank015": 353}  # distinct real schemes printed with Fig. 2
 
 
@@ -369,6 +425,8 @@ def main():
     ap.add_argument("--budget-log2", type=int, default=26)
     ap.add_argument("--generic", action="store_true", help="time the generic (unspecialised) kernel")
     ap.add_argument("--chunk-log2", type=int, default=32, help="masks per step (profiling runs use less)")
+    ap.add_argument("--no-full-check", action="store_true",
+                    help="skip the checks of whole passes (the generic kernel's reference sweep)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -424,15 +482,20 @@ def main():
     else:
         tri.specialize()
     t_spec = time.perf_counter() - t_spec
-    hist = pw.Histogram(1024)
     warm = pw.Histogram(1024)
     stream = torch.cuda.current_stream()
 
     CHUNK = 1 << args.chunk_log2
+    assert CHUNK <= TOTAL
     for w in range(args.warmup):
         tri.enumerate_range((w * CHUNK) % TOTAL, CHUNK, warm)
     torch.cuda.synchronize()
 
+    # one histogram per pass over the 2^35 indices (the steps of pass p go
+    # into passes[p]): a whole pass is closed under the sign symmetries, so
+    # its counts can be checked after the timed region
+    n_pass = (args.steps * CHUNK + TOTAL - 1) // TOTAL
+    passes = [pw.Histogram(1024) for _ in range(n_pass)]
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -440,15 +503,20 @@ def main():
     for k in range(args.steps):
         first = (k * CHUNK) % TOTAL
         starts[k].record(stream)
-        tri.enumerate_range(first, CHUNK, hist)
+        tri.enumerate_range(first, CHUNK, passes[k * CHUNK // TOTAL])
         ends[k].record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     launch_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
-    h = hist.read()
+    hs = [p.read() for p in passes]
     assert tri.errors() == 0
     masks_done = args.steps * CHUNK
-    assert sum(c for c, _ in h.values()) == masks_done
+    assert sum(c for h_ in hs for c, _ in h_.values()) == masks_done
+    h = hs[0]
+    full = [h_ for k, h_ in enumerate(hs) if (k + 1) * TOTAL <= masks_done]
+    full_checks = None
+    if full and not args.no_full_check:
+        full_checks = full_sweep_checks(full, d, E)
     value = masks_done / elapsed
     avg_launch_s = sum(launch_ms) / len(launch_ms) / 1e3
     ops = algorithmic_ops_per_mask(d) * CHUNK
@@ -472,7 +540,8 @@ def main():
                         "sigma(0,0)=+, generated in-kernel, scheme histogram",
             "degree": d,
             "masks_per_step": CHUNK,
-            "full_sweep": masks_done == TOTAL,
+            "full_sweep": masks_done >= TOTAL,
+            "full_sweep_checks": full_checks,
             "distinct_schemes": len(h),
             "specialize_seconds": t_spec,
         },
@@ -494,7 +563,13 @@ def main():
             torch.cuda.synchronize()
             return c.cpu().numpy().view(np.uint64)
 
-        out["cpu_baseline"] = cpu_baseline(d, E, args.cpu_sample, gpu_codes)
+        def sweep_hist(a, k):
+            hk = pw.Histogram(512)
+            tri.enumerate_range(a, k, hk)
+            return hk.read()
+
+        out["cpu_baseline"] = cpu_baseline(d, E, args.cpu_sample, gpu_codes,
+                                           None if args.generic else sweep_hist)
     print(json.dumps(out), flush=True)
 
 

@@ -189,7 +189,11 @@ pw_status patchwork_scheme_enumerate_range(pw_tri_t tri, uint64_t first, uint64_
  * set (first, count, chunk, fixed bits, hist): calling again with the same
  * arguments launches the kept graph again (the histogram accumulates once
  * more), other arguments capture a new one.  Capture happens on a stream of
- * the handle's own, so `stream` may be the default stream.  Errors: as
+ * the handle's own, so `stream` may be the default stream.  The kept graph
+ * names its histogram by a serial number that pw_hist_create never reuses, so
+ * a histogram created after another was destroyed (even at the same address)
+ * gets a new capture; a histogram must not be destroyed while a launch of
+ * the graph may still run on it.  Errors: as
  * patchwork_scheme_enumerate_range, plus PW_ERR_ARG for chunk == 0 or more
  * than 2^16 launches, PW_ERR_HIP if the capture fails.  Not for concurrent
  * use of one handle from several threads.

@@ -27,6 +27,9 @@ struct pw_tri {
 
 struct pw_hist {
   int32_t cap = 0;
+  // process-wide serial number, never reused: a kept sweep graph names its
+  // histogram by it (a freed handle's address may come back for a new one)
+  uint64_t serial = 0;
   uint32_t* state = nullptr;
   uint64_t* key = nullptr;
   uint64_t* cnt = nullptr;

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
@@ -285,6 +286,8 @@ pw_status pw_hist_create(int32_t capacity, pw_hist_t* out) {
     return set_err(PW_ERR_ARG, "histogram capacity must be a power of two in [16, 2^26], got %d", (int)capacity);
   pw_hist* h = new (std::nothrow) pw_hist();
   if (!h) return set_err(PW_ERR_ARG, "out of host memory");
+  static std::atomic<uint64_t> next_serial{1};
+  h->serial = next_serial.fetch_add(1, std::memory_order_relaxed);
   h->cap = capacity;
   hipError_t e = hipMalloc(&h->state, sizeof(uint32_t) * capacity);
   if (e == hipSuccess) e = hipMalloc(&h->key, sizeof(uint64_t) * 2 * capacity);
@@ -438,7 +441,9 @@ pw_status patchwork_scheme_sweep_graph(pw_tri_t t, uint64_t first, uint64_t coun
   if (count == 0) return PW_OK;
   const uint64_t launches = (count - 1) / chunk + 1;
   if (launches > (1u << 16)) return set_err(PW_ERR_ARG, "%llu launches (at most 65536)", (unsigned long long)launches);
-  const uint64_t key[6] = {first, count, chunk, fixed_zero_bits[0], fixed_zero_bits[1], (uint64_t)(uintptr_t)h};
+  // the histogram is named by its serial number, not its address: a graph
+  // captured for a destroyed handle is never launched for a new one
+  const uint64_t key[6] = {first, count, chunk, fixed_zero_bits[0], fixed_zero_bits[1], h->serial};
   if (!t->sweep_exec || std::memcmp(key, t->sweep_key, sizeof key) != 0) {
     if (t->sweep_exec) {
       PW_HIP(hipGraphExecDestroy(t->sweep_exec));

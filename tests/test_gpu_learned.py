@@ -13,6 +13,7 @@ from __future__ import annotations
 import numpy as np
 import pytest
 
+from oracle import mlp as R
 from paper_2604_09221_amd import inputs as I
 
 torch = pytest.importorskip("torch")
@@ -97,7 +98,7 @@ def test_network_ranking_beats_random_ranking(trained):
 
 
 def test_flip_distribution_and_sampling():
-    """pw_flip_cdf against its formula (numpy), and pw_mutate_cdf's draws
+    """pw_flip_cdf against the oracle's table, and pw_mutate_cdf's draws
     against the distribution (one parent, 2^20 single flips, 5 sigma)."""
     from paper_2604_09221_amd import learn as Lr
 
@@ -109,13 +110,8 @@ def test_flip_distribution_and_sampling():
     temp, explore = 0.3, 0.1
     pt = torch.from_numpy(par.view(np.int64)).cuda()
     cdf = Lr.flip_cdf(pt, torch.from_numpy(dX).cuda(), n_bits, temp, explore).cpu().numpy().astype(np.float64)
-    for p in range(n_par):
-        x = np.where((par[p, 0] >> np.arange(64, dtype=np.uint64)) & np.uint64(1), -1.0, 1.0)
-        gain = -2.0 * x[1:n_bits] * dX[p, 1:n_bits]
-        w = np.exp((gain - gain.max()) / (temp * np.abs(gain).max()))
-        prob = (1 - explore) * w / w.sum() + explore / (n_bits - 1)
-        want = np.concatenate([[0.0], np.cumsum(prob)[:-1], np.ones(64 - n_bits + 1)])
-        assert np.allclose(cdf[p], want, atol=2e-6)
+    want = R.flip_cdf(par, dX.astype(np.float64), n_bits, temp, explore)
+    assert np.allclose(cdf, want, atol=2e-6, rtol=0)
     n = 1 << 20
     one = pt[:1].contiguous()
     out = Lr.mutate_guided(one, torch.from_numpy(dX[:1]).cuda(), n, n_bits, 1, 99, temp, explore)

@@ -330,3 +330,88 @@ def test_specialized_kernels_match_oracle(pw):
             want3 = oracle.scheme_many(d, E, enum_masks(last, 5000, nA=I.n_points(d)), threads=THREADS)
             assert h3.read() == oracle_hist(want3, index_of=np.arange(last, last + 5000, dtype=np.uint64))
         assert tri.errors() == 0
+
+
+# ------------------------------------- the timed sweep kernel over its whole range
+
+def _chunks_across_range(rng, n_free, n_aligned, n_ragged, chunk=512):
+    """(first, count) pairs: n_aligned whole 512-mask chunks at random
+    positions of [0, 2^n_free) (so the fixed-sign pattern of every snapshot
+    -- index bits 9 and up -- takes random values), then n_ragged ranges of
+    random start and length up to three chunks (partial chunks at both
+    ends)."""
+    top = 1 << n_free
+    out = []
+    for _ in range(n_aligned):
+        out.append((int(rng.integers(0, top // chunk)) * chunk, chunk))
+    for _ in range(n_ragged):
+        n = int(rng.integers(1, 3 * chunk))
+        out.append((int(rng.integers(0, top - n)), n))
+    return out
+
+
+def test_d7_sweep_kernel_mid_range(pw):
+    """The specialised d = 7 sweep kernel (shared snapshot per 512 masks)
+    on 256 whole chunks spread over the 2^35 indices and 64 ragged ranges:
+    histogram counts and witnesses of every range against the oracle."""
+    d = 7
+    E = I.standard_triangulation(d)
+    tri = pw.Triangulation(d, E).specialize()
+    rng = np.random.default_rng(735)
+    ranges = _chunks_across_range(rng, 35, 256, 64)
+    hist = pw.Histogram(512)
+    allm = np.concatenate([enum_masks(a, n, nA=36) for a, n in ranges])
+    want = oracle.scheme_many(d, E, allm, threads=THREADS)
+    pos = 0
+    for a, n in ranges:
+        hist.reset()
+        tri.enumerate_range(a, n, hist)
+        assert hist.read() == oracle_hist(want[pos:pos + n], index_of=np.arange(a, a + n, dtype=np.uint64)), (a, n)
+        pos += n
+    assert tri.errors() == 0
+
+
+def test_d8_class_sweep_kernel_mid_range(pw):
+    """The even-degree sweep kernel on the Fig. 2 class-representative
+    enumeration (sigma fixed at (0,0), (1,1), (2,1)): 128 whole chunks
+    spread over the 2^42 classes and 32 ragged ranges, per range against
+    the oracle."""
+    import bench
+
+    fz = bench.fig2_fixed_bits(8)
+    rng = np.random.default_rng(842)
+    for name in ("rank015", "bow_tie"):
+        E = fig2_edges(name)
+        tri = pw.Triangulation(8, E).specialize()
+        ranges = _chunks_across_range(rng, 42, 128, 32)
+        allm = np.concatenate([enum_masks(a, n, fixed=fz, nA=45) for a, n in ranges])
+        want = oracle.scheme_many(8, E, allm, threads=THREADS)
+        hist = pw.Histogram(1024)
+        pos = 0
+        for a, n in ranges:
+            hist.reset()
+            tri.enumerate_range(a, n, hist, fixed_zero_bits=fz)
+            assert hist.read() == oracle_hist(want[pos:pos + n], index_of=np.arange(a, a + n, dtype=np.uint64)), \
+                (name, a, n)
+            pos += n
+        assert tri.errors() == 0
+
+
+def test_sweep_graph_new_histogram_after_destroy(pw):
+    """A histogram destroyed and created again (the allocator may hand out
+    the same address) gets a new capture, not the kept graph of the old
+    one: same arguments, fresh histogram, result equal to the eager one."""
+    d = 6
+    E = I.standard_triangulation(d)
+    tri = pw.Triangulation(d, E)
+    first, n, chunk = 99, (1 << 16) + 5, 1 << 14
+    h_eager = pw.Histogram(256)
+    tri.enumerate_range(first, n, h_eager)
+    want = h_eager.read()
+    for _ in range(3):
+        h = pw.Histogram(256)
+        tri.sweep_graph(first, n, chunk, h)
+        torch.cuda.synchronize()
+        assert h.read() == want
+        h.close()
+    assert tri.errors() == 0
