@@ -52,6 +52,9 @@ MULTI_SOURCES = ("paper_2604_09221_amd/csrc/pw_device.h", "paper_2604_09221_amd/
                  "paper_2604_09221_amd/csrc/multi.hip", "paper_2604_09221_amd/csrc/tri.cpp",
                  "paper_2604_09221_amd/tune_cache_gfx950.json")
 MULTI_TRAFFIC_PROFILE = "profiles/k_multi_batched_uneven_4096x2p16_counters.md"
+# the d=6 codes + histogram launches (the generated kernel's sources)
+D6_SOURCES = KERNEL_SOURCES
+D6_TRAFFIC_PROFILE = "profiles/pw_jit_hist_d6_codes_64x2p20_counters.md"
 
 
 def kernel_sources_sha256(sources=KERNEL_SOURCES):
@@ -205,6 +208,173 @@ def bench_multi(args):
                      "per": "call (the class launches back to back)",
                      "avg_call_ms": sum(times) / len(times) * 1e3},
     }
+
+
+def _events():
+    import torch
+
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def bench_d4(args):
+    """d = 4: the standard triangulation (seed-0 lift), all 2^14 masks with
+    sigma(0,0) = '+' (mask = k << 1, uint32), codes and histogram in one
+    fused launch of the kernel specialised to the triangulation.  The
+    workload is a single small launch, so the figure is its latency."""
+    import torch
+
+    from paper_2604_09221_amd import inputs as I
+    from paper_2604_09221_amd import patchwork as pw
+
+    d, n = 4, 1 << 14
+    E = I.lift_triangulation(d, 0, noise=0.05)
+    torch.cuda.set_device(0)
+    tri = pw.Triangulation(d, E).specialize()
+    masks2 = np.zeros((n, 2), dtype=np.uint64)
+    masks2[:, 0] = np.arange(n, dtype=np.uint64) << np.uint64(1)
+    mt = pw.mask_tensor(masks2, d)
+    codes = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+    hist = pw.Histogram(64)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        tri.codes_histogram(mt, hist, codes)
+    hist.reset()
+    torch.cuda.synchronize()
+    ev = [_events() for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        tri.codes_histogram(mt, hist, codes)
+        b.record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    lat = sorted(a.elapsed_time(b) / 1e3 for a, b in ev)
+    h = hist.read()
+    assert tri.errors() == 0 and sum(c for c, _ in h.values()) == args.steps * n
+    med = lat[len(lat) // 2]
+    ops = algorithmic_ops_per_mask(d) * n
+    out = {"metric": "latency of all 2^14 sign distributions at d=4 (codes + histogram)",
+           "value": med * 1e6, "unit": "us", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+           "config": {"workload": "d=4 standard triangulation (seed-0 lift), all 2^14 masks with sigma(0,0)=+, "
+                                  "codes + histogram in one launch", "masks_per_s_at_median": n / med,
+                      "latency_us_min": lat[0] * 1e6, "latency_us_max": lat[-1] * 1e6, "distinct_schemes": len(h)},
+           "roofline": {"bound": "alu", "achieved": ops / med / 1e12, "peak": PEAK_INT_OPS / 1e12, "unit": "TOP/s",
+                        "frac": ops / med / PEAK_INT_OPS, "traffic": None,
+                        "kernel": "pw_jit_hist (codes + histogram, specialised to the triangulation)",
+                        "ops_per_mask": algorithmic_ops_per_mask(d), "avg_launch_ms": sum(lat) / len(lat) * 1e3,
+                        "note": "a single 2^14-mask launch: launch latency, not throughput, bounds it"}}
+    if not args.no_cpu_baseline:
+        import oracle
+
+        oracle.build()
+        threads = os.cpu_count() or 1
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            want = oracle.scheme_many(d, E, masks2, threads=threads)
+            reps += 1
+            if time.perf_counter() - t0 > 2.0:
+                break
+        dt = (time.perf_counter() - t0) / reps
+        got = codes.cpu().numpy().view(np.uint64)
+        if not np.array_equal(got, want):
+            raise AssertionError("d=4 codes differ from the oracle")
+        ref = {}
+        for k, (lo, hi) in enumerate(want):
+            c = int(lo) | (int(hi) << 64)
+            ref[c] = ref.get(c, 0) + 1
+        if {c: v for c, (v, _) in h.items()} != {c: v * args.steps for c, v in ref.items()}:
+            raise AssertionError("d=4 histogram differs from the oracle")
+        out["cpu_baseline"] = {"value": dt * 1e6, "unit": "us", "cores": threads, "kind": "oracle",
+                               "sample": f"all 2^14 masks, {reps} repetitions on {threads} host threads; GPU codes "
+                                         "and histogram bit-exact"}
+    return out
+
+
+def bench_d6(args):
+    """d = 6: 64 triangulations (lift seeds 0..63: the literal quadratic
+    lift, or U[0,1) noise with --varied), per slot 2^20 uniform uint32 masks
+    (SplitMix64 stream = slot seed, bit 0 cleared); per slot one fused
+    launch writing every code and the slot's histogram.  A step is all 64
+    launches."""
+    import torch
+
+    from paper_2604_09221_amd import inputs as I
+    from paper_2604_09221_amd import patchwork as pw
+
+    d, slots, per = 6, 64, 1 << 20
+    noise = 1.0 if args.varied else 0.05
+    torch.cuda.set_device(0)
+    t_setup = time.perf_counter()
+    edges = [I.lift_triangulation(d, t, noise=noise) for t in range(slots)]
+    tris = [pw.Triangulation(d, E).specialize() for E in edges]
+    host = [I.random_masks(d, t, per) for t in range(slots)]
+    masks = torch.cat([pw.mask_tensor(m, d) for m in host])          # 64 x 2^20 uint32 (256 MiB)
+    codes = torch.empty((slots * per, 2), dtype=torch.int64, device="cuda")   # 1 GiB
+    hists = [pw.Histogram(128) for _ in range(slots)]
+    t_setup = time.perf_counter() - t_setup
+    stream = torch.cuda.current_stream()
+
+    def step():
+        for t in range(slots):
+            tris[t].codes_histogram(masks[t * per:(t + 1) * per], hists[t], codes[t * per:(t + 1) * per])
+
+    for _ in range(args.warmup):
+        step()
+    for h in hists:
+        h.reset()
+    torch.cuda.synchronize()
+    ev = [_events() for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        step()
+        b.record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    step_s = sum(a.elapsed_time(b) for a, b in ev) / len(ev) / 1e3
+    hs = [h.read() for h in hists]
+    assert all(t.errors() == 0 for t in tris)
+    assert all(sum(c for c, _ in h.values()) == args.steps * per and len(h) <= 55 for h in hs)
+    evals = slots * per
+    ops = algorithmic_ops_per_mask(d) * evals
+    alg_bytes = evals * (4 + 16)
+    traffic = profiled_traffic(D6_TRAFFIC_PROFILE, D6_SOURCES) if not args.varied else None
+    out = {"metric": "sign distributions/sec at d=6 (codes + per-triangulation histograms)",
+           "value": args.steps * evals / elapsed, "unit": "masks/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+           "config": {"workload": f"d=6: 64 triangulations ({'varied' if args.varied else 'literal'} lifts, seeds "
+                                  "0..63) x 2^20 uniform uint32 masks, codes (1 GiB) + 64 histograms, one fused "
+                                  "launch per triangulation", "setup_seconds": t_setup,
+                      "hbm_algorithmic_GBps": alg_bytes / step_s / 1e9,
+                      "distinct_schemes_max": max(len(h) for h in hs)},
+           "roofline": {"bound": "alu", "achieved": ops / step_s / 1e12, "peak": PEAK_INT_OPS / 1e12,
+                        "unit": "TOP/s", "frac": ops / step_s / PEAK_INT_OPS,
+                        "traffic": traffic, "kernel": "pw_jit_hist (codes + histogram, specialised per slot)",
+                        "per": "step (64 launches)", "ops_per_mask": algorithmic_ops_per_mask(d),
+                        "avg_step_ms": step_s * 1e3,
+                        "hbm": {"achieved_GBps": (traffic if traffic else alg_bytes) / step_s / 1e9,
+                                "peak_GBps": 8000.0, "algorithmic_bytes_per_step": alg_bytes}}}
+    if not args.no_cpu_baseline:
+        import oracle
+
+        oracle.build()
+        threads = os.cpu_count() or 1
+        sample = 1 << 22
+        k = sample // slots
+        ms = np.concatenate([m[:k] for m in host])
+        t0 = time.perf_counter()
+        want = np.concatenate([oracle.scheme_many(d, edges[t], host[t][:k], threads=threads) for t in range(slots)])
+        dt = time.perf_counter() - t0
+        got = np.concatenate([codes[t * per:t * per + k].cpu().numpy().view(np.uint64) for t in range(slots)])
+        if not np.array_equal(got, want):
+            raise AssertionError("d=6 codes differ from the oracle")
+        out["cpu_baseline"] = {"value": len(ms) / dt, "unit": "masks/s", "cores": threads, "kind": "oracle",
+                               "sample": f"the first {k} masks of each of the 64 slots ({len(ms)} masks) on "
+                                         f"{threads} host threads; GPU codes for them bit-exact"}
+    return out
 
 
 def bench_learned(args):
@@ -413,7 +583,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=1 << 24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--config", choices=("d7", "multi", "learned", "gemm", "copyprobe", "fig2", "fig2-check"),
+    ap.add_argument("--config", choices=("d7", "d4", "d6", "multi", "learned", "gemm", "copyprobe", "fig2",
+                                         "fig2-check"),
                     default="d7")
     ap.add_argument("--tri", choices=sorted(FIG2), default="rank016", help="--config fig2: the triangulation")
     ap.add_argument("--part", type=int, default=0, help="--config fig2: which part of the sweep")
@@ -447,6 +618,9 @@ def main():
         return
     if args.config == "multi":
         print(json.dumps(bench_multi(args)), flush=True)
+        return
+    if args.config in ("d4", "d6"):
+        print(json.dumps((bench_d4 if args.config == "d4" else bench_d6)(args)), flush=True)
         return
     if args.config == "learned":
         print(json.dumps(bench_learned(args)), flush=True)

@@ -112,7 +112,9 @@ pw_status pw_tri_errors(pw_tri_t tri, uint32_t *flags);
  * hipRTC for gfx950 and loaded on the current device.  Afterwards
  * patchwork_scheme_batch / _histogram / _enumerate_range on this handle use
  * them; results are identical to the generic kernels.  Takes seconds (a
- * compile); idempotent.  Errors: PW_ERR_ARG (d > 9), PW_ERR_HIP (compile or
+ * compile; the code object is kept per generated source for the life of the
+ * process, so an equal triangulation loads it without compiling again);
+ * idempotent.  Errors: PW_ERR_ARG (d > 9), PW_ERR_HIP (compile or
  * load failed; the handle keeps using the generic kernels).
  */
 pw_status pw_tri_specialize(pw_tri_t tri);
@@ -131,8 +133,9 @@ pw_status pw_jit_compile(int32_t d, const int16_t *edges_ij, int32_t n_edges, in
 /*
  * Codes of n sign masks (Alg. 1 for each pair (T, sigma_k)).
  *   d_masks  n masks of pw_mask_bytes(d) bytes each, contiguous.
- *   d_codes  n x 2 uint64 (lo, hi) written in input order.
- * n = 0 is a no-op; n < 0 is PW_ERR_ARG.
+ *   d_codes  n x 2 uint64 (lo, hi) written in input order, 16-byte aligned
+ *            (each code is one 16-byte store).
+ * n = 0 is a no-op; n < 0 or a misaligned d_codes is PW_ERR_ARG.
  */
 pw_status patchwork_scheme_batch(pw_tri_t tri, const void *d_masks, int64_t n, uint64_t *d_codes,
                                  hipStream_t stream);
@@ -152,6 +155,16 @@ pw_status pw_hist_reset(pw_hist_t hist, hipStream_t stream);
 pw_status pw_hist_read(pw_hist_t hist, uint64_t *codes, uint64_t *counts, uint64_t *witness,
                        int32_t capacity, int32_t *n_used);
 pw_status pw_hist_destroy(pw_hist_t hist);
+
+/*
+ * Codes and histogram of the same n masks in one pass (each mask evaluated
+ * once): d_codes as in patchwork_scheme_batch, `hist` as in
+ * patchwork_scheme_histogram (accumulates; witness = smallest index_base +
+ * k).  Sec. 3: a sweep wants both the scheme of every sign distribution and
+ * the per-triangulation distribution.  Errors as those two calls.
+ */
+pw_status patchwork_scheme_codes_histogram(pw_tri_t tri, const void *d_masks, int64_t n, uint64_t index_base,
+                                           uint64_t *d_codes, pw_hist_t hist, hipStream_t stream);
 
 /*
  * Histogram of the codes of n masks (the per-triangulation distribution of
@@ -211,7 +224,8 @@ pw_status patchwork_scheme_sweep_graph(pw_tri_t tri, uint64_t first, uint64_t co
  *   offsets   host array of n_tris + 1 non-decreasing indices.
  *   hists     host array of n_tris histogram handles, or NULL; the witness
  *             of a code is its smallest global mask index.
- *   d_codes   NULL, or n x 2 uint64 codes written at the masks' positions.
+ *   d_codes   NULL, or n x 2 uint64 codes written at the masks' positions
+ *             (16-byte aligned).
  *   cfg       NULL for the defaults, or the tuned launch shape: masks per
  *             work item, waves per block (lowered until a block's LDS for
  *             the largest degree of its class fits in 160 KiB), blocks per

@@ -22,6 +22,8 @@
 #include <cstring>
 #include <sstream>
 #include <string>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "patchwork.h"
@@ -358,8 +360,8 @@ std::string jit_source(const HostProgram& P) {
        "  extern __shared__ uint32_t smem[];\n  pw::codes_body<"
     << d << ">(pw::JitEval{}, masks, n, codes, errflag, smem);\n}\n";
   o << attr << "pw_jit_hist(const void* masks, int64_t n, uint64_t index_base, const pw::HistDev* h, "
-       "uint32_t* errflag) {\n  extern __shared__ uint32_t smem[];\n  pw::hist_body<"
-    << d << ">(pw::JitEval{}, masks, n, index_base, h, errflag, smem);\n}\n";
+       "uint64_t* codes, uint32_t* errflag) {\n  extern __shared__ uint32_t smem[];\n  pw::hist_body<"
+    << d << ">(pw::JitEval{}, masks, n, index_base, h, codes, errflag, smem);\n}\n";
   o << attr << "pw_jit_enum(uint64_t first, uint64_t count, pw::Runs runs, const pw::HistDev* h, "
        "uint32_t* errflag) {\n  extern __shared__ uint32_t smem[];\n  pw::enum_body<"
     << d << ">(pw::JitEval{}, first, count, runs, h, errflag, smem);\n}\n";
@@ -440,9 +442,26 @@ pw_status pw_tri_specialize(pw_tri_t t) {
   if (!t) return set_err(PW_ERR_ARG, "null handle");
   if (t->prog.d > kJitMaxDegree) return set_err(PW_ERR_ARG, "specialised kernels exist for d <= %d", kJitMaxDegree);
   if (t->jit_mod) return PW_OK;
+  // Code objects are kept per source text for the life of the process: a
+  // triangulation equal to an earlier one (same edges, hence the same
+  // generated source) loads the kept object instead of compiling again.
+  // Each handle still loads its own module and runs its own launches.
+  static std::mutex cache_mu;
+  static std::map<std::string, std::vector<char>> cache;
+  const std::string src = jit_source(t->prog);
   std::vector<char> code;
-  const pw_status rc = compile(jit_source(t->prog), &code);
-  if (rc != PW_OK) return rc;
+  {
+    std::lock_guard<std::mutex> lock(cache_mu);
+    const auto it = cache.find(src);
+    if (it != cache.end()) code = it->second;
+  }
+  if (code.empty()) {
+    const pw_status rc = compile(src, &code);
+    if (rc != PW_OK) return rc;
+    std::lock_guard<std::mutex> lock(cache_mu);
+    if (cache.size() >= 256) cache.clear();  // bound the host memory it holds
+    cache.emplace(src, code);
+  }
   hipModule_t mod = nullptr;
   PW_HIP(hipModuleLoadData(&mod, code.data()));
   hipFunction_t fc = nullptr, fh = nullptr, fe = nullptr, fs = nullptr;

@@ -86,10 +86,7 @@ __device__ __forceinline__ void run_item(const TriDesc& t, const Item& w, const 
       valid = false;  // counted and written by k_multi_big
     }
     errs |= e & ~kErrOverflow;
-    if (codes && valid) {
-      codes[2 * i] = (uint64_t)code;
-      codes[2 * i + 1] = (uint64_t)(code >> 64);
-    }
+    if (codes && valid) store_code(codes, i, code);
     if (t.use_hist) tab.add_batch((uint64_t)code, (uint64_t)(code >> 64), valid, (uint64_t)i, lane, t.hist);
   }
   if (t.use_hist) tab.flush(t.hist);
@@ -145,10 +142,7 @@ __device__ __forceinline__ void run_big(const TriDesc& t, int64_t i, const uint6
   uint32_t e = 0;
   const u128 code = Eval<D>::run(t.prog, m, L, e);
   if (e) atomicOr(t.err, e);
-  if (codes) {
-    codes[2 * i] = (uint64_t)code;
-    codes[2 * i + 1] = (uint64_t)(code >> 64);
-  }
+  if (codes) store_code(codes, i, code);
   // (the descriptor differs between lanes here: a plain vector load)
   if (t.use_hist && code != 0) global_insert(*t.hist, (uint64_t)code, (uint64_t)(code >> 64), 1, (uint64_t)i);
 }
@@ -211,21 +205,48 @@ MultiScratch& scratch_for_multi() {
 
 using namespace pw;
 
-extern "C" pw_status patchwork_scheme_batch_multi(const pw_tri_t* tris, int32_t n_tris, const void* d_masks,
-                                                  const int64_t* offsets, const pw_hist_t* hists,
-                                                  uint64_t* d_codes, const pw_multi_config* cfg,
-                                                  hipStream_t stream) {
+namespace {
+
+// The host part of a call: descriptors, work items and LDS classes.
+struct MultiPlan {
+  std::vector<TriDesc> desc;
+  std::vector<Item> items;  // grouped by class (in launch order), longest first within a class
+  struct Shape {
+    int words, wpb, per_cu;
+  };
+  std::vector<Shape> cls;
+  std::vector<int> order;  // classes in launch order
+  int cls_of_deg[13];
+};
+
+// Device buffers one call runs on: descriptor and item tables, the ticket
+// counter and the overflow list.
+struct MultiBuffers {
+  TriDesc* tris;
+  Item* items;
+  unsigned long long* ticket;
+  unsigned long long* issued;  // host copy: tickets handed out by earlier launches on `ticket`
+  uint64_t* over;
+  unsigned long long* over_n;
+  unsigned long long over_cap;
+};
+
+pw_status plan_multi(const pw_tri_t* tris, int32_t n_tris, const void* d_masks, const int64_t* offsets,
+                     const pw_hist_t* hists, uint64_t* d_codes, const pw_multi_config* cfg, MultiPlan& P) {
   if (!tris || n_tris < 0 || !offsets) return set_err(PW_ERR_ARG, "null or negative argument");
   if (n_tris == 0) return PW_OK;
   if (!hists && !d_codes) return set_err(PW_ERR_ARG, "need histograms, codes or both");
+  if ((uintptr_t)d_codes & 15) return set_err(PW_ERR_ARG, "d_codes must be 16-byte aligned");
   pw_multi_config c = {4096, 1, 0};
   if (cfg) c = *cfg;
   if (c.chunk < 64 || c.chunk > (1 << 24) || c.waves_per_block < 1 || c.waves_per_block > 4 ||
       c.blocks_per_cu < 0 || c.blocks_per_cu > 32)
     return set_err(PW_ERR_ARG, "bad multi config (chunk %d, waves %d, blocks/CU %d)", c.chunk, c.waves_per_block,
                    c.blocks_per_cu);
-  std::vector<TriDesc> desc(n_tris);
-  std::vector<Item> items;
+  std::vector<TriDesc>& desc = P.desc;
+  std::vector<Item>& items = P.items;
+  desc.assign(n_tris, TriDesc{});
+  items.clear();
   for (int t = 0; t < n_tris; ++t) {
     if (!tris[t]) return set_err(PW_ERR_ARG, "null triangulation %d", t);
     if (offsets[t + 1] < offsets[t] || offsets[t] < 0) return set_err(PW_ERR_ARG, "offsets must not decrease");
@@ -253,9 +274,7 @@ extern "C" pw_status patchwork_scheme_batch_multi(const pw_tri_t* tris, int32_t 
   // areas allow the same number of resident blocks per CU (LDS, registers
   // and the configured cap) share a launch sized for the largest of them;
   // the launches follow each other on the stream.
-  struct Shape {
-    int words, wpb, per_cu;
-  };
+  using Shape = MultiPlan::Shape;
   auto shape_for = [&](int words) {
     Shape s{words, c.waves_per_block, 1};
     while (s.wpb > 1 && (size_t)words * 256 * s.wpb > 160 * 1024) --s.wpb;
@@ -272,12 +291,12 @@ extern "C" pw_status patchwork_scheme_batch_multi(const pw_tri_t* tris, int32_t 
     s.per_cu = std::max(1, std::min(per_cu, 32 / s.wpb));
     return s;
   };
-  int cls_of_deg[13];
-  std::vector<Shape> cls;
-  for (int d = 1; d <= 12; ++d) cls_of_deg[d] = -1;
+  std::vector<Shape>& cls = P.cls;
+  cls.clear();
+  for (int d = 0; d <= 12; ++d) P.cls_of_deg[d] = -1;
   for (const TriDesc& t : desc) {
     if (t.d < 1 || t.d > 12) return set_err(PW_ERR_ARG, "degree %d outside 1..12", t.d);
-    if (cls_of_deg[t.d] >= 0) continue;
+    if (P.cls_of_deg[t.d] >= 0) continue;
     const Shape s = shape_for(lane_words_for(t.d));
     if ((size_t)s.words * 256 * s.wpb > 160 * 1024)
       return set_err(PW_ERR_ARG, "block needs %zu bytes of LDS", (size_t)s.words * 256 * s.wpb);
@@ -285,34 +304,102 @@ extern "C" pw_status patchwork_scheme_batch_multi(const pw_tri_t* tris, int32_t 
     while (k < (int)cls.size() && (cls[k].per_cu != s.per_cu || cls[k].wpb != s.wpb)) ++k;
     if (k == (int)cls.size()) cls.push_back(s);
     cls[k].words = std::max(cls[k].words, s.words);
-    cls_of_deg[t.d] = k;
+    P.cls_of_deg[t.d] = k;
   }
   // longest processing time first within a class: cost ~ chunk length x
   // diamond edges; classes with the largest areas go first
-  std::vector<int> order(cls.size());
+  std::vector<int>& order = P.order;
+  order.resize(cls.size());
   for (size_t k = 0; k < cls.size(); ++k) order[k] = (int)k;
   std::sort(order.begin(), order.end(), [&](int a, int b) { return cls[a].words > cls[b].words; });
   std::vector<int> rank(cls.size());
   for (size_t k = 0; k < order.size(); ++k) rank[order[k]] = (int)k;
   std::stable_sort(items.begin(), items.end(), [&](const Item& a, const Item& b) {
-    const int ra = rank[cls_of_deg[desc[a.tri].d]], rb = rank[cls_of_deg[desc[b.tri].d]];
+    const int ra = rank[P.cls_of_deg[desc[a.tri].d]], rb = rank[P.cls_of_deg[desc[b.tri].d]];
     if (ra != rb) return ra < rb;
     const int64_t ca = a.count * n_diamond_edges(desc[a.tri].d), cb = b.count * n_diamond_edges(desc[b.tri].d);
     return ca > cb;
   });
+  return PW_OK;
+}
+
+// Uploads the plan's tables into B, runs one persistent launch per class,
+// then the overflow kernel; returns after the stream has finished.
+pw_status run_multi(const MultiPlan& P, MultiBuffers& B, const void* d_masks, uint64_t* d_codes,
+                    hipStream_t stream) {
+  const std::vector<TriDesc>& desc = P.desc;
+  const std::vector<Item>& items = P.items;
+  // the descriptor and item tables are reused by the next call: the copies
+  // finish before the call returns (it synchronises the stream)
+  PW_HIP(hipMemcpyAsync(B.tris, desc.data(), sizeof(TriDesc) * desc.size(), hipMemcpyHostToDevice, stream));
+  PW_HIP(hipMemcpyAsync(B.items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice, stream));
+  const Overflow ov{B.over, B.over_n, B.over_cap};
+  size_t first = 0;
+  for (const int k : P.order) {
+    size_t last = first;
+    while (last < items.size() && P.cls_of_deg[desc[items[last].tri].d] == k) ++last;
+    const int64_t n = (int64_t)(last - first);
+    if (n == 0) continue;  // a class whose triangulations have no masks
+    const MultiPlan::Shape& s = P.cls[k];
+    const size_t lds = (size_t)s.words * 256 * s.wpb;
+    const int64_t blocks = std::min<int64_t>((int64_t)cu_count() * s.per_cu, (n + s.wpb - 1) / s.wpb);
+    const unsigned long long base = *B.issued;
+    // every wave takes one ticket past the end of its launch before it stops
+    *B.issued += (unsigned long long)n + (unsigned long long)blocks * s.wpb;
+    hipLaunchKernelGGL(k_multi, dim3((unsigned)blocks), dim3(64 * s.wpb), lds, stream, B.tris, B.items + first, n,
+                       B.ticket, base, static_cast<const uint64_t*>(d_masks), d_codes, s.words, ov);
+    const hipError_t le = hipGetLastError();
+    if (le != hipSuccess) {
+      *B.issued = base;  // a launch that failed took no tickets
+      return set_err(PW_ERR_HIP, "k_multi launch: %s (code %d)", hipGetErrorString(le), (int)le);
+    }
+    first = last;
+  }
+  unsigned long long n_over = 0;
+  PW_HIP(hipMemcpyAsync(&n_over, B.over_n, sizeof n_over, hipMemcpyDeviceToHost, stream));
+  PW_HIP(hipStreamSynchronize(stream));
+  if (n_over > B.over_cap)
+    return set_err(PW_ERR_INTERNAL, "%llu masks have more than 31 ovals (at most %llu per call): split the call",
+                   n_over, B.over_cap);
+  if (n_over > 0) {
+    const size_t big_lds = (size_t)Cfg<12>::LANE_WORDS * 4 * 64;
+    static const hipError_t attr_big = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_multi_big),
+                                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (attr_big != hipSuccess) {
+      (void)hipGetLastError();
+      return set_err(PW_ERR_HIP, "hipFuncSetAttribute: %s (code %d)", hipGetErrorString(attr_big), (int)attr_big);
+    }
+    const int64_t nb = std::min<int64_t>(((int64_t)n_over + 63) / 64, (int64_t)cu_count());
+    hipLaunchKernelGGL(k_multi_big, dim3((unsigned)nb), dim3(64), big_lds, stream, B.tris, B.over, (int64_t)n_over,
+                       static_cast<const uint64_t*>(d_masks), d_codes);
+    PW_HIP(hipGetLastError());
+    PW_HIP(hipStreamSynchronize(stream));
+  }
+  return PW_OK;
+}
+
+}  // namespace
+
+extern "C" pw_status patchwork_scheme_batch_multi(const pw_tri_t* tris, int32_t n_tris, const void* d_masks,
+                                                  const int64_t* offsets, const pw_hist_t* hists,
+                                                  uint64_t* d_codes, const pw_multi_config* cfg,
+                                                  hipStream_t stream) {
+  MultiPlan P;
+  const pw_status st = plan_multi(tris, n_tris, d_masks, offsets, hists, d_codes, cfg, P);
+  if (st != PW_OK || P.items.empty()) return st;
   MultiScratch& S = scratch_for_multi();
   std::lock_guard<std::mutex> lock(S.mu);
-  if (S.tri_cap < desc.size()) {
+  if (S.tri_cap < P.desc.size()) {
     if (S.d_tris) (void)hipFree(S.d_tris);
     S.d_tris = nullptr;
-    PW_HIP(hipMalloc(&S.d_tris, sizeof(TriDesc) * desc.size()));
-    S.tri_cap = desc.size();
+    PW_HIP(hipMalloc(&S.d_tris, sizeof(TriDesc) * P.desc.size()));
+    S.tri_cap = P.desc.size();
   }
-  if (S.item_cap < items.size()) {
+  if (S.item_cap < P.items.size()) {
     if (S.d_items) (void)hipFree(S.d_items);
     S.d_items = nullptr;
-    PW_HIP(hipMalloc(&S.d_items, sizeof(Item) * items.size()));
-    S.item_cap = items.size();
+    PW_HIP(hipMalloc(&S.d_items, sizeof(Item) * P.items.size()));
+    S.item_cap = P.items.size();
   }
   if (!S.d_ticket) {
     PW_HIP(hipMalloc(&S.d_ticket, sizeof(unsigned long long)));
@@ -324,51 +411,7 @@ extern "C" pw_status patchwork_scheme_batch_multi(const pw_tri_t* tris, int32_t 
     PW_HIP(hipMalloc(&S.d_over_n, sizeof(unsigned long long)));
   }
   PW_HIP(hipMemsetAsync(S.d_over_n, 0, sizeof(unsigned long long), stream));
-  // the descriptor and item tables are reused by the next call: finish the
-  // copies before returning so the host vectors may go away
-  PW_HIP(hipMemcpyAsync(S.d_tris, desc.data(), sizeof(TriDesc) * desc.size(), hipMemcpyHostToDevice, stream));
-  PW_HIP(hipMemcpyAsync(S.d_items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice, stream));
-  const Overflow ov{S.d_over, S.d_over_n, kOverflowCap};
-  size_t first = 0;
-  for (const int k : order) {
-    size_t last = first;
-    while (last < items.size() && cls_of_deg[desc[items[last].tri].d] == k) ++last;
-    const int64_t n = (int64_t)(last - first);
-    if (n == 0) continue;  // a class whose triangulations have no masks
-    const Shape& s = cls[k];
-    const size_t lds = (size_t)s.words * 256 * s.wpb;
-    const int64_t blocks = std::min<int64_t>((int64_t)cu_count() * s.per_cu, (n + s.wpb - 1) / s.wpb);
-    const unsigned long long base = S.issued;
-    // every wave takes one ticket past the end of its launch before it stops
-    S.issued += (unsigned long long)n + (unsigned long long)blocks * s.wpb;
-    hipLaunchKernelGGL(k_multi, dim3((unsigned)blocks), dim3(64 * s.wpb), lds, stream, S.d_tris, S.d_items + first,
-                       n, S.d_ticket, base, static_cast<const uint64_t*>(d_masks), d_codes, s.words, ov);
-    const hipError_t le = hipGetLastError();
-    if (le != hipSuccess) {
-      S.issued = base;  // a launch that failed took no tickets
-      return set_err(PW_ERR_HIP, "k_multi launch: %s (code %d)", hipGetErrorString(le), (int)le);
-    }
-    first = last;
-  }
-  unsigned long long n_over = 0;
-  PW_HIP(hipMemcpyAsync(&n_over, S.d_over_n, sizeof n_over, hipMemcpyDeviceToHost, stream));
-  PW_HIP(hipStreamSynchronize(stream));
-  if (n_over > kOverflowCap)
-    return set_err(PW_ERR_INTERNAL, "%llu masks have more than 31 ovals (at most %llu per call): split the call",
-                   n_over, kOverflowCap);
-  if (n_over > 0) {
-    const size_t big_lds = (size_t)Cfg<12>::LANE_WORDS * 4 * 64;
-    static const hipError_t attr_big = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_multi_big),
-                                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (attr_big != hipSuccess) {
-      (void)hipGetLastError();
-      return set_err(PW_ERR_HIP, "hipFuncSetAttribute: %s (code %d)", hipGetErrorString(attr_big), (int)attr_big);
-    }
-    const int64_t nb = std::min<int64_t>(((int64_t)n_over + 63) / 64, (int64_t)cu_count());
-    hipLaunchKernelGGL(k_multi_big, dim3((unsigned)nb), dim3(64), big_lds, stream, S.d_tris, S.d_over,
-                       (int64_t)n_over, static_cast<const uint64_t*>(d_masks), d_codes);
-    PW_HIP(hipGetLastError());
-    PW_HIP(hipStreamSynchronize(stream));
-  }
-  return PW_OK;
+  MultiBuffers B{S.d_tris, S.d_items, S.d_ticket, &S.issued, S.d_over, S.d_over_n, kOverflowCap};
+  return run_multi(P, B, d_masks, d_codes, stream);
 }
+

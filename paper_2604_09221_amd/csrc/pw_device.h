@@ -814,6 +814,15 @@ __device__ __forceinline__ Lane lane_memory_split(uint32_t* smem, uint8_t* par) 
               reinterpret_cast<char*>(par) + wave * C::PAR_ROWS * 64 + lane};
 }
 
+// The code of mask i as one 16-byte store (codes must be 16-byte aligned:
+// the entry points check it).
+struct __attribute__((aligned(16))) Code16 {
+  uint64_t lo, hi;
+};
+__device__ __forceinline__ void store_code(uint64_t* __restrict__ codes, int64_t i, u128 code) {
+  *reinterpret_cast<Code16*>(codes + 2 * i) = Code16{(uint64_t)code, (uint64_t)(code >> 64)};
+}
+
 // codes of n masks, one per thread, grid-stride
 template <int D, class EV>
 __device__ __forceinline__ void codes_body(const EV& ev, const void* __restrict__ masks, int64_t n,
@@ -829,19 +838,17 @@ __device__ __forceinline__ void codes_body(const EV& ev, const void* __restrict_
     const bool valid = i < n;
     const typename C::Mask m = valid ? load_mask<D>(masks, i) : (typename C::Mask)0;
     const u128 code = ev(m, L, errs);
-    if (valid) {
-      codes[2 * i] = (uint64_t)code;
-      codes[2 * i + 1] = (uint64_t)(code >> 64);
-    }
+    if (valid) store_code(codes, i, code);
   }
   if (errs) atomicOr(errflag, errs);
 }
 
-// histogram of n masks; each wave takes batches of 64 consecutive masks
+// histogram of n masks; each wave takes batches of 64 consecutive masks;
+// with codes != null the codes are also written (one pass for both)
 template <int D, class EV>
 __device__ __forceinline__ void hist_body(const EV& ev, const void* __restrict__ masks, int64_t n,
-                                          uint64_t index_base, const HistDev* h, uint32_t* __restrict__ errflag,
-                                          uint32_t* smem) {
+                                          uint64_t index_base, const HistDev* h, uint64_t* __restrict__ codes,
+                                          uint32_t* __restrict__ errflag, uint32_t* smem) {
   using C = Cfg<D>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   __shared__ uint8_t par_rows[C::WAVES * C::PAR_ROWS * 64];
@@ -855,6 +862,7 @@ __device__ __forceinline__ void hist_body(const EV& ev, const void* __restrict__
     const bool valid = i < n;
     const typename C::Mask m = valid ? load_mask<D>(masks, i) : (typename C::Mask)0;
     const u128 code = ev(m, L, errs);
+    if (codes && valid) store_code(codes, i, code);
     tab.add_batch((uint64_t)code, (uint64_t)(code >> 64), valid, index_base + (uint64_t)i, lane, h);
   }
   tab.flush(h);

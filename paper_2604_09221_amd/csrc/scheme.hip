@@ -34,9 +34,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Cfg<D>::WAV
 template <int D>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Cfg<D>::WAVES_PER_EU))) void k_hist(const uint32_t* __restrict__ prog, const void* __restrict__ masks,
                                               int64_t n, uint64_t index_base, const HistDev* __restrict__ h,
-                                              uint32_t* __restrict__ errflag) {
+                                              uint64_t* __restrict__ codes, uint32_t* __restrict__ errflag) {
   extern __shared__ uint32_t smem[];
-  hist_body<D>(RtEval<D>{prog}, masks, n, index_base, h, errflag, smem);
+  hist_body<D>(RtEval<D>{prog}, masks, n, index_base, h, codes, errflag, smem);
 }
 
 template <int D>
@@ -125,7 +125,7 @@ pw_status launch_codes(const pw_tri* t, const void* masks, int64_t n, uint64_t* 
 
 template <int D>
 pw_status launch_hist(const pw_tri* t, const void* masks, int64_t n, uint64_t base, const pw_hist* h,
-                      hipStream_t s) {
+                      uint64_t* codes, hipStream_t s) {
   using C = Cfg<D>;
   const int threads = 64 * C::WAVES;
   const size_t lds = (size_t)C::DYN_WORDS * 4 * 64 * C::WAVES;  // + the static parent table
@@ -134,14 +134,15 @@ pw_status launch_hist(const pw_tri* t, const void* masks, int64_t n, uint64_t ba
   if (t->jit_hist && lds <= 64 * 1024) {
     const void* m_ = masks;
     const HistDev* hd = h->d_dev;
+    uint64_t* c_ = codes;
     uint32_t* e_ = t->d_err;
-    void* args[] = {&m_, &n, &base, &hd, &e_};
+    void* args[] = {&m_, &n, &base, &hd, &c_, &e_};
     PW_HIP(hipModuleLaunchKernel(t->jit_hist, blocks_for<D>(threads, n), 1, 1, threads, 1, 1, (unsigned)lds, s, args,
                                  nullptr));
     return PW_OK;
   }
   hipLaunchKernelGGL(k_hist<D>, dim3(blocks_for<D>(threads, n)), dim3(threads), lds, s, t->d_prog, masks, n, base,
-                     h->d_dev, t->d_err);
+                     h->d_dev, codes, t->d_err);
   PW_HIP(hipGetLastError());
   return PW_OK;
 }
@@ -276,6 +277,7 @@ pw_status patchwork_scheme_batch(pw_tri_t t, const void* masks, int64_t n, uint6
   if (n < 0) return set_err(PW_ERR_ARG, "negative mask count %lld", (long long)n);
   if (n == 0) return PW_OK;
   if (!masks || !codes) return set_err(PW_ERR_ARG, "null device buffer");
+  if ((uintptr_t)codes & 15) return set_err(PW_ERR_ARG, "d_codes must be 16-byte aligned");
   PW_DISPATCH(t->prog.d, launch_codes, t, masks, n, codes, s);
 }
 
@@ -384,7 +386,17 @@ pw_status patchwork_scheme_histogram(pw_tri_t t, const void* masks, int64_t n, u
   if (n < 0) return set_err(PW_ERR_ARG, "negative mask count %lld", (long long)n);
   if (n == 0) return PW_OK;
   if (!masks) return set_err(PW_ERR_ARG, "null device buffer");
-  PW_DISPATCH(t->prog.d, launch_hist, t, masks, n, index_base, h, s);
+  PW_DISPATCH(t->prog.d, launch_hist, t, masks, n, index_base, h, nullptr, s);
+}
+
+pw_status patchwork_scheme_codes_histogram(pw_tri_t t, const void* masks, int64_t n, uint64_t index_base,
+                                           uint64_t* codes, pw_hist_t h, hipStream_t s) {
+  if (!t || !h) return set_err(PW_ERR_ARG, "null handle");
+  if (n < 0) return set_err(PW_ERR_ARG, "negative mask count %lld", (long long)n);
+  if (n == 0) return PW_OK;
+  if (!masks || !codes) return set_err(PW_ERR_ARG, "null device buffer");
+  if ((uintptr_t)codes & 15) return set_err(PW_ERR_ARG, "d_codes must be 16-byte aligned");
+  PW_DISPATCH(t->prog.d, launch_hist, t, masks, n, index_base, h, codes, s);
 }
 
 // The runs of free bits for an enumeration and the check of its range.

@@ -65,6 +65,7 @@ def lib():
     L.pw_hist_read.argtypes = [vp, u64p, u64p, u64p, i32, i32p]
     L.pw_hist_destroy.argtypes = [vp]
     L.patchwork_scheme_histogram.argtypes = [vp, vp, i64, u64, vp, vp]
+    L.patchwork_scheme_codes_histogram.argtypes = [vp, vp, i64, u64, vp, vp, vp]
     L.patchwork_scheme_enumerate_range.argtypes = [vp, u64, u64, u64p, vp, vp]
     L.patchwork_scheme_sweep_graph.argtypes = [vp, u64, u64, u64, u64p, vp, vp]
     L.pw_tri_specialize.argtypes = [vp]
@@ -75,7 +76,7 @@ def lib():
                                                ctypes.POINTER(vp), vp, ctypes.POINTER(MultiConfig), vp]
     for name in ("pw_tri_create", "pw_tri_destroy", "pw_tri_info", "pw_tri_errors", "patchwork_scheme_batch",
                  "pw_hist_create", "pw_hist_reset", "pw_hist_read", "pw_hist_destroy",
-                 "patchwork_scheme_histogram", "patchwork_scheme_enumerate_range", "patchwork_scheme_sweep_graph",
+                 "patchwork_scheme_histogram", "patchwork_scheme_codes_histogram", "patchwork_scheme_enumerate_range", "patchwork_scheme_sweep_graph",
                  "patchwork_scheme_batch_multi",
                  "pw_tri_specialize", "pw_jit_source", "pw_jit_compile"):
         getattr(L, name).restype = i32
@@ -182,6 +183,17 @@ class Triangulation:
         n = masks.numel() * masks.element_size() // mask_bytes(self.d)
         check(lib().patchwork_scheme_histogram(self.handle, _ptr(masks), n, int(index_base), hist.handle,
                                                _stream(stream)))
+
+    def codes_histogram(self, masks, hist: "Histogram", codes=None, index_base: int = 0, stream=None):
+        """Codes and histogram of the same masks in one pass -> codes."""
+        import torch
+
+        n = masks.numel() * masks.element_size() // mask_bytes(self.d)
+        if codes is None:
+            codes = torch.empty((n, 2), dtype=torch.int64, device=masks.device)
+        check(lib().patchwork_scheme_codes_histogram(self.handle, _ptr(masks), n, int(index_base), _ptr(codes),
+                                                     hist.handle, _stream(stream)))
+        return codes
 
     def enumerate_range(self, first: int, count: int, hist: "Histogram", fixed_zero_bits: int = 1, stream=None):
         fz = (ctypes.c_uint64 * 2)(fixed_zero_bits & 0xFFFFFFFFFFFFFFFF, fixed_zero_bits >> 64)

@@ -415,3 +415,36 @@ def test_sweep_graph_new_histogram_after_destroy(pw):
         assert h.read() == want
         h.close()
     assert tri.errors() == 0
+
+
+# ------------------------------------------------- codes and histogram in one pass
+
+@pytest.mark.parametrize("spec", [False, True])
+def test_codes_histogram_fused(pw, spec):
+    """patchwork_scheme_codes_histogram: the codes equal the oracle's and the
+    histogram (counts, witnesses) equals the one of those codes, for ragged
+    sizes at d = 4, 6 (varied lifts) and 8; a misaligned code buffer is an
+    argument error."""
+    for d, seed, n in ((4, 1, (1 << 14) - 3), (6, 5, (1 << 16) + 77), (8, 2, 20001)):
+        E = I.lift_triangulation(d, seed, noise=1.0)
+        tri = pw.Triangulation(d, E)
+        if spec:
+            tri.specialize()
+        masks = I.random_masks(d, 40 + seed, n)
+        mt = pw.mask_tensor(masks, d)
+        hist = pw.Histogram(1024)
+        codes = tri.codes_histogram(mt, hist, index_base=7)
+        torch.cuda.synchronize()
+        got = codes.cpu().numpy().view(np.uint64)
+        want = oracle.scheme_many(d, E, masks, threads=THREADS)
+        assert np.array_equal(got, want)
+        assert hist.read() == oracle_hist(want, index_of=np.arange(7, 7 + n, dtype=np.uint64))
+        assert tri.errors() == 0
+    buf = torch.empty((n + 1) * 2, dtype=torch.int64, device="cuda")
+    mis = buf[1:2 * n + 1]                                   # 8 bytes off a 16-byte boundary
+    with pytest.raises(pw.PatchworkError) as e:
+        tri.codes_histogram(mt, hist, codes=mis)
+    assert e.value.status == pw.PW_ERR_ARG
+    with pytest.raises(pw.PatchworkError) as e:
+        tri.batch(mt, mis)
+    assert e.value.status == pw.PW_ERR_ARG
