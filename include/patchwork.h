@@ -248,6 +248,34 @@ pw_status patchwork_scheme_batch_multi(const pw_tri_t *tris, int32_t n_tris, con
                                        const int64_t *offsets, const pw_hist_t *hists, uint64_t *d_codes,
                                        const pw_multi_config *cfg, hipStream_t stream);
 
+/*
+ * patchwork_scheme_batch_multi for callers that cannot allocate device
+ * memory (code that must not call hipMalloc: tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, launches and results as
+ * patchwork_scheme_batch_multi; its descriptor and work-item tables, ticket
+ * counter and overflow list live in one fixed device array of the library
+ * (about 7.4 MiB per GPU, held from the first call on that GPU until the
+ * process ends) instead of buffers the library allocates.  It calls no
+ * hipMalloc or hipFree.  Limits: n_tris <= PW_NOALLOC_MAX_TRIS; at most
+ * PW_NOALLOC_MAX_ITEMS work items (sum over t of ceil(masks of t / chunk));
+ * at most PW_NOALLOC_MAX_OVERFLOW masks of degree >= 10 with more than 31
+ * ovals per call.  Beyond the first two: PW_ERR_ARG before anything is
+ * launched; beyond the third: PW_ERR_INTERNAL (split the call).  Every call
+ * on one GPU uses that GPU's array and keeps nothing in it between calls
+ * (the counters are cleared at the start of each).  Calls that overlapped
+ * on one GPU would race on it, so the library serialises calls from the
+ * threads of a process, and a call returns only after its launches have
+ * finished; after an error return, synchronise `stream` before the next
+ * call, since a launch made before the error may still be running.
+ */
+#define PW_NOALLOC_MAX_TRIS 4096
+#define PW_NOALLOC_MAX_ITEMS 262144
+#define PW_NOALLOC_MAX_OVERFLOW 65536
+
+pw_status patchwork_scheme_batch_multi_noalloc(const pw_tri_t *tris, int32_t n_tris, const void *d_masks,
+                                               const int64_t *offsets, const pw_hist_t *hists, uint64_t *d_codes,
+                                               const pw_multi_config *cfg, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Learned proposal of sign distributions.
  *

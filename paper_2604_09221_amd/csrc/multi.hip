@@ -201,6 +201,28 @@ MultiScratch& scratch_for_multi() {
   return s;
 }
 
+// Fixed device array of patchwork_scheme_batch_multi_noalloc: the ticket
+// counter and the overflow count, the descriptor table, the work-item table
+// and the overflow list of one call, at the offsets below.  Every GPU the
+// library runs on holds its own copy until the process ends.  Host code
+// never passes `scratch` itself to a kernel (in host code the name is a
+// stand-in, not a device address): it uses the address returned for the
+// current device by hipGetSymbolAddress.
+constexpr size_t kNaTicket = 0;                                         // u64
+constexpr size_t kNaOverN = 8;                                          // u64
+constexpr size_t kNaTris = 256;                                         // TriDesc[PW_NOALLOC_MAX_TRIS]
+constexpr size_t kNaItems = kNaTris + sizeof(TriDesc) * PW_NOALLOC_MAX_TRIS;  // Item[PW_NOALLOC_MAX_ITEMS]
+constexpr size_t kNaOver = kNaItems + sizeof(Item) * PW_NOALLOC_MAX_ITEMS;    // u64[2 * PW_NOALLOC_MAX_OVERFLOW]
+constexpr size_t kNaBytes = kNaOver + sizeof(uint64_t) * 2 * PW_NOALLOC_MAX_OVERFLOW;
+static_assert(kNaItems % 256 == 0 && kNaOver % 256 == 0, "scratch sections stay 256-byte aligned");
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+__global__ void k_clear_u64(uint64_t* p, int n) {
+  const int i = (int)threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
 }  // namespace pw
 
 using namespace pw;
@@ -415,3 +437,64 @@ extern "C" pw_status patchwork_scheme_batch_multi(const pw_tri_t* tris, int32_t 
   return run_multi(P, B, d_masks, d_codes, stream);
 }
 
+namespace {
+
+constexpr int kNaMaxDevices = 64;
+
+// Address of `scratch` on each device, looked up once per device (with that
+// device current) on the first call there.
+struct NoallocState {
+  std::mutex mu;
+  unsigned char* ptr[kNaMaxDevices] = {};
+};
+
+NoallocState& noalloc_state() {
+  static NoallocState s;
+  return s;
+}
+
+}  // namespace
+
+extern "C" pw_status patchwork_scheme_batch_multi_noalloc(const pw_tri_t* tris, int32_t n_tris,
+                                                          const void* d_masks, const int64_t* offsets,
+                                                          const pw_hist_t* hists, uint64_t* d_codes,
+                                                          const pw_multi_config* cfg, hipStream_t stream) {
+  if (n_tris > PW_NOALLOC_MAX_TRIS)
+    return set_err(PW_ERR_ARG, "%d triangulations: the allocation-free call takes at most %d", n_tris,
+                   PW_NOALLOC_MAX_TRIS);
+  MultiPlan P;
+  const pw_status st = plan_multi(tris, n_tris, d_masks, offsets, hists, d_codes, cfg, P);
+  if (st != PW_OK || P.items.empty()) return st;
+  if (P.items.size() > (size_t)PW_NOALLOC_MAX_ITEMS)
+    return set_err(PW_ERR_ARG, "%zu work items: the allocation-free call takes at most %d (use larger chunks)",
+                   P.items.size(), PW_NOALLOC_MAX_ITEMS);
+  int dev = 0;
+  PW_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNaMaxDevices) return set_err(PW_ERR_ARG, "device %d beyond %d", dev, kNaMaxDevices);
+  NoallocState& S = noalloc_state();
+  std::lock_guard<std::mutex> lock(S.mu);
+  if (!S.ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return set_err(PW_ERR_HIP, "hipGetSymbolAddress(scratch): %s (code %d)", hipGetErrorString(e), (int)e);
+    }
+    S.ptr[dev] = static_cast<unsigned char*>(p);
+  }
+  unsigned char* const base = S.ptr[dev];
+  // ticket counter and overflow count start at zero in every call (a fill
+  // kernel, not a memset: the stream may belong to a caller that records
+  // graphs elsewhere)
+  hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(64), 0, stream, reinterpret_cast<uint64_t*>(base + kNaTicket), 2);
+  PW_HIP(hipGetLastError());
+  unsigned long long issued = 0;
+  MultiBuffers B{reinterpret_cast<TriDesc*>(base + kNaTris),
+                 reinterpret_cast<Item*>(base + kNaItems),
+                 reinterpret_cast<unsigned long long*>(base + kNaTicket),
+                 &issued,
+                 reinterpret_cast<uint64_t*>(base + kNaOver),
+                 reinterpret_cast<unsigned long long*>(base + kNaOverN),
+                 (unsigned long long)PW_NOALLOC_MAX_OVERFLOW};
+  return run_multi(P, B, d_masks, d_codes, stream);
+}

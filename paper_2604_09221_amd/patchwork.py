@@ -74,10 +74,11 @@ def lib():
     L.pw_jit_compile.argtypes = [i32, i16p, i32, ctypes.POINTER(ctypes.c_int64)]
     L.patchwork_scheme_batch_multi.argtypes = [ctypes.POINTER(vp), i32, vp, ctypes.POINTER(ctypes.c_int64),
                                                ctypes.POINTER(vp), vp, ctypes.POINTER(MultiConfig), vp]
+    L.patchwork_scheme_batch_multi_noalloc.argtypes = L.patchwork_scheme_batch_multi.argtypes
     for name in ("pw_tri_create", "pw_tri_destroy", "pw_tri_info", "pw_tri_errors", "patchwork_scheme_batch",
                  "pw_hist_create", "pw_hist_reset", "pw_hist_read", "pw_hist_destroy",
                  "patchwork_scheme_histogram", "patchwork_scheme_codes_histogram", "patchwork_scheme_enumerate_range", "patchwork_scheme_sweep_graph",
-                 "patchwork_scheme_batch_multi",
+                 "patchwork_scheme_batch_multi", "patchwork_scheme_batch_multi_noalloc",
                  "pw_tri_specialize", "pw_jit_source", "pw_jit_compile"):
         getattr(L, name).restype = i32
     _lib = L
@@ -271,7 +272,7 @@ class Histogram:
         return out
 
 
-def batch_multi(tris, masks128, offsets, hists=None, codes=None, config=None, stream=None):
+def batch_multi(tris, masks128, offsets, hists=None, codes=None, config=None, stream=None, noalloc=False):
     """Many triangulations (any mix of degrees) in one call: one persistent
     launch per LDS class of degrees, back to back on the stream.
 
@@ -279,7 +280,9 @@ def batch_multi(tris, masks128, offsets, hists=None, codes=None, config=None, st
     t owns masks [offsets[t], offsets[t+1]).  hists: list of Histogram (one
     per triangulation) or None; codes: (n,2) int64 device tensor or None.
     config: (chunk, waves_per_block, blocks_per_cu), or None for the tuned
-    shape from the tuning cache (defaults if there is none)."""
+    shape from the tuning cache (defaults if there is none).  noalloc: use
+    patchwork_scheme_batch_multi_noalloc (the library's fixed device array
+    instead of buffers it allocates)."""
     n = len(tris)
     off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
     if len(off) != n + 1:
@@ -291,7 +294,8 @@ def batch_multi(tris, masks128, offsets, hists=None, codes=None, config=None, st
 
         config = tune.lookup_multi([t.d for t in tris])
     cfg = MultiConfig(*config) if config is not None else None
-    check(lib().patchwork_scheme_batch_multi(
+    fn = lib().patchwork_scheme_batch_multi_noalloc if noalloc else lib().patchwork_scheme_batch_multi
+    check(fn(
         th, n, _ptr(masks128), off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
         hh, _ptr(codes) if codes is not None else None, ctypes.byref(cfg) if cfg is not None else None,
         _stream(stream)))
