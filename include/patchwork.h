@@ -119,6 +119,52 @@ pw_status pw_tri_errors(pw_tri_t tri, uint32_t *flags);
  */
 pw_status pw_tri_specialize(pw_tri_t tri);
 
+/* Copy the handle's program (the reflected diamond in the layout the
+ * kernels walk: per diamond vertex its lattice point, reflection parity and
+ * earlier neighbours, then the 2d antipodal pairs; Alg. 1, first steps) into
+ * a host buffer of cap words; *n_words receives its length (words may be
+ * NULL to query it).  Host memory only; PW_ERR_ARG if cap is too small. */
+pw_status pw_tri_program(pw_tri_t tri, uint32_t *words, int32_t cap, int32_t *n_words);
+
+/* ------------------------------------------------------------------------
+ * Symmetries of the search space (Sec. 3, Table 1).  Host calls; no device
+ * work.
+ *
+ * S3 acts on d*Delta_2 by permuting the barycentric coordinates
+ * (i, j, d-i-j); permutation k in 0..5 is the k-th of (0,1,2) (0,2,1)
+ * (1,0,2) (1,2,0) (2,0,1) (2,1,0) in this order, sending (i, j) to
+ * (b[P0], b[P1]) with b = (i, j, d-i-j).  It maps a triangulation T and a
+ * sign distribution sigma to (pi T, sigma o pi^-1), which have the same
+ * real scheme, so one member of each orbit of triangulations (6 members, 3
+ * for those fixed by a transposition, 1 for the fully symmetric) stands for
+ * all.  (Z/2)^3 acts on sign distributions by sigma -> sigma + a + b i + c j
+ * (mod 2), freely and without changing the scheme: one representative per
+ * class covers 8 distributions.
+ * ---------------------------------------------------------------------- */
+
+/* Canonical member of the S3 orbit of T: the image whose edge list (each
+ * edge with its endpoints in point-index order, edges sorted by the point
+ * indices of their endpoints) is lexicographically least, written to
+ * out_edges (host, n_edges x 4, in that order; may be NULL); *perm_index
+ * receives a permutation k that maps T to it and *stabilizer the number of
+ * permutations fixing T (1, 2, 3 or 6; the orbit has 6 / stabilizer
+ * members).  T is validated as in pw_tri_create (PW_ERR_TRI). */
+pw_status pw_tri_canonical(int32_t d, const int16_t *edges_ij, int32_t n_edges, int16_t *out_edges,
+                           int32_t *perm_index, int32_t *stabilizer);
+
+/* out[k] = index of the image under permutation perm_index of lattice point
+ * k, for k < |A| (host array).  A sign mask maps to the permuted
+ * triangulation's by moving bit k to bit out[k]. */
+pw_status pw_point_map(int32_t d, int32_t perm_index, int32_t *out);
+
+/* The fixed_zero_bits (two uint64 words) that make
+ * patchwork_scheme_enumerate_range visit one representative of each
+ * (Z/2)^3 class: sigma = '+' at (0,0) and at two points of distinct nonzero
+ * parity classes (i mod 2, j mod 2), taken from lattice point 10 on when
+ * the degree allows (so points 1..9 stay free and the sweep kernel with a
+ * shared snapshot applies).  The free bits number |A| - 3.  d >= 2. */
+pw_status pw_class_fixed_bits(int32_t d, uint64_t out[2]);
+
 /* The source text pw_tri_specialize compiles for the triangulation given
  * by (d, edges_ij, n_edges) (validated as in pw_tri_create), into a host
  * buffer of cap bytes, NUL-terminated and truncated to fit; *len receives
@@ -275,6 +321,100 @@ pw_status patchwork_scheme_batch_multi(const pw_tri_t *tris, int32_t n_tris, con
 pw_status patchwork_scheme_batch_multi_noalloc(const pw_tri_t *tris, int32_t n_tris, const void *d_masks,
                                                const int64_t *offsets, const pw_hist_t *hists, uint64_t *d_codes,
                                                const pw_multi_config *cfg, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Search over triangulations (Sec. 3: the second search mode checks many
+ * (symmetric) triangulations against a few witness sign distributions;
+ * simulated annealing over triangulations optimises the number of distinct
+ * types or a target (p, n) count).
+ *
+ * A triangulation of d*Delta_2, d <= 9, lives in device memory as 64
+ * uint64 adjacency rows: bit q of row p is set iff lattice points p and q
+ * (numbered as for sign masks) are joined by an edge; rows >= |A| are 0.
+ * A batch of n triangulations is n x 64 uint64, contiguous.  Every buffer
+ * named d_* is device memory owned by the caller; calls are asynchronous
+ * on `stream`.
+ * ---------------------------------------------------------------------- */
+
+/* Host: the adjacency rows (64 uint64, host) of an edge list, validated as
+ * in pw_tri_create.  d <= 9.  Errors: PW_ERR_ARG, PW_ERR_TRI. */
+pw_status pw_adjacency_from_edges(int32_t d, const int16_t *edges_ij, int32_t n_edges, uint64_t *rows);
+
+/* Host: the edge list (i0, j0, i1, j1 rows, endpoints in increasing point
+ * order, edges in increasing order) of 64 adjacency rows, into edges_ij of
+ * cap rows; *n_edges receives the count (edges_ij may be NULL to query).
+ * PW_ERR_TRI for an asymmetric adjacency or bits beyond |A|. */
+pw_status pw_edges_from_adjacency(int32_t d, const uint64_t *rows, int16_t *edges_ij, int32_t cap,
+                                  int32_t *n_edges);
+
+/*
+ * Random walks in the flip graph, in place: `steps` proposed moves on each
+ * of n_tris triangulations (one wavefront each).  A flip replaces an
+ * interior edge ab, whose two unimodular triangles abc, abe form a
+ * parallelogram (c + e = a + b), by the diagonal ce (the flips connect all
+ * unimodular triangulations of d*Delta_2).  Move s of triangulation w draws
+ * r1 = F(seed ^ F(w * 0x100000001B3 + 2 (step0 + s))) and r2 the same with
+ * + 1 (F = the SplitMix64 finaliser): a = r1 mod |A|, b = the
+ * (r2 mod deg a)-th neighbour of a in increasing point order, and ab is
+ * flipped if it can be.  symmetric != 0 keeps (i, j) -> (j, i) symmetry
+ * (the input must be symmetric): an edge mapped to itself is flipped
+ * alone; otherwise ab and its mirror image are flipped together when both
+ * can be and their quadrilaterals share no triangle; other moves change
+ * nothing.  d_moves (n_tris uint32, or NULL) is incremented by the number of
+ * moves made.  d <= 9.
+ */
+pw_status pw_flip_walk(int32_t d, uint64_t *d_adj, int64_t n_tris, int32_t steps, int32_t symmetric, uint64_t seed,
+                       uint64_t step0, uint32_t *d_moves, hipStream_t stream);
+
+/* Words of one triangulation's program (the layout of pw_tri_program):
+ * |A<>| + |E(T<>)| + 2d. */
+int32_t pw_program_words(int32_t d);
+
+/* The program of each of n_tris triangulations (d_adj) built on the device
+ * into d_progs (n_tris x pw_program_words(d) uint32), word for word what
+ * pw_tri_create builds for the same edge list.  d_bad[t] (uint32) becomes
+ * non-zero if triangulation t's program could not be built (its adjacency
+ * is not a unimodular triangulation); its program is then unusable. d <= 9. */
+pw_status pw_build_programs(int32_t d, const uint64_t *d_adj, int64_t n_tris, uint32_t *d_progs, uint32_t *d_bad,
+                            hipStream_t stream);
+
+/*
+ * Every triangulation of a batch against every witness (Alg. 1 for each of
+ * n_tris x n_w pairs): d_progs as built by pw_build_programs (any degree
+ * 1..12), d_masks n_w witnesses of two uint64 words each.  The code of
+ * (t, w) goes to d_codes[t * n_w + w] (n_tris x n_w x 2 uint64, 16-byte
+ * aligned, or NULL) and/or into `hist` (or NULL) with witness t * n_w + w.
+ * d_err (one uint32) accumulates the device consistency flags of
+ * pw_tri_errors.
+ */
+pw_status patchwork_scheme_programs(int32_t d, const uint32_t *d_progs, int64_t n_tris, const uint64_t *d_masks,
+                                    int64_t n_w, uint64_t *d_codes, pw_hist_t hist, uint32_t *d_err,
+                                    hipStream_t stream);
+
+/* Score of each triangulation over its n_w codes d_codes[t * n_w ..], as
+ * float: mode 0 = number of distinct codes (the number of types it
+ * realises on those witnesses), mode 1 = number of codes whose scheme has
+ * (p, n) = (target_p, target_n) (p ovals at odd depth, outermost = depth 1;
+ * n at even depth).  Codes 0 count for nothing.  d <= 9, n_w <= 8192. */
+pw_status pw_tri_objective(int32_t d, const uint64_t *d_codes, int64_t n_tris, int32_t n_w, int32_t mode,
+                           int32_t target_p, int32_t target_n, float *d_score, hipStream_t stream);
+
+/*
+ * Metropolis step of simulated annealing over triangulations (maximising
+ * the score), for n_chains chains of adjacency rows: the proposal d_prop
+ * (scored d_score_prop) replaces d_cur (d_score_cur) if it scores at least
+ * as high, or else if u < d_accept[k - 1], k = score_cur - score_prop (the
+ * scores are whole numbers), u = the top 24 bits of
+ * F(seed ^ F(chain * 0x100000001B3 + step)); d_accept holds
+ * floor(2^24 exp(-k / temperature)) for k = 1 .. n_accept, computed by the
+ * caller (0 beyond).  Then d_prop is set equal to d_cur.  d_best /
+ * d_score_best keep each chain's best state; d_n_accepted[chain] counts
+ * accepted proposals.
+ */
+pw_status pw_anneal_accept(uint64_t *d_cur, uint64_t *d_prop, float *d_score_cur, const float *d_score_prop,
+                           uint64_t *d_best, float *d_score_best, int64_t n_chains, const uint32_t *d_accept,
+                           int32_t n_accept, uint64_t seed, uint64_t step, uint32_t *d_n_accepted,
+                           hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Learned proposal of sign distributions.

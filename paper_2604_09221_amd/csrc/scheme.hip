@@ -264,6 +264,16 @@ pw_status pw_tri_info(pw_tri_t t, int32_t* d, int32_t* n_points_, int32_t* n_ver
   return PW_OK;
 }
 
+pw_status pw_tri_program(pw_tri_t t, uint32_t* words, int32_t cap, int32_t* n_words) {
+  if (!t) return set_err(PW_ERR_ARG, "null handle");
+  if (n_words) *n_words = t->prog.n_words;
+  if (words) {
+    if (cap < t->prog.n_words) return set_err(PW_ERR_ARG, "program has %d words, buffer %d", t->prog.n_words, cap);
+    std::memcpy(words, t->prog.words, sizeof(uint32_t) * t->prog.n_words);
+  }
+  return PW_OK;
+}
+
 pw_status pw_tri_errors(pw_tri_t t, uint32_t* flags) {
   if (!t || !flags) return set_err(PW_ERR_ARG, "null argument");
   PW_HIP(hipDeviceSynchronize());

@@ -75,6 +75,22 @@ def lib():
     L.patchwork_scheme_batch_multi.argtypes = [ctypes.POINTER(vp), i32, vp, ctypes.POINTER(ctypes.c_int64),
                                                ctypes.POINTER(vp), vp, ctypes.POINTER(MultiConfig), vp]
     L.patchwork_scheme_batch_multi_noalloc.argtypes = L.patchwork_scheme_batch_multi.argtypes
+    L.pw_tri_program.argtypes = [vp, u32p, i32, i32p]
+    L.pw_tri_canonical.argtypes = [i32, i16p, i32, i16p, i32p, i32p]
+    L.pw_point_map.argtypes = [i32, i32, i32p]
+    L.pw_class_fixed_bits.argtypes = [i32, u64p]
+    L.pw_program_words.argtypes = [i32]
+    L.pw_adjacency_from_edges.argtypes = [i32, i16p, i32, u64p]
+    L.pw_edges_from_adjacency.argtypes = [i32, u64p, i16p, i32, i32p]
+    L.pw_flip_walk.argtypes = [i32, vp, i64, i32, i32, u64, u64, vp, vp]
+    L.pw_build_programs.argtypes = [i32, vp, i64, vp, vp, vp]
+    L.patchwork_scheme_programs.argtypes = [i32, vp, i64, vp, i64, vp, vp, vp, vp]
+    L.pw_tri_objective.argtypes = [i32, vp, i64, i32, i32, i32, i32, vp, vp]
+    L.pw_anneal_accept.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp, i32, u64, u64, vp, vp]
+    for name in ("pw_tri_program", "pw_tri_canonical", "pw_point_map", "pw_class_fixed_bits", "pw_program_words",
+                 "pw_adjacency_from_edges", "pw_edges_from_adjacency", "pw_flip_walk", "pw_build_programs",
+                 "patchwork_scheme_programs", "pw_tri_objective", "pw_anneal_accept"):
+        getattr(L, name).restype = i32
     for name in ("pw_tri_create", "pw_tri_destroy", "pw_tri_info", "pw_tri_errors", "patchwork_scheme_batch",
                  "pw_hist_create", "pw_hist_reset", "pw_hist_read", "pw_hist_destroy",
                  "patchwork_scheme_histogram", "patchwork_scheme_codes_histogram", "patchwork_scheme_enumerate_range", "patchwork_scheme_sweep_graph",
@@ -165,6 +181,15 @@ class Triangulation:
         check(lib().pw_tri_specialize(self.handle))
         return self
 
+    def program(self) -> np.ndarray:
+        """The handle's program words (host copy)."""
+        n = ctypes.c_int32()
+        check(lib().pw_tri_program(self.handle, None, 0, ctypes.byref(n)))
+        w = np.zeros(n.value, dtype=np.uint32)
+        check(lib().pw_tri_program(self.handle, w.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), n.value,
+                                   ctypes.byref(n)))
+        return w
+
     def errors(self) -> int:
         f = ctypes.c_uint32()
         check(lib().pw_tri_errors(self.handle, ctypes.byref(f)))
@@ -231,6 +256,31 @@ def jit_compile(d: int, edges) -> int:
     n = ctypes.c_int64()
     check(lib().pw_jit_compile(d, p, len(e), ctypes.byref(n)))
     return n.value
+
+
+def canonical(d: int, edges):
+    """S3-canonical member of the triangulation's orbit: (edges (n,4)
+    int16, permutation index mapping the input to it, stabiliser order)."""
+    e, p = _edges16(edges)
+    out = np.zeros_like(e)
+    k, st = ctypes.c_int32(), ctypes.c_int32()
+    check(lib().pw_tri_canonical(d, p, len(e), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int16)), ctypes.byref(k),
+                                 ctypes.byref(st)))
+    return out, k.value, st.value
+
+
+def point_map(d: int, perm_index: int) -> np.ndarray:
+    """Image index of every lattice point under an S3 permutation."""
+    out = np.zeros((d + 1) * (d + 2) // 2, dtype=np.int32)
+    check(lib().pw_point_map(d, perm_index, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return out
+
+
+def class_fixed_bits(d: int) -> int:
+    """fixed_zero_bits of the (Z/2)^3 class representatives (as an int)."""
+    out = (ctypes.c_uint64 * 2)()
+    check(lib().pw_class_fixed_bits(d, out))
+    return int(out[0]) | (int(out[1]) << 64)
 
 
 class Histogram:
@@ -300,3 +350,89 @@ def batch_multi(tris, masks128, offsets, hists=None, codes=None, config=None, st
         hh, _ptr(codes) if codes is not None else None, ctypes.byref(cfg) if cfg is not None else None,
         _stream(stream)))
     return codes
+
+
+# ---------------------------------------------------------------- search
+# Triangulations on the device: int64 tensors of shape (n, 64), row p =
+# neighbour bits of lattice point p (pw_flip_walk and the calls below).
+
+def program_words(d: int) -> int:
+    n = lib().pw_program_words(d)
+    if n < 0:
+        raise PatchworkError(n, "degree out of range")
+    return n
+
+
+def adjacency_from_edges(d: int, edges) -> np.ndarray:
+    """Edge list -> 64 adjacency rows (uint64; validated as pw_tri_create)."""
+    e, p = _edges16(edges)
+    rows = np.zeros(64, dtype=np.uint64)
+    check(lib().pw_adjacency_from_edges(d, p, len(e), rows.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+    return rows
+
+
+def edges_from_adjacency(d: int, rows) -> np.ndarray:
+    """64 adjacency rows -> edge list (n, 4) int16."""
+    r = np.ascontiguousarray(np.asarray(rows).view(np.uint64).reshape(64))
+    rp = r.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+    n = ctypes.c_int32()
+    check(lib().pw_edges_from_adjacency(d, rp, None, 0, ctypes.byref(n)))
+    out = np.zeros((n.value, 4), dtype=np.int16)
+    check(lib().pw_edges_from_adjacency(d, rp, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int16)), n.value,
+                                        ctypes.byref(n)))
+    return out
+
+
+def flip_walk(d: int, adj, steps: int, symmetric: bool, seed: int, step0: int = 0, moves=None, stream=None):
+    """`steps` random flip moves on every triangulation of adj (in place)."""
+    check(lib().pw_flip_walk(d, _ptr(adj), adj.shape[0], int(steps), int(bool(symmetric)), int(seed), int(step0),
+                             _ptr(moves) if moves is not None else None, _stream(stream)))
+
+
+def build_programs(d: int, adj, progs=None, bad=None, stream=None):
+    """Diamond programs of every triangulation of adj -> (progs, bad)."""
+    import torch
+
+    n = adj.shape[0]
+    if progs is None:
+        progs = torch.empty((n, program_words(d)), dtype=torch.int32, device=adj.device)
+    if bad is None:
+        bad = torch.empty(n, dtype=torch.int32, device=adj.device)
+    check(lib().pw_build_programs(d, _ptr(adj), n, _ptr(progs), _ptr(bad), _stream(stream)))
+    return progs, bad
+
+
+def scheme_programs(d: int, progs, masks128, codes=None, hist=None, err=None, stream=None):
+    """Codes of every (triangulation, witness) pair: progs (n, words),
+    masks128 two int64 words per witness -> codes (n * n_w, 2) or None."""
+    import torch
+
+    n_tris = progs.shape[0]
+    n_w = masks128.numel() // 2
+    if err is None:
+        err = torch.zeros(1, dtype=torch.int32, device=progs.device)
+    check(lib().patchwork_scheme_programs(d, _ptr(progs), n_tris, _ptr(masks128), n_w,
+                                          _ptr(codes) if codes is not None else None,
+                                          hist.handle if hist is not None else None, _ptr(err), _stream(stream)))
+    return codes, err
+
+
+def tri_objective(d: int, codes, n_tris: int, n_w: int, mode: int = 0, target=(0, 0), score=None, stream=None):
+    """Per-triangulation score over its n_w codes: mode 0 distinct codes,
+    mode 1 codes with (p, n) = target."""
+    import torch
+
+    if score is None:
+        score = torch.empty(n_tris, dtype=torch.float32, device=codes.device)
+    check(lib().pw_tri_objective(d, _ptr(codes), n_tris, n_w, mode, int(target[0]), int(target[1]), _ptr(score),
+                                 _stream(stream)))
+    return score
+
+
+def anneal_accept(cur, prop, score_cur, score_prop, best, score_best, accept_table, seed: int, step: int,
+                  n_accepted, stream=None):
+    """Metropolis accept/reject of every chain (pw_anneal_accept)."""
+    n = cur.shape[0]
+    check(lib().pw_anneal_accept(_ptr(cur), _ptr(prop), _ptr(score_cur), _ptr(score_prop), _ptr(best),
+                                 _ptr(score_best), n, _ptr(accept_table), accept_table.numel(), int(seed), int(step),
+                                 _ptr(n_accepted), _stream(stream)))

@@ -1,0 +1,273 @@
+"""Search over triangulations (Sec. 3), orchestrated on the host, computed
+on the device.
+
+* ``mode2_sweep``: the second search mode -- many triangulations (random
+  walks in the flip graph, optionally keeping the (i, j) -> (j, i)
+  symmetry) judged against a pool of witness sign distributions.  Walks,
+  programs and evaluation all run on the GPU (``pw_flip_walk``,
+  ``pw_build_programs``, ``patchwork_scheme_programs``); only the
+  histogram of codes comes back.
+* ``anneal``: simulated annealing over triangulations, each chain scored by
+  the number of distinct types it realises on a fixed sample of sign
+  distributions, or by how many of them reach a target (p, n); proposals
+  are single (symmetric) flip moves, accepted by the Metropolis rule
+  (``pw_tri_objective``, ``pw_anneal_accept``).
+* ``iterate``: the witness <-> triangulation loop: sweep every sign class of
+  the selected triangulations (one witness per new type), sweep generated
+  triangulations against the accumulated witnesses, select the
+  triangulations that realise new types, repeat until nothing new appears.
+
+Types count as realised only with a regular triangulation (Viro's
+patchworking needs a convex one; ``regular.certificate`` gives an exact
+certificate), and every witness kept is re-evaluated by the exact kernel.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import inputs as I
+from . import orbits
+from . import patchwork as pw
+from . import regular
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def replicate(d: int, edges, n: int, device="cuda"):
+    """n copies of one triangulation as device adjacency rows (n, 64) int64."""
+    torch = _torch()
+    rows = pw.adjacency_from_edges(d, edges).view(np.int64)
+    return torch.from_numpy(np.tile(rows, (n, 1))).to(device)
+
+
+def edges_of(d: int, adj_row) -> np.ndarray:
+    """Edge list of one device (or host) adjacency row block."""
+    r = adj_row.cpu().numpy() if hasattr(adj_row, "cpu") else np.asarray(adj_row)
+    return pw.edges_from_adjacency(d, r.view(np.uint64))
+
+
+def witness_tensor(masks2, device="cuda"):
+    """(n, 2) uint64 host masks -> flat int64 device tensor."""
+    torch = _torch()
+    return torch.from_numpy(I.masks128(np.asarray(masks2, dtype=np.uint64).reshape(-1, 2))).to(device)
+
+
+@dataclass
+class Mode2Result:
+    d: int
+    n_tris: int
+    n_w: int
+    hist: dict                      # code -> (count over all pairs, smallest pair index t * n_w + w)
+    adj: object                     # the batch's adjacency rows (device)
+    gpu_seconds: float
+
+    def pair(self, code):
+        """(triangulation index, witness index) of a code's witness pair."""
+        gi = self.hist[code][1]
+        return gi // self.n_w, gi % self.n_w
+
+
+def mode2_sweep(d: int, witnesses, n_tris: int, walk_steps: int, seed: int, start=None, symmetric: bool = True,
+                capacity: int = 1 << 14, adj=None) -> Mode2Result:
+    """Generate n_tris triangulations by `walk_steps` random (symmetric)
+    flip moves from `start` (default: the standard triangulation), or take
+    the device batch `adj`, and judge each against every witness."""
+    torch = _torch()
+    if adj is None:
+        adj = replicate(d, start if start is not None else I.standard_triangulation(d), n_tris)
+        t0 = time.perf_counter()
+        pw.flip_walk(d, adj, walk_steps, symmetric, seed)
+    else:
+        t0 = time.perf_counter()
+    progs, bad = pw.build_programs(d, adj)
+    wt = witness_tensor(witnesses, adj.device)
+    h = pw.Histogram(capacity)
+    _, err = pw.scheme_programs(d, progs, wt, hist=h)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    if int(bad.max().item()) != 0 or int(err.item()) != 0:
+        raise pw.PatchworkError(pw.PW_ERR_INTERNAL, "a generated triangulation failed its program or evaluation checks")
+    return Mode2Result(d, adj.shape[0], len(np.asarray(witnesses).reshape(-1, 2)), h.read(), adj, dt)
+
+
+@dataclass
+class AnnealResult:
+    d: int
+    best: object                    # (n_chains, 64) device adjacency of each chain's best state
+    best_score: np.ndarray
+    final_score: np.ndarray
+    accepted: np.ndarray
+    masks: np.ndarray               # the fixed sample of sign distributions the score is taken on
+    gpu_seconds: float
+    trace: list = field(default_factory=list)   # (iteration, max score, mean score)
+
+
+def accept_table(temperature: float, n: int = 64) -> np.ndarray:
+    """floor(2^24 exp(-k / temperature)) for k = 1..n (uint32)."""
+    k = np.arange(1, n + 1, dtype=np.float64)
+    return np.floor((1 << 24) * np.exp(-k / max(temperature, 1e-9))).astype(np.uint32)
+
+
+def score_batch(d, adj, masks_t, n_w, mode, target):
+    progs, bad = pw.build_programs(d, adj)
+    n = adj.shape[0]
+    torch = _torch()
+    codes = torch.empty((n * n_w, 2), dtype=torch.int64, device=adj.device)
+    _, err = pw.scheme_programs(d, progs, masks_t, codes=codes)
+    score = pw.tri_objective(d, codes, n, n_w, mode, target)
+    return score, codes, bad, err
+
+
+def anneal(d: int, n_chains: int, iters: int, n_masks: int = 1024, mode: int = 0, target=(0, 0),
+           t_start: float = 4.0, t_end: float = 0.25, seed: int = 1, symmetric: bool = False, start=None,
+           scramble: int = 64, log_every: int = 0) -> AnnealResult:
+    """Simulated annealing over triangulations of degree d (<= 9), n_chains
+    chains in parallel, maximising `mode` (0: distinct types on the sample,
+    1: sample masks whose scheme has (p, n) = target).  The temperature
+    falls geometrically from t_start to t_end; each chain starts from
+    `start` (default standard) after `scramble` random moves."""
+    torch = _torch()
+    dev = "cuda"
+    masks = I.random_masks(d, 0xA77 + seed, n_masks)
+    mt = witness_tensor(masks, dev)
+    cur = replicate(d, start if start is not None else I.standard_triangulation(d), n_chains, dev)
+    t0 = time.perf_counter()
+    if scramble:
+        pw.flip_walk(d, cur, scramble, symmetric, seed ^ 0x5C, step0=0)
+    prop = cur.clone()
+    best = cur.clone()
+    score_cur, _, bad, err = score_batch(d, cur, mt, n_masks, mode, target)
+    score_best = score_cur.clone()
+    n_acc = torch.zeros(n_chains, dtype=torch.int32, device=dev)
+    tables = np.stack([accept_table(t_start * (t_end / t_start) ** (k / max(1, iters - 1))) for k in range(iters)])
+    tables_t = torch.from_numpy(tables.view(np.int32)).to(dev)
+    trace = []
+    for it in range(iters):
+        pw.flip_walk(d, prop, 1, symmetric, seed, step0=1 << 20 | it)
+        score_prop, _, bad_p, err_p = score_batch(d, prop, mt, n_masks, mode, target)
+        pw.anneal_accept(cur, prop, score_cur, score_prop, best, score_best, tables_t[it], seed, it, n_acc)
+        if log_every and (it % log_every == 0 or it == iters - 1):
+            s = score_cur.cpu().numpy()
+            trace.append((it, float(s.max()), float(s.mean())))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    if int(bad.max().item()) or int(err.item()) or int(bad_p.max().item()) or int(err_p.item()):
+        raise pw.PatchworkError(pw.PW_ERR_INTERNAL, "a chain's triangulation failed its program or evaluation checks")
+    return AnnealResult(d, best, score_best.cpu().numpy(), score_cur.cpu().numpy(),
+                        n_acc.cpu().numpy(), masks, dt, trace)
+
+
+@dataclass
+class Realised:
+    edges: np.ndarray
+    mask: int
+    regular: bool
+
+
+@dataclass
+class IterateResult:
+    d: int
+    found: dict                     # code -> Realised (a regular triangulation and a witness)
+    rounds: list                    # per round: dict of counts and seconds
+    gpu_seconds: float
+
+
+def _canon_key(d, E):
+    c, _, _ = pw.canonical(d, E)
+    return c.tobytes()
+
+
+def iterate(d: int, pool, n_tris: int = 4096, walk_steps: int = 64, max_rounds: int = 8, seed: int = 0,
+            symmetric: bool = True, capacity: int = 1 << 14, max_selected: int = 32, log=None) -> IterateResult:
+    """The witness <-> triangulation loop of Sec. 3 from an initial pool of
+    triangulations.  Each round: (1) every (Z/2)^3 class of each selected
+    triangulation is swept (its orbit-canonical member), one witness kept
+    per new type; (2) n_tris triangulations generated by random
+    (symmetric) walks from the selected and pool triangulations are judged
+    against all witnesses; (3) those realising new types, once certified
+    regular, are selected for the next round.  Stops when a round adds
+    nothing."""
+    found: dict = {}
+    witnesses: list = []
+    rounds = []
+    selected = {}
+    for E in pool:
+        selected.setdefault(_canon_key(d, E), np.asarray(E))
+    starts = list(selected.values())
+    t_all = 0.0
+    for r in range(max_rounds):
+        info = {"round": r, "swept": len(selected)}
+        t0 = time.perf_counter()
+        new_from_sweeps = 0
+        for E in list(selected.values())[:max_selected]:
+            res = orbits.orbit_sweep(d, E, capacity=capacity, specialize=False)
+            for code, (_, widx) in res.hist.items():
+                if code in found:
+                    continue
+                m = res.class_mask(widx)
+                found[code] = Realised(res.canonical_edges, m, True)
+                witnesses.append(m)
+                new_from_sweeps += 1
+        t_sweep = time.perf_counter() - t0
+        info["new_from_class_sweeps"] = new_from_sweeps
+        wm = np.zeros((len(witnesses), 2), dtype=np.uint64)
+        wm[:, 0] = [m & ((1 << 64) - 1) for m in witnesses]
+        # generated triangulations: walks from the triangulations met so far
+        per = max(1, n_tris // max(1, len(starts)))
+        torch = _torch()
+        adj = torch.cat([replicate(d, E, per) for E in starts], 0)
+        pw.flip_walk(d, adj, walk_steps, symmetric, seed * 1000 + r)
+        m2 = mode2_sweep(d, wm, adj.shape[0], 0, 0, adj=adj, capacity=capacity)
+        info["mode2_pairs"] = adj.shape[0] * len(witnesses)
+        info["mode2_seconds"] = m2.gpu_seconds
+        nxt = {}
+        new_regular = 0
+        for code, (_, gi) in m2.hist.items():
+            if code in found:
+                continue
+            t, w = gi // m2.n_w, gi % m2.n_w
+            E = edges_of(d, adj[t])
+            if not regular.is_regular(d, E):
+                continue
+            found[code] = Realised(E, witnesses[w], True)
+            nxt.setdefault(_canon_key(d, E), E)
+            new_regular += 1
+        info["new_from_mode2"] = new_regular
+        info["sweep_seconds"] = t_sweep
+        info["distinct"] = len(found)
+        t_all += time.perf_counter() - t0
+        rounds.append(info)
+        if log:
+            log(info)
+        if not nxt and new_from_sweeps == 0:
+            break
+        selected = nxt
+        starts = (starts + list(nxt.values()))[-64:]
+    return IterateResult(d, found, rounds, t_all)
+
+
+def schemes_text(codes) -> list:
+    """Rohlin-Viro strings of codes (display only)."""
+    out = []
+    for c in sorted(codes):
+        bits = bin(c & ((1 << 127) - 1))[3:]
+        out.append((c, bits))
+    return out
+
+
+def certify(d: int, res: IterateResult, check) -> int:
+    """Re-evaluate every kept (triangulation, witness) with `check(d, edges,
+    mask) -> code` and return how many agree."""
+    return sum(check(d, r.edges, r.mask) == code for code, r in res.found.items())
+
+
+__all__ = ["replicate", "edges_of", "mode2_sweep", "anneal", "iterate", "accept_table", "Mode2Result",
+           "AnnealResult", "IterateResult", "math"]
