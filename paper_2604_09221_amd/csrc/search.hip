@@ -178,7 +178,8 @@ __device__ __forceinline__ int vid(int d, int x, int y) {
 
 // visit the diamond neighbours of vertex (x, y): the reflections (ex iq,
 // ey jq) of the triangulation's neighbours q of (|x|, |y|), ex over the
-// signs that map |x| to x (both when x = 0, once when iq = 0)
+// signs that map |x| to x (both when x = 0, but once when iq = 0 too, as
+// both give the same vertex), ey likewise
 template <class F>
 __device__ __forceinline__ void for_each_nbr(int d, int x, int y, uint64_t rowp, const int8_t* pti,
                                              const int8_t* ptj, F&& f) {
@@ -188,10 +189,10 @@ __device__ __forceinline__ void for_each_nbr(int d, int x, int y, uint64_t rowp,
     const int iq = pti[q], jq = ptj[q];
     for (int sx = -1; sx <= 1; sx += 2) {
       if (x != 0 && (sx < 0) != (x < 0)) continue;
-      if (iq == 0 && sx < 0) continue;
+      if (iq == 0 && x == 0 && sx < 0) continue;  // (0, .) once
       for (int sy = -1; sy <= 1; sy += 2) {
         if (y != 0 && (sy < 0) != (y < 0)) continue;
-        if (jq == 0 && sy < 0) continue;
+        if (jq == 0 && y == 0 && sy < 0) continue;
         f(vid(d, sx * iq, sy * jq));
       }
     }
@@ -302,7 +303,17 @@ __global__ __launch_bounds__(64) void k_build_programs(int d, const uint64_t* __
       const int r = rank - dup_below;
       if (r < 2 * d) prog[nV + nE + r] = (key >> 16) | ((key & 0xFFFFu) << 16);
     }
-    if (lane == 0) bad[t] = err;
+    // a program that could not be built keeps no neighbour lists (every
+    // count and offset 0, every listed neighbour vertex 0), so that an
+    // evaluation of it reads only its own words and in-range vertices (and
+    // fails its checks)
+    const bool any_err = __ballot(err != 0) != 0;
+    if (any_err) {
+      __syncthreads();
+      for (int v = lane; v < nV; v += 64) prog[v] &= 0xFFu;
+      for (int k = lane; k < nE; k += 64) prog[nV + k] = 0;
+    }
+    if (lane == 0) bad[t] = any_err ? 1u : 0u;
   }
 }
 
@@ -584,6 +595,12 @@ pw_status pw_tri_objective(int32_t d, const uint64_t* d_codes, int64_t n_tris, i
   int cap = 64;
   while (cap < 2 * n_w) cap <<= 1;
   const size_t lds = mode == 0 ? sizeof(uint64_t) * cap : 0;
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_objective),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (attr != hipSuccess) {
+    (void)hipGetLastError();
+    return set_err(PW_ERR_HIP, "hipFuncSetAttribute: %s (code %d)", hipGetErrorString(attr), (int)attr);
+  }
   const int64_t blocks = std::min<int64_t>(n_tris, (int64_t)cu_count() * 8);
   hipLaunchKernelGGL(k_objective, dim3((unsigned)blocks), dim3(64), lds, stream, d_codes, n_tris, n_w, mode, target_p,
                      target_n, cap, d_score);
