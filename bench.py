@@ -511,10 +511,8 @@ def bench_orbit(args):
     = '+') of the same triangulation, sampled class ranges equal the
     oracle's, and every witness mapped back to the input triangulation gives
     its code on the oracle."""
-    import numpy as np
     import torch
 
-    import oracle
     from paper_2604_09221_amd import inputs as I
     from paper_2604_09221_amd import orbits
     from paper_2604_09221_amd import patchwork as pw
@@ -557,31 +555,10 @@ def bench_orbit(args):
     assert {c: 4 * n for c, (n, _) in h.items()} == {c: n for c, (n, _) in hf.items()}, \
         "class histogram x 4 differs from the full sweep"
     res = orbits.OrbitSweep(d, canon, k_perm, stab, fixed, n_classes, h)
-    threads = os.cpu_count() or 1
-    for code, (_, widx) in h.items():
-        m_in = res.witness_for_input(widx)
-        assert oracle.scheme(d, E, m_in) == code, "a class witness does not map back to the input triangulation"
-    rng = np.random.default_rng(7)
-    free = ((1 << I.n_points(d)) - 1) & ~fixed
-    sampled = 0
-    for _ in range(24):
-        a = int(rng.integers(0, n_classes // 512)) * 512
-        kk = 512 if sampled % 3 else int(rng.integers(1, 700))
-        m = np.zeros((kk, 2), dtype=np.uint64)
-        m[:, 0] = [I.pdep(a + j, free) for j in range(kk)]
-        ref = {}
-        for j, (lo, hi) in enumerate(oracle.scheme_many(d, canon, m, threads=threads)):
-            c = int(lo) | (int(hi) << 64)
-            cnt, w = ref.get(c, (0, a + j))
-            ref[c] = (cnt + 1, min(w, a + j))
-        hk = pw.Histogram(512)
-        tri.enumerate_range(a, kk, hk, fixed_zero_bits=fixed)
-        assert hk.read() == ref, f"class range [{a}, {a + kk}) differs from the oracle"
-        sampled += 1
     value = args.steps * n_classes / elapsed
     ops = algorithmic_ops_per_mask(d) * n_classes
     achieved = ops / launch_s / 1e12
-    return {
+    out = {
         "metric": "sign-distribution classes/sec at d=7, orbit-reduced (bit-exact)",
         "value": value, "unit": "masks/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -590,8 +567,7 @@ def bench_orbit(args):
                                "orbit, all 2^33 (Z/2)^3 class representatives per step, in-kernel, histogram",
                    "s3_stabilizer": stab, "orbit_size": 6 // stab, "classes_per_step": n_classes,
                    "distinct_schemes": len(h), "specialize_seconds": t_spec,
-                   "checks": {"class_hist_x4_equals_full_sweep": True, "witnesses_map_back": len(h),
-                              "oracle_sampled_class_ranges": sampled}},
+                   "checks": {"class_hist_x4_equals_full_sweep": True}},
         "effective": {"value": value * 8 * (6 // stab), "unit": "(T, sigma) pairs/s",
                       "note": "each class stands for 8 sign distributions of each of the orbit's "
                               f"{6 // stab} triangulations; not masks classified"},
@@ -600,6 +576,171 @@ def bench_orbit(args):
                      "kernel": "pw_jit_enum_snap (specialised, shared snapshot per 512 masks)",
                      "ops_per_mask": algorithmic_ops_per_mask(d), "avg_launch_ms": launch_s * 1e3},
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = orbit_cpu_baseline(d, E, res, tri)
+    return out
+
+
+def orbit_cpu_baseline(d, E, res, tri):
+    """The oracle on the orbit sweep's workload: 24 class ranges at random
+    positions of the 2^33 classes (16 whole 512-class chunks, 8 ragged),
+    timed on the host's threads and checked equal to the GPU sweep kernel's
+    histograms of the same ranges; and every class witness, mapped back to
+    the input triangulation, gives its code."""
+    import numpy as np
+
+    import oracle
+    from paper_2604_09221_amd import inputs as I
+    from paper_2604_09221_amd import patchwork as pw
+
+    threads = os.cpu_count() or 1
+    for code, (_, widx) in res.hist.items():
+        if oracle.scheme(d, E, res.witness_for_input(widx)) != code:
+            raise AssertionError("a class witness does not map back to the input triangulation")
+    rng = np.random.default_rng(7)
+    free = ((1 << I.n_points(d)) - 1) & ~res.fixed_zero_bits
+    n_done, dt = 0, 0.0
+    for k in range(24):
+        a = int(rng.integers(0, res.classes // 512)) * 512
+        kk = 512 if k % 3 else int(rng.integers(1, 700))
+        m = np.zeros((kk, 2), dtype=np.uint64)
+        m[:, 0] = [I.pdep(a + j, free) for j in range(kk)]
+        t0 = time.perf_counter()
+        codes = oracle.scheme_many(d, res.canonical_edges, m, threads=threads)
+        dt += time.perf_counter() - t0
+        n_done += kk
+        ref = {}
+        for j, (lo, hi) in enumerate(codes):
+            c = int(lo) | (int(hi) << 64)
+            cnt, w = ref.get(c, (0, a + j))
+            ref[c] = (cnt + 1, min(w, a + j))
+        hk = pw.Histogram(512)
+        tri.enumerate_range(a, kk, hk, fixed_zero_bits=res.fixed_zero_bits)
+        if hk.read() != ref:
+            raise AssertionError(f"class range [{a}, {a + kk}) differs from the oracle")
+    return {"value": n_done / dt, "unit": "masks/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_done} class representatives in 24 ranges at random positions of the 2^33 classes, "
+                      f"plain C oracle on {threads} host threads; the GPU sweep kernel's histograms of the same "
+                      f"ranges equal, and all {len(res.hist)} class witnesses map back to masks of the input "
+                      f"triangulation with the same code"}
+
+
+def bench_search(args):
+    """The search over triangulations at d=6 (Sec. 3): simulated annealing
+    over triangulations (chains scored by the number of distinct types they
+    realise on 1024 fixed random sign distributions), then the witness <->
+    triangulation loop from the annealing's best triangulations and the
+    standard one: exhaustive class sweeps of the selected triangulations
+    (one witness per new type), second-mode sweeps of 4096 symmetric
+    triangulations (random symmetric flip walks, generated on the GPU)
+    against all witnesses, selection of the regular triangulations that
+    realise new types, until a round adds nothing.  The paper states that
+    all 55 non-empty real schemes of degree six are realised by T-curves;
+    none beyond them can appear.  `value` is the second mode's throughput:
+    (triangulation, witness) pairs per second including the generation of
+    the triangulations and their programs.  Every kept (triangulation,
+    witness) is re-evaluated by the oracle and every kept triangulation
+    carries an exact regularity certificate."""
+    import numpy as np
+    import torch
+
+    from paper_2604_09221_amd import inputs as I
+    from paper_2604_09221_amd import patchwork as pw
+    from paper_2604_09221_amd import regular
+    from paper_2604_09221_amd import search as S
+
+    d = 6
+    torch.cuda.set_device(0)
+    t_all = time.perf_counter()
+    # warm-up: load the kernels once
+    S.mode2_sweep(d, I.random_masks(d, 1, 64), 64, 4, 1)
+    ann = S.anneal(d, n_chains=args.chains, iters=args.iters, n_masks=1024, mode=0, seed=args.seed,
+                   symmetric=False, log_every=max(1, args.iters // 8))
+    sa_evals = args.chains * (args.iters + 1) * 1024
+    order = np.argsort(-ann.best_score)
+    rows = ann.best.cpu().numpy()
+    pool, keys = [I.standard_triangulation(d)], set()
+    for t in order:
+        E = pw.edges_from_adjacency(d, rows[t].view(np.uint64))
+        k = pw.canonical(d, E)[0].tobytes()
+        if k in keys or not regular.is_regular(d, E):
+            continue
+        keys.add(k)
+        pool.append(E)
+        if len(pool) > args.pool:
+            break
+    res = S.iterate(d, pool, n_tris=args.slots, walk_steps=64, max_rounds=args.rounds, seed=args.seed,
+                    target_count=55, log=lambda info: print(json.dumps(info), file=sys.stderr, flush=True))
+    total_s = time.perf_counter() - t_all
+    assert all(regular.certificate(d, r.edges) is not None for r in res.found.values())
+    assert len(res.found) <= 55
+    m2_pairs = sum(r["mode2_pairs"] for r in res.rounds)
+    m2_s = sum(r["mode2_seconds"] for r in res.rounds)
+    out = {
+        "metric": "triangulation x witness pairs/sec, second search mode at d=6 (generation included)",
+        "value": m2_pairs / m2_s, "unit": "pairs/s", "n_gpus": 1, "steps": len(res.rounds), "warmup": 1,
+        "ms_per_step": res.gpu_seconds / max(1, len(res.rounds)) * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "d=6 search: annealing over triangulations (distinct types on 1024 random sign "
+                               "distributions), then the witness <-> triangulation loop with 4096 symmetric "
+                               "triangulations per round",
+                   "annealing": {"chains": args.chains, "iterations": args.iters, "evaluations": sa_evals,
+                                 "seconds": ann.gpu_seconds, "evaluations_per_s": sa_evals / ann.gpu_seconds,
+                                 "best_score": float(ann.best_score.max()),
+                                 "start_score": float(ann.trace[0][1]) if ann.trace else None,
+                                 "pool_triangulations": len(pool)},
+                   "rounds": res.rounds,
+                   "distinct_nonempty_schemes": len(res.found), "paper_total_degree6": 55,
+                   "schemes": sorted(S.scheme_text(c) for c in res.found),
+                   "all_55_found": len(res.found) == 55,
+                   "seconds_total": total_s,
+                   "checks": {"regularity_certificates": len(res.found), "at_most_55": True}},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = search_cpu_baseline(d, res)
+    return out
+
+
+def search_cpu_baseline(d, res):
+    """The oracle on the second search mode's workload: 512 generated
+    symmetric triangulations against the found types' witnesses, timed on
+    the host's threads, with the GPU's codes for the same pairs checked
+    equal; and every kept (triangulation, witness) re-evaluated (each must
+    give its code)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2604_09221_amd import inputs as I
+    from paper_2604_09221_amd import patchwork as pw
+    from paper_2604_09221_amd import search as S
+
+    agree = S.certify(d, res, lambda d_, E, m: oracle.scheme(d_, E, m))
+    if agree != len(res.found):
+        raise AssertionError("a kept witness does not reproduce its code on the oracle")
+    n_t = 512
+    wm = np.zeros((len(res.found), 2), dtype=np.uint64)
+    wm[:, 0] = [r.mask for r in res.found.values()]
+    adj = S.replicate(d, I.standard_triangulation(d), n_t)
+    pw.flip_walk(d, adj, 64, True, 4242)
+    progs, _ = pw.build_programs(d, adj)
+    codes = torch.zeros((n_t * len(wm), 2), dtype=torch.int64, device="cuda")
+    pw.scheme_programs(d, progs, S.witness_tensor(wm), codes=codes)
+    got = codes.cpu().numpy().view(np.uint64).reshape(n_t, len(wm), 2)
+    rows = adj.cpu().numpy()
+    edges = [pw.edges_from_adjacency(d, rows[t].view(np.uint64)) for t in range(n_t)]
+    threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    want = [oracle.scheme_many(d, E, wm, threads=threads) for E in edges]
+    dt = time.perf_counter() - t0
+    for t in range(n_t):
+        if not np.array_equal(got[t], want[t]):
+            raise AssertionError(f"second-mode codes of generated triangulation {t} differ from the oracle")
+    return {"value": n_t * len(wm) / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_t} symmetric triangulations (64 random symmetric flip moves from the standard one) x "
+                      f"{len(wm)} witnesses (one per type found) on {threads} host threads; the GPU's codes for "
+                      f"these pairs equal, and all {agree} kept (triangulation, witness) pairs reproduce their "
+                      f"codes on the oracle"}
 
 
 FIG2 = {"bow_tie": 123, "rank016": 359, "rank015": 353}  # distinct real schemes printed with Fig. 2
@@ -686,7 +827,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=1 << 24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--config", choices=("d7", "d4", "d6", "orbit", "multi", "learned", "gemm", "copyprobe", "fig2",
+    ap.add_argument("--config", choices=("d7", "d4", "d6", "orbit", "search", "multi", "learned", "gemm", "copyprobe", "fig2",
                                          "fig2-check"),
                     default="d7")
     ap.add_argument("--tri", choices=sorted(FIG2), default="rank016", help="--config fig2: the triangulation")
@@ -694,6 +835,11 @@ def main():
     ap.add_argument("--parts", type=int, default=2, help="--config fig2: parts of the 2^42 sweep")
     ap.add_argument("inputs", nargs="*", help="--config fig2-check: the parts' JSON outputs")
     ap.add_argument("--slots", type=int, default=4096)
+    ap.add_argument("--chains", type=int, default=256, help="--config search: annealing chains")
+    ap.add_argument("--iters", type=int, default=300, help="--config search: annealing iterations")
+    ap.add_argument("--pool", type=int, default=8, help="--config search: annealed triangulations kept")
+    ap.add_argument("--rounds", type=int, default=10, help="--config search: witness <-> triangulation rounds")
+    ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--varied", action="store_true")
     ap.add_argument("--tune", action="store_true")
     ap.add_argument("--budget-log2", type=int, default=26)
@@ -721,6 +867,9 @@ def main():
         return
     if args.config == "multi":
         print(json.dumps(bench_multi(args)), flush=True)
+        return
+    if args.config == "search":
+        print(json.dumps(bench_search(args)), flush=True)
         return
     if args.config == "orbit":
         print(json.dumps(bench_orbit(args)), flush=True)

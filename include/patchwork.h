@@ -395,9 +395,13 @@ pw_status patchwork_scheme_programs(int32_t d, const uint32_t *d_progs, int64_t 
  * float: mode 0 = number of distinct codes (the number of types it
  * realises on those witnesses), mode 1 = number of codes whose scheme has
  * (p, n) = (target_p, target_n) (p ovals at odd depth, outermost = depth 1;
- * n at even depth).  Codes 0 count for nothing.  d <= 9, n_w <= 8192. */
+ * n at even depth), mode 2 = number of distinct codes whose low word is not
+ * in d_known (n_known uint64 in increasing order: the types found so far).
+ * Codes 0 count for nothing.  d <= 9 (a code's low word then holds all of
+ * it but the J bit), n_w <= 8192. */
 pw_status pw_tri_objective(int32_t d, const uint64_t *d_codes, int64_t n_tris, int32_t n_w, int32_t mode,
-                           int32_t target_p, int32_t target_n, float *d_score, hipStream_t stream);
+                           int32_t target_p, int32_t target_n, const uint64_t *d_known, int32_t n_known,
+                           float *d_score, hipStream_t stream);
 
 /*
  * Metropolis step of simulated annealing over triangulations (maximising

@@ -377,22 +377,37 @@ __device__ __forceinline__ void code_pn(uint64_t lo, int& p, int& n) {
   }
 }
 
+// true iff lo is in the sorted list known[0 .. n_known)
+__device__ __forceinline__ bool in_sorted(const uint64_t* __restrict__ known, int n_known, uint64_t lo) {
+  int a = 0, b = n_known;
+  while (a < b) {
+    const int m = (a + b) >> 1;
+    if (known[m] < lo) a = m + 1;
+    else b = m;
+  }
+  return a < n_known && known[a] == lo;
+}
+
 // One wave per triangulation over its n_w codes (t * n_w .. + n_w - 1):
 // mode 0 = number of distinct codes (an open-addressing set in LDS of
 // `cap` slots, cap a power of two >= 2 n_w); mode 1 = number of codes
-// with (p, n) = (tp, tn).  Failed evaluations (code 0) count for nothing.
+// with (p, n) = (tp, tn); mode 2 = number of distinct codes not in the
+// sorted list `known` (the types a triangulation adds to those found).
+// Failed evaluations (code 0) count for nothing.
 __global__ __launch_bounds__(64) void k_objective(const uint64_t* __restrict__ codes, int64_t n_tris, int n_w,
-                                                  int mode, int tp, int tn, int cap, float* __restrict__ score) {
+                                                  int mode, int tp, int tn, const uint64_t* __restrict__ known,
+                                                  int n_known, int cap, float* __restrict__ score) {
   extern __shared__ uint64_t slots[];
   const int lane = threadIdx.x;
   for (int64_t t = blockIdx.x; t < n_tris; t += gridDim.x) {
     int count = 0;
-    if (mode == 0) {
+    if (mode != 1) {
       for (int s = lane; s < cap; s += 64) slots[s] = 0;
       __syncthreads();
       for (int w = lane; w < n_w; w += 64) {
         const uint64_t lo = codes[2 * (t * n_w + w)];
         if (lo == 0) continue;
+        if (mode == 2 && in_sorted(known, n_known, lo)) continue;
         uint32_t s = (uint32_t)((lo * 0x9E3779B97F4A7C15ull) >> 40) & (uint32_t)(cap - 1);
         while (true) {
           const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&slots[s]), 0ull,
@@ -587,14 +602,16 @@ pw_status patchwork_scheme_programs(int32_t d, const uint32_t* d_progs, int64_t 
 }
 
 pw_status pw_tri_objective(int32_t d, const uint64_t* d_codes, int64_t n_tris, int32_t n_w, int32_t mode,
-                           int32_t target_p, int32_t target_n, float* d_score, hipStream_t stream) {
-  if (d < 1 || d > kSearchMaxDegree || n_tris < 0 || n_w < 0 || n_w > 8192 || (mode != 0 && mode != 1))
+                           int32_t target_p, int32_t target_n, const uint64_t* d_known, int32_t n_known,
+                           float* d_score, hipStream_t stream) {
+  if (d < 1 || d > kSearchMaxDegree || n_tris < 0 || n_w < 0 || n_w > 8192 || mode < 0 || mode > 2 ||
+      n_known < 0)
     return set_err(PW_ERR_ARG, "bad objective arguments (d %d, n_w %d, mode %d)", d, n_w, mode);
   if (n_tris == 0) return PW_OK;
-  if (!d_codes || !d_score) return set_err(PW_ERR_ARG, "null buffer");
+  if (!d_codes || !d_score || (mode == 2 && n_known > 0 && !d_known)) return set_err(PW_ERR_ARG, "null buffer");
   int cap = 64;
   while (cap < 2 * n_w) cap <<= 1;
-  const size_t lds = mode == 0 ? sizeof(uint64_t) * cap : 0;
+  const size_t lds = mode != 1 ? sizeof(uint64_t) * cap : 0;
   static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_objective),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   if (attr != hipSuccess) {
@@ -603,7 +620,7 @@ pw_status pw_tri_objective(int32_t d, const uint64_t* d_codes, int64_t n_tris, i
   }
   const int64_t blocks = std::min<int64_t>(n_tris, (int64_t)cu_count() * 8);
   hipLaunchKernelGGL(k_objective, dim3((unsigned)blocks), dim3(64), lds, stream, d_codes, n_tris, n_w, mode, target_p,
-                     target_n, cap, d_score);
+                     target_n, d_known, mode == 2 ? n_known : 0, cap, d_score);
   PW_HIP(hipGetLastError());
   return PW_OK;
 }

@@ -85,7 +85,7 @@ def lib():
     L.pw_flip_walk.argtypes = [i32, vp, i64, i32, i32, u64, u64, vp, vp]
     L.pw_build_programs.argtypes = [i32, vp, i64, vp, vp, vp]
     L.patchwork_scheme_programs.argtypes = [i32, vp, i64, vp, i64, vp, vp, vp, vp]
-    L.pw_tri_objective.argtypes = [i32, vp, i64, i32, i32, i32, i32, vp, vp]
+    L.pw_tri_objective.argtypes = [i32, vp, i64, i32, i32, i32, i32, vp, i32, vp, vp]
     L.pw_anneal_accept.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp, i32, u64, u64, vp, vp]
     for name in ("pw_tri_program", "pw_tri_canonical", "pw_point_map", "pw_class_fixed_bits", "pw_program_words",
                  "pw_adjacency_from_edges", "pw_edges_from_adjacency", "pw_flip_walk", "pw_build_programs",
@@ -417,15 +417,18 @@ def scheme_programs(d: int, progs, masks128, codes=None, hist=None, err=None, st
     return codes, err
 
 
-def tri_objective(d: int, codes, n_tris: int, n_w: int, mode: int = 0, target=(0, 0), score=None, stream=None):
+def tri_objective(d: int, codes, n_tris: int, n_w: int, mode: int = 0, target=(0, 0), known=None, score=None,
+                  stream=None):
     """Per-triangulation score over its n_w codes: mode 0 distinct codes,
-    mode 1 codes with (p, n) = target."""
+    mode 1 codes with (p, n) = target, mode 2 distinct codes whose low word
+    is not in `known` (sorted int64 device tensor)."""
     import torch
 
     if score is None:
         score = torch.empty(n_tris, dtype=torch.float32, device=codes.device)
-    check(lib().pw_tri_objective(d, _ptr(codes), n_tris, n_w, mode, int(target[0]), int(target[1]), _ptr(score),
-                                 _stream(stream)))
+    nk = int(known.numel()) if known is not None else 0
+    check(lib().pw_tri_objective(d, _ptr(codes), n_tris, n_w, mode, int(target[0]), int(target[1]),
+                                 _ptr(known) if nk else None, nk, _ptr(score), _stream(stream)))
     return score
 
 

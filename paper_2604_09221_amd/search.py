@@ -116,35 +116,47 @@ def accept_table(temperature: float, n: int = 64) -> np.ndarray:
     return np.floor((1 << 24) * np.exp(-k / max(temperature, 1e-9))).astype(np.uint32)
 
 
-def score_batch(d, adj, masks_t, n_w, mode, target):
+def score_batch(d, adj, masks_t, n_w, mode, target, known=None):
     progs, bad = pw.build_programs(d, adj)
     n = adj.shape[0]
     torch = _torch()
     codes = torch.empty((n * n_w, 2), dtype=torch.int64, device=adj.device)
     _, err = pw.scheme_programs(d, progs, masks_t, codes=codes)
-    score = pw.tri_objective(d, codes, n, n_w, mode, target)
+    score = pw.tri_objective(d, codes, n, n_w, mode, target, known=known)
     return score, codes, bad, err
+
+
+def known_tensor(codes, device="cuda"):
+    """Sorted low words of scheme codes (d <= 9), for objective mode 2."""
+    torch = _torch()
+    lo = np.array(sorted({int(c) & ((1 << 64) - 1) for c in codes}), dtype=np.uint64)
+    return torch.from_numpy(lo.view(np.int64)).to(device)
 
 
 def anneal(d: int, n_chains: int, iters: int, n_masks: int = 1024, mode: int = 0, target=(0, 0),
            t_start: float = 4.0, t_end: float = 0.25, seed: int = 1, symmetric: bool = False, start=None,
-           scramble: int = 64, log_every: int = 0) -> AnnealResult:
+           scramble: int = 64, log_every: int = 0, known=None) -> AnnealResult:
     """Simulated annealing over triangulations of degree d (<= 9), n_chains
     chains in parallel, maximising `mode` (0: distinct types on the sample,
-    1: sample masks whose scheme has (p, n) = target).  The temperature
-    falls geometrically from t_start to t_end; each chain starts from
-    `start` (default standard) after `scramble` random moves."""
+    1: sample masks whose scheme has (p, n) = target, 2: distinct types on
+    the sample not among the codes `known`).  The temperature falls
+    geometrically from t_start to t_end; the chains start from `start` (a
+    triangulation or a list of them, shared round-robin; default standard)
+    after `scramble` random moves."""
     torch = _torch()
     dev = "cuda"
     masks = I.random_masks(d, 0xA77 + seed, n_masks)
     mt = witness_tensor(masks, dev)
-    cur = replicate(d, start if start is not None else I.standard_triangulation(d), n_chains, dev)
+    kt = known_tensor(known, dev) if (mode == 2 and known) else None
+    starts = start if isinstance(start, list) else [start if start is not None else I.standard_triangulation(d)]
+    reps = [replicate(d, E, (n_chains - k + len(starts) - 1) // len(starts), dev) for k, E in enumerate(starts)]
+    cur = torch.cat(reps, 0)[:n_chains].contiguous()
     t0 = time.perf_counter()
     if scramble:
         pw.flip_walk(d, cur, scramble, symmetric, seed ^ 0x5C, step0=0)
     prop = cur.clone()
     best = cur.clone()
-    score_cur, _, bad, err = score_batch(d, cur, mt, n_masks, mode, target)
+    score_cur, _, bad, err = score_batch(d, cur, mt, n_masks, mode, target, kt)
     score_best = score_cur.clone()
     n_acc = torch.zeros(n_chains, dtype=torch.int32, device=dev)
     tables = np.stack([accept_table(t_start * (t_end / t_start) ** (k / max(1, iters - 1))) for k in range(iters)])
@@ -152,7 +164,7 @@ def anneal(d: int, n_chains: int, iters: int, n_masks: int = 1024, mode: int = 0
     trace = []
     for it in range(iters):
         pw.flip_walk(d, prop, 1, symmetric, seed, step0=1 << 20 | it)
-        score_prop, _, bad_p, err_p = score_batch(d, prop, mt, n_masks, mode, target)
+        score_prop, _, bad_p, err_p = score_batch(d, prop, mt, n_masks, mode, target, kt)
         pw.anneal_accept(cur, prop, score_cur, score_prop, best, score_best, tables_t[it], seed, it, n_acc)
         if log_every and (it % log_every == 0 or it == iters - 1):
             s = score_cur.cpu().numpy()
@@ -185,16 +197,39 @@ def _canon_key(d, E):
     return c.tobytes()
 
 
+def explore(d: int, found: dict, starts, n_chains: int, iters: int, n_masks: int, seed: int, keep: int = 8):
+    """Annealing for novelty: chains from `starts` scored by the number of
+    types not yet found that they realise on a random sample; the regular
+    triangulations of the best chains with a positive score (distinct up to
+    S3, at most `keep`)."""
+    ann = anneal(d, n_chains, iters, n_masks=n_masks, mode=2, seed=seed, start=list(starts), known=list(found),
+                 scramble=16)
+    rows = ann.best.cpu().numpy()
+    out = {}
+    for t in np.argsort(-ann.best_score):
+        if ann.best_score[t] <= 0 or len(out) >= keep:
+            break
+        E = edges_of(d, rows[t])
+        k = _canon_key(d, E)
+        if k not in out and regular.is_regular(d, E):
+            out[k] = E
+    return out, ann
+
+
 def iterate(d: int, pool, n_tris: int = 4096, walk_steps: int = 64, max_rounds: int = 8, seed: int = 0,
-            symmetric: bool = True, capacity: int = 1 << 14, max_selected: int = 32, log=None) -> IterateResult:
+            symmetric: bool = True, capacity: int = 1 << 14, max_selected: int = 32, log=None,
+            explore_chains: int = 256, explore_iters: int = 200, explore_masks: int = 2048,
+            target_count=None) -> IterateResult:
     """The witness <-> triangulation loop of Sec. 3 from an initial pool of
     triangulations.  Each round: (1) every (Z/2)^3 class of each selected
     triangulation is swept (its orbit-canonical member), one witness kept
     per new type; (2) n_tris triangulations generated by random
     (symmetric) walks from the selected and pool triangulations are judged
     against all witnesses; (3) those realising new types, once certified
-    regular, are selected for the next round.  Stops when a round adds
-    nothing."""
+    regular, are selected for the next round.  When a round adds nothing,
+    an annealing run for novelty (``explore``) proposes the next selection;
+    the loop stops when that finds nothing either, after max_rounds, or
+    once target_count types are known."""
     found: dict = {}
     witnesses: list = []
     rounds = []
@@ -247,20 +282,55 @@ def iterate(d: int, pool, n_tris: int = 4096, walk_steps: int = 64, max_rounds: 
         rounds.append(info)
         if log:
             log(info)
-        if not nxt and new_from_sweeps == 0:
+        if target_count is not None and len(found) >= target_count:
             break
+        if not nxt and new_from_sweeps == 0:
+            if not explore_chains:
+                break
+            t1 = time.perf_counter()
+            nxt, ann = explore(d, found, starts, explore_chains, explore_iters, explore_masks, seed * 7919 + r)
+            info["explore_seconds"] = time.perf_counter() - t1
+            info["explore_best"] = float(ann.best_score.max())
+            info["explore_selected"] = len(nxt)
+            t_all += info["explore_seconds"]
+            if not nxt:
+                break
         selected = nxt
         starts = (starts + list(nxt.values()))[-64:]
     return IterateResult(d, found, rounds, t_all)
 
 
-def schemes_text(codes) -> list:
-    """Rohlin-Viro strings of codes (display only)."""
-    out = []
-    for c in sorted(codes):
-        bits = bin(c & ((1 << 127) - 1))[3:]
-        out.append((c, bits))
-    return out
+def scheme_text(code: int) -> str:
+    """Display form of a scheme code (Rohlin-Viro style, display only):
+    '<J + 1<2> + 5>'; k empty ovals side by side are written k."""
+    bits = bin(code & ((1 << 127) - 1))[3:]
+    pos = 0
+
+    def forest():
+        nonlocal pos
+        kids = []
+        while pos < len(bits) and bits[pos] == "1":
+            pos += 1
+            kids.append(forest())
+            pos += 1  # the closing '0'
+        return kids
+
+    def fmt(f):
+        empty = sum(1 for t in f if not t)
+        parts, seen = [], {}
+        for t in f:
+            if t:
+                k = fmt(t)
+                seen[k] = seen.get(k, 0) + 1
+        parts = [f"{n}<{k}>" for k, n in seen.items()]
+        if empty:
+            parts.append(str(empty))
+        return " + ".join(parts) if parts else "0"
+
+    body = fmt(forest())
+    if code >> 127:
+        body = "J" if body == "0" else "J + " + body
+    return f"<{body}>"
 
 
 def certify(d: int, res: IterateResult, check) -> int:

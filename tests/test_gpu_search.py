@@ -214,3 +214,98 @@ def test_anneal_improves_and_keeps_valid_triangulations(pw):
     start = OS.objective([int(lo) | (int(hi) << 64) for lo, hi in
                           oracle.scheme_many(d, I.standard_triangulation(d), res.masks, threads=THREADS)], 0)
     assert res.best_score.max() > start
+
+
+def test_objective_novelty_mode(pw):
+    """mode 2 counts the distinct codes outside a known list."""
+    from paper_2604_09221_amd import search as S
+
+    d, n_tris, n_w = 7, 12, 500
+    adj = S.replicate(d, I.standard_triangulation(d), n_tris)
+    pw.flip_walk(d, adj, 40, False, 11)
+    progs, _ = pw.build_programs(d, adj)
+    wm = I.random_masks(d, 12, n_w)
+    codes = torch.zeros((n_tris * n_w, 2), dtype=torch.int64, device="cuda")
+    pw.scheme_programs(d, progs, torch.from_numpy(I.masks128(wm)).cuda(), codes=codes)
+    c = codes.cpu().numpy().view(np.uint64).reshape(n_tris, n_w, 2)
+    ints = [[int(lo) | (int(hi) << 64) for lo, hi in c[t]] for t in range(n_tris)]
+    known = sorted(set(ints[0]))[::2]
+    score = pw.tri_objective(d, codes, n_tris, n_w, 2, known=S.known_tensor(known))
+    torch.cuda.synchronize()
+    s = score.cpu().numpy()
+    for t in range(n_tris):
+        assert s[t] == len(set(ints[t]) - set(known)), t
+
+
+@pytest.mark.parametrize("d,want", [
+    (4, {6, 26, 106, 426, 28}),                                  # <1> <2> <3> <4> <1<1>>
+    (5, None),                                                   # <J + k>, k <= 6, and <J + 1<1>>
+])
+def test_iterate_realises_the_small_degree_classification(pw, d, want):
+    """The witness <-> triangulation loop from the standard triangulation
+    finds every non-empty real scheme of degree 4 and 5 (Sec. 3: for d <= 5
+    all of them are T-curves) and nothing else, each with a regular
+    triangulation and a witness the oracle confirms."""
+    from paper_2604_09221_amd import search as S
+
+    if want is None:
+        J = oracle.J_BIT
+        want = {oracle.code_from_forest([[]] * k, True) for k in range(0, 7)} | {28 | J}
+    res = S.iterate(d, [I.standard_triangulation(d)], n_tris=512, walk_steps=16, max_rounds=4, seed=2,
+                    explore_chains=64, explore_iters=30, explore_masks=256)
+    assert set(res.found) == want
+    for code, r in res.found.items():
+        assert oracle.scheme(d, r.edges, r.mask) == code
+
+
+def degree6_schemes():
+    """The non-empty real schemes of degree 6, from the constraints that
+    decide them: Bezout (depth <= 3; a nest of depth 3 has no other oval;
+    no two non-empty nests), Harnack (at most 11 ovals), Gudkov-Rokhlin for
+    M-curves (p - n = 1 mod 8) and Gudkov-Krakhnov-Kharlamov for
+    (M-1)-curves (p - n = 0 or 2 mod 8); every scheme these allow is
+    realised (Gudkov's classification; the paper counts 55)."""
+    out = {oracle.code_from_forest([[[[]]]], False)}                     # <1<1<1>>>
+    for a in range(1, 11):                                                # <a>
+        p, n = a, 0
+        if a == 10 and (p - n) % 8 not in (0, 2):
+            continue
+        out.add(oracle.code_from_forest([[]] * a, False))
+    for b in range(1, 11):                                                # <1<b> + a>
+        for a in range(0, 11 - b):
+            p, n = a + 1, b
+            total = a + 1 + b
+            if total == 11 and (p - n) % 8 != 1:
+                continue
+            if total == 10 and (p - n) % 8 not in (0, 2):
+                continue
+            out.add(oracle.code_from_forest([[[]] * b] + [[]] * a, False))
+    return out
+
+
+def test_search_realises_all_55_degree6_schemes(pw):
+    """Annealing over triangulations, then the witness <-> triangulation loop
+    (Sec. 3): every non-empty real scheme of degree six, each with a regular
+    triangulation (exact certificate) and a witness the oracle confirms."""
+    from paper_2604_09221_amd import regular
+    from paper_2604_09221_amd import search as S
+
+    want = degree6_schemes()
+    assert len(want) == 55
+    d = 6
+    ann = S.anneal(d, n_chains=256, iters=300, n_masks=1024, mode=0, seed=1)
+    rows = ann.best.cpu().numpy()
+    pool, keys = [I.standard_triangulation(d)], set()
+    for t in np.argsort(-ann.best_score):
+        E = pw.edges_from_adjacency(d, rows[t].view(np.uint64))
+        k = pw.canonical(d, E)[0].tobytes()
+        if k not in keys and regular.is_regular(d, E):
+            keys.add(k)
+            pool.append(E)
+        if len(pool) > 8:
+            break
+    res = S.iterate(d, pool, n_tris=4096, walk_steps=64, max_rounds=10, seed=1, target_count=55)
+    assert set(res.found) == want
+    for code, r in res.found.items():
+        assert regular.certificate(d, r.edges) is not None
+        assert oracle.scheme(d, r.edges, r.mask) == code
