@@ -390,7 +390,13 @@ def bench_learned(args):
 
     d = 8
     torch.cuda.set_device(0)
-    tri = pw.Triangulation(d, I.lift_triangulation(d, 8, noise=0.05))
+    if args.learned_tri == "standard":
+        E = I.lift_triangulation(d, 8, noise=0.05)
+        known = None
+    else:
+        E = np.loadtxt(os.path.join(ROOT, "tests", "golden", f"fig2_{args.learned_tri}.edges"), dtype=np.int32)
+        known = FIG2[args.learned_tri]          # distinct schemes over all 2^42 classes (Fig. 2)
+    tri = pw.Triangulation(d, E)
     tri.specialize()
     budget = 1 << args.budget_log2
     log = (lambda m: print(m, file=sys.stderr, flush=True))
@@ -398,12 +404,23 @@ def bench_learned(args):
     per_round = max(1 << 20, budget >> 8)
     target = res[0]["distinct"]
     t_uniform = res[0]["gpu_seconds"]
+    targets = [int(np.ceil(f * known)) for f in (0.9, 0.99, 1.0)] if known else list(args.targets or [])
     res.append(Lr.run_search(tri, d, budget, use_net=True, train_n=min(1 << 24, budget // 4), per_round=per_round,
-                             log=log, target=target, time_budget=t_uniform))
+                             log=log, target=target, time_budget=t_uniform, targets=targets))
+    res.append(Lr.run_search(tri, d, budget, use_net=True, train_n=min(1 << args.online_train_log2, budget // 16),
+                             per_round=per_round, log=log, target=target, time_budget=t_uniform, targets=targets,
+                             online=True))
     res.append(Lr.run_search(tri, d, budget, use_net=False, train_n=min(1 << 24, budget // 4), per_round=per_round,
-                             log=log, target=target, time_budget=t_uniform))
+                             log=log, target=target, time_budget=t_uniform, targets=targets))
     # the same uniform stream again, untimed, for its curve
-    res[0]["curve"] = Lr.run_uniform(tri, d, budget, curve=True)["curve"]
+    uc = Lr.run_uniform(tri, d, budget, curve=True)
+    res[0]["curve"] = uc["curve"]
+    if targets:
+        rate = budget / t_uniform
+        res[0]["seconds_to"] = {tk: next((ev / rate for ev, n in uc["full_curve"] if n >= tk), None) for tk in targets}
+        for r in res:
+            if known:
+                r["recall"] = r["distinct"] / known
     for r in res:
         r["distinct_per_gpu_second"] = r["distinct"] / r["gpu_seconds"]
     # GPU-seconds each search needs to find as many schemes as uniform
@@ -424,7 +441,8 @@ def bench_learned(args):
         "value": res[1]["distinct_per_gpu_second_equal_time"], "unit": "schemes/s", "n_gpus": 1, "steps": 1,
         "warmup": 0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16+u64",
         "data": "synthetic",
-        "config": {"workload": f"d=8 standard triangulation, {budget} judged masks per method",
+        "config": {"workload": f"d=8 {args.learned_tri} triangulation, {budget} judged masks per method"
+                               + (f"; {known} schemes known over all 2^42 classes (Fig. 2)" if known else ""),
                    "value": "learned proposal: distinct schemes seen within the GPU time uniform sampling takes for "
                             "the whole budget, per GPU-second (equal-time); uniform's equal-time rate: "
                             f"{res[0]['distinct_per_gpu_second_equal_time']:.1f}; each method's rate over its own "
@@ -843,6 +861,11 @@ def main():
     ap.add_argument("--varied", action="store_true")
     ap.add_argument("--tune", action="store_true")
     ap.add_argument("--budget-log2", type=int, default=26)
+    ap.add_argument("--learned-tri", choices=("standard", "bow_tie", "rank016", "rank015"), default="standard",
+                    help="--config learned: the d=8 triangulation")
+    ap.add_argument("--targets", type=int, nargs="*", help="--config learned: scheme counts to time")
+    ap.add_argument("--online-train-log2", type=int, default=22,
+                    help="--config learned: uniform training masks of the online-learning search")
     ap.add_argument("--generic", action="store_true", help="time the generic (unspecialised) kernel")
     ap.add_argument("--chunk-log2", type=int, default=32, help="masks per step (profiling runs use less)")
     ap.add_argument("--no-full-check", action="store_true",

@@ -340,6 +340,12 @@ def rarity_from_labels(lab):
 
     cnt = torch.zeros(OUT, dtype=torch.int32, device=lab.device)
     pw.check(_bind().pw_label_counts(_p(lab), lab.shape[0], _p(cnt), _s()))
+    return rarity_from_counts(cnt)
+
+
+def rarity_from_counts(cnt):
+    """-log of the class frequencies of the six heads from 64 class counts
+    (a device tensor of pw_label_counts)."""
     c = cnt.cpu().numpy().view(np.uint32).astype(np.float64) + 0.5
     r = np.zeros(OUT, dtype=np.float32)
     st = np.concatenate([[0], np.cumsum(HEADS)])
@@ -384,12 +390,14 @@ def run_uniform(tri, d, budget, chunk=1 << 22, seed=1, curve=False):
     dt = time.perf_counter() - t0
     out = {"method": "uniform", "evaluations": done, "distinct": len(hist.read()), "gpu_seconds": dt}
     if curve:
+        out["full_curve"] = points
         out["curve"] = points[:: max(1, len(points) // 32)] + ([points[-1]] if len(points) > 32 else [])
     return out
 
 
 def run_search(tri, d, budget, use_net=True, train_n=1 << 24, epochs=1, batch=1 << 16, lr=3e-3, per_round=1 << 22,
-               n_elite=4096, temp=0.25, explore=0.1, seed=7, log=None, target=None, time_budget=None):
+               n_elite=4096, temp=0.25, explore=0.1, seed=7, log=None, target=None, time_budget=None,
+               online=False, online_batch=1 << 16, targets=()):
     """Mutation search from the witnesses of the rarest schemes seen.
 
     With use_net, the network (trained first on train_n uniform masks
@@ -403,7 +411,12 @@ def run_search(tri, d, budget, use_net=True, train_n=1 << 24, epochs=1, batch=1 
     the result also holds the seconds (training included) until at least
     that many distinct schemes had been seen; with `time_budget`, the
     number of distinct schemes seen within that many seconds (read at the
-    start of each round)."""
+    start of each round).  With `online`, the network keeps learning
+    during the search: every round it takes one training step on
+    `online_batch` of the round's judged mutants (labels from their exact
+    codes, which the same pass returns), and the rarity of each feature
+    class is re-estimated from every mask judged so far, so the score
+    points at classes the search has rarely reached."""
     import torch
 
     nA = (d + 1) * (d + 2) // 2
@@ -414,9 +427,13 @@ def run_search(tri, d, budget, use_net=True, train_n=1 << 24, epochs=1, batch=1 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
 
-    def judge(masks, at):
+    def judge(masks, at, want_codes=False):
         archive[at:at + masks.shape[0]] = masks
-        tri.histogram(masks if wide else masks[:, 0].contiguous(), hist, index_base=at)
+        mm = masks if wide else masks[:, 0].contiguous()
+        if want_codes:
+            codes = tri.codes_histogram(mm, hist, index_base=at)
+            return at + masks.shape[0], codes
+        tri.histogram(mm, hist, index_base=at)
         return at + masks.shape[0]
 
     # labelled data from uniform masks (judged, counted)
@@ -432,7 +449,9 @@ def run_search(tri, d, budget, use_net=True, train_n=1 << 24, epochs=1, batch=1 
         for ep in range(epochs):
             for a in range(0, train_n - batch + 1, batch):
                 net.train_step(X[a:a + batch], lab[a:a + batch], lr=lr)
-        rarity = torch.from_numpy(rarity_from_labels(lab)).cuda()
+        counts = torch.zeros(OUT, dtype=torch.int32, device="cuda")
+        pw.check(_bind().pw_label_counts(_p(lab), lab.shape[0], _p(counts), _s()))
+        rarity = torch.from_numpy(rarity_from_counts(counts)).cuda()
         del codes, lab, X
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
@@ -449,7 +468,16 @@ def run_search(tri, d, budget, use_net=True, train_n=1 << 24, epochs=1, batch=1 
             cand = mutate_guided(parents, dX, k, nA, flips, seed * 1000003 + rnd, temp, explore)
         else:
             cand = mutate(parents, k, nA, flips, seed * 1000003 + rnd)
-        used = judge(cand, used)
+        if use_net and online:
+            used, codes = judge(cand, used, want_codes=True)
+            lab = features(codes)
+            pw.check(_bind().pw_label_counts(_p(lab), lab.shape[0], _p(counts), _s()))
+            nb = min(online_batch, (cand.shape[0] // 64) * 64)
+            if nb >= 64:
+                net.train_step(encode(cand[:nb], nb, nA), lab[:nb], lr=lr)
+            rarity = torch.from_numpy(rarity_from_counts(counts)).cuda()
+        else:
+            used = judge(cand, used)
         if log and rnd % 16 == 0:
             log(f"round {rnd}: {used} evaluations, {distinct} schemes")
     final = len(hist.read())
@@ -460,10 +488,15 @@ def run_search(tri, d, budget, use_net=True, train_n=1 << 24, epochs=1, batch=1 
     if target is not None:
         hit = [c for c in curve if c[1] >= target]
         reach = hit[0][2] if hit else None
+    reach_k = {}
+    for tk in targets:
+        hit = [c for c in curve if c[1] >= tk]
+        reach_k[int(tk)] = hit[0][2] if hit else None
     within = None
     if time_budget is not None:
         within = max([c[1] for c in curve if c[2] <= time_budget], default=0)
-    return {"method": "learned" if use_net else "ablation (uniform flips)", "evaluations": used,
-            "seconds_to_target": reach, "distinct_within_time_budget": within,
+    name = ("learned (online)" if online else "learned") if use_net else "ablation (uniform flips)"
+    return {"method": name, "evaluations": used,
+            "seconds_to_target": reach, "distinct_within_time_budget": within, "seconds_to": reach_k,
             "distinct": final, "gpu_seconds": dt, "train_seconds": train_s, "rounds": rnd,
             "curve": curve[:: max(1, len(curve) // 32)] + ([curve[-1]] if len(curve) > 32 else [])}
