@@ -667,14 +667,16 @@ def bench_search(args):
     from paper_2604_09221_amd import regular
     from paper_2604_09221_amd import search as S
 
-    d = 6
+    d = args.degree
+    total = {6: 55, 7: 121}[d]      # non-empty real schemes of degree 6 and 7 (Sec. 1, Sec. 3)
     torch.cuda.set_device(0)
     t_all = time.perf_counter()
     # warm-up: load the kernels once
     S.mode2_sweep(d, I.random_masks(d, 1, 64), 64, 4, 1)
-    ann = S.anneal(d, n_chains=args.chains, iters=args.iters, n_masks=1024, mode=0, seed=args.seed,
+    n_masks = 1024 if d == 6 else 4096
+    ann = S.anneal(d, n_chains=args.chains, iters=args.iters, n_masks=n_masks, mode=0, seed=args.seed,
                    symmetric=False, log_every=max(1, args.iters // 8))
-    sa_evals = args.chains * (args.iters + 1) * 1024
+    sa_evals = args.chains * (args.iters + 1) * n_masks
     order = np.argsort(-ann.best_score)
     rows = ann.best.cpu().numpy()
     pool, keys = [I.standard_triangulation(d)], set()
@@ -688,31 +690,33 @@ def bench_search(args):
         if len(pool) > args.pool:
             break
     res = S.iterate(d, pool, n_tris=args.slots, walk_steps=64, max_rounds=args.rounds, seed=args.seed,
-                    target_count=55, log=lambda info: print(json.dumps(info), file=sys.stderr, flush=True))
+                    target_count=total, max_selected=args.max_selected, explore_masks=2 * n_masks,
+                    witness_mutants=args.witness_mutants, explore_tries=args.explore_tries,
+                    log=lambda info: print(json.dumps(info), file=sys.stderr, flush=True))
     total_s = time.perf_counter() - t_all
     assert all(regular.certificate(d, r.edges) is not None for r in res.found.values())
-    assert len(res.found) <= 55
+    assert len(res.found) <= total
     m2_pairs = sum(r["mode2_pairs"] for r in res.rounds)
     m2_s = sum(r["mode2_seconds"] for r in res.rounds)
     out = {
-        "metric": "triangulation x witness pairs/sec, second search mode at d=6 (generation included)",
+        "metric": f"triangulation x witness pairs/sec, second search mode at d={d} (generation included)",
         "value": m2_pairs / m2_s, "unit": "pairs/s", "n_gpus": 1, "steps": len(res.rounds), "warmup": 1,
         "ms_per_step": res.gpu_seconds / max(1, len(res.rounds)) * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": {"workload": "d=6 search: annealing over triangulations (distinct types on 1024 random sign "
-                               "distributions), then the witness <-> triangulation loop with 4096 symmetric "
-                               "triangulations per round",
+        "config": {"workload": f"d={d} search: annealing over triangulations (distinct types on {n_masks} random "
+                               f"sign distributions), then the witness <-> triangulation loop with {args.slots} "
+                               "symmetric triangulations per round",
                    "annealing": {"chains": args.chains, "iterations": args.iters, "evaluations": sa_evals,
                                  "seconds": ann.gpu_seconds, "evaluations_per_s": sa_evals / ann.gpu_seconds,
                                  "best_score": float(ann.best_score.max()),
                                  "start_score": float(ann.trace[0][1]) if ann.trace else None,
                                  "pool_triangulations": len(pool)},
                    "rounds": res.rounds,
-                   "distinct_nonempty_schemes": len(res.found), "paper_total_degree6": 55,
+                   "distinct_nonempty_schemes": len(res.found), "paper_total": total,
                    "schemes": sorted(S.scheme_text(c) for c in res.found),
-                   "all_55_found": len(res.found) == 55,
+                   "all_found": len(res.found) == total,
                    "seconds_total": total_s,
-                   "checks": {"regularity_certificates": len(res.found), "at_most_55": True}},
+                   "checks": {"regularity_certificates": len(res.found), f"at_most_{total}": True}},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = search_cpu_baseline(d, res)
@@ -858,6 +862,10 @@ def main():
     ap.add_argument("--pool", type=int, default=8, help="--config search: annealed triangulations kept")
     ap.add_argument("--rounds", type=int, default=10, help="--config search: witness <-> triangulation rounds")
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--degree", type=int, choices=(6, 7), default=6, help="--config search: the degree")
+    ap.add_argument("--max-selected", type=int, default=32, help="--config search: class sweeps per round")
+    ap.add_argument("--witness-mutants", type=int, default=0, help="--config search: mutants per witness")
+    ap.add_argument("--explore-tries", type=int, default=1, help="--config search: novelty annealing runs")
     ap.add_argument("--varied", action="store_true")
     ap.add_argument("--tune", action="store_true")
     ap.add_argument("--budget-log2", type=int, default=26)

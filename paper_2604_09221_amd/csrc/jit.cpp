@@ -321,9 +321,8 @@ std::string jit_source(const HostProgram& P) {
     // words keeps the loads from all being hoisted at once, which would
     // need a register each)
     o << "    {\n      const uint32_t* s = reinterpret_cast<const uint32_t*>(__builtin_assume_aligned(snap, 16));\n"
-         "      uint32_t* e = reinterpret_cast<uint32_t*>(L.e);\n"
          "#pragma unroll\n      for (int k = 0; k < Cfg<"
-      << d << ">::SNAP_WORDS; ++k) {\n        e[k] = s[k];\n        if (k % 8 == 7) PW_FENCE();\n      }\n    }\n";
+      << d << ">::SNAP_WORDS; ++k) {\n        L.eword(k) = s[k];\n        if (k % 8 == 7) PW_FENCE();\n      }\n    }\n";
     o << "    const E::Ent* srow = reinterpret_cast<const E::Ent*>(snap);\n";
     o << "    // phase 1 for the varying vertices (in index order; each with all\n"
          "    // its fixed-sign neighbours and its earlier varying ones; duplicate\n"

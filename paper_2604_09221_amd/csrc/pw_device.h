@@ -165,6 +165,8 @@ struct Lane {
   char* e;      // entry 0 of this lane
   char* b;      // byte 0 of this lane in byte rows: byte row x at b[x * 64]
   __device__ __forceinline__ uint32_t& word(int k) const { return w[k * 64]; }
+  // word k of the lane's entry row (entries 4 k / EB .. 4 (k + 1) / EB - 1)
+  __device__ __forceinline__ uint32_t& eword(int k) const { return reinterpret_cast<uint32_t*>(e)[k]; }
 };
 
 constexpr uint32_t kParity = 0x200u;  // u16 entries only

@@ -135,17 +135,21 @@ def known_tensor(codes, device="cuda"):
 
 def anneal(d: int, n_chains: int, iters: int, n_masks: int = 1024, mode: int = 0, target=(0, 0),
            t_start: float = 4.0, t_end: float = 0.25, seed: int = 1, symmetric: bool = False, start=None,
-           scramble: int = 64, log_every: int = 0, known=None) -> AnnealResult:
+           scramble: int = 64, log_every: int = 0, known=None, extra_masks=None) -> AnnealResult:
     """Simulated annealing over triangulations of degree d (<= 9), n_chains
     chains in parallel, maximising `mode` (0: distinct types on the sample,
     1: sample masks whose scheme has (p, n) = target, 2: distinct types on
     the sample not among the codes `known`).  The temperature falls
     geometrically from t_start to t_end; the chains start from `start` (a
     triangulation or a list of them, shared round-robin; default standard)
-    after `scramble` random moves."""
+    after `scramble` random moves.  `extra_masks` ((k, 2) uint64, e.g.
+    mutants of known witnesses) join the random sample."""
     torch = _torch()
     dev = "cuda"
     masks = I.random_masks(d, 0xA77 + seed, n_masks)
+    if extra_masks is not None and len(extra_masks):
+        masks = np.concatenate([masks, np.asarray(extra_masks, dtype=np.uint64).reshape(-1, 2)])[:8192]
+        n_masks = len(masks)
     mt = witness_tensor(masks, dev)
     kt = known_tensor(known, dev) if (mode == 2 and known) else None
     starts = start if isinstance(start, list) else [start if start is not None else I.standard_triangulation(d)]
@@ -197,13 +201,31 @@ def _canon_key(d, E):
     return c.tobytes()
 
 
-def explore(d: int, found: dict, starts, n_chains: int, iters: int, n_masks: int, seed: int, keep: int = 8):
+def mutants(d: int, witnesses, per: int, seed: int):
+    """`per` mutants of every witness (1 to 3 random flips each, bit 0
+    kept; the device mutation kernel), as (k, 2) uint64 host masks."""
+    from . import learn
+
+    torch = _torch()
+    if not len(witnesses) or per <= 0:
+        return np.zeros((0, 2), dtype=np.uint64)
+    par = witness_tensor(witnesses).view(-1, 2)
+    out = [learn.mutate(par, per * len(witnesses), I.n_points(d), f, seed * 7 + f).cpu().numpy()
+           for f in (1, 2, 3)]
+    return np.concatenate(out).view(np.uint64)
+
+
+def explore(d: int, found: dict, starts, n_chains: int, iters: int, n_masks: int, seed: int, keep: int = 8,
+            witnesses=None):
     """Annealing for novelty: chains from `starts` scored by the number of
-    types not yet found that they realise on a random sample; the regular
-    triangulations of the best chains with a positive score (distinct up to
-    S3, at most `keep`)."""
+    types not yet found that they realise on a sample of random masks and
+    mutants of the known witnesses; the regular triangulations of the best
+    chains with a positive score (distinct up to S3, at most `keep`)."""
+    extra = None
+    if witnesses is not None and len(witnesses):
+        extra = mutants(d, witnesses, max(1, n_masks // (3 * len(witnesses))), seed)
     ann = anneal(d, n_chains, iters, n_masks=n_masks, mode=2, seed=seed, start=list(starts), known=list(found),
-                 scramble=16)
+                 scramble=16, extra_masks=extra)
     rows = ann.best.cpu().numpy()
     out = {}
     for t in np.argsort(-ann.best_score):
@@ -219,7 +241,7 @@ def explore(d: int, found: dict, starts, n_chains: int, iters: int, n_masks: int
 def iterate(d: int, pool, n_tris: int = 4096, walk_steps: int = 64, max_rounds: int = 8, seed: int = 0,
             symmetric: bool = True, capacity: int = 1 << 14, max_selected: int = 32, log=None,
             explore_chains: int = 256, explore_iters: int = 200, explore_masks: int = 2048,
-            target_count=None) -> IterateResult:
+            target_count=None, witness_mutants: int = 0, explore_tries: int = 1) -> IterateResult:
     """The witness <-> triangulation loop of Sec. 3 from an initial pool of
     triangulations.  Each round: (1) every (Z/2)^3 class of each selected
     triangulation is swept (its orbit-canonical member), one witness kept
@@ -227,9 +249,11 @@ def iterate(d: int, pool, n_tris: int = 4096, walk_steps: int = 64, max_rounds: 
     (symmetric) walks from the selected and pool triangulations are judged
     against all witnesses; (3) those realising new types, once certified
     regular, are selected for the next round.  When a round adds nothing,
-    an annealing run for novelty (``explore``) proposes the next selection;
-    the loop stops when that finds nothing either, after max_rounds, or
-    once target_count types are known."""
+    an annealing run for novelty (``explore``) proposes the next selection
+    (up to explore_tries runs); the loop stops when that finds nothing
+    either, after max_rounds, or once target_count types are known.  With
+    witness_mutants > 0 the second mode also judges that many mutants of
+    every witness (1-3 flips each) against the generated triangulations."""
     found: dict = {}
     witnesses: list = []
     rounds = []
@@ -255,13 +279,15 @@ def iterate(d: int, pool, n_tris: int = 4096, walk_steps: int = 64, max_rounds: 
         info["new_from_class_sweeps"] = new_from_sweeps
         wm = np.zeros((len(witnesses), 2), dtype=np.uint64)
         wm[:, 0] = [m & ((1 << 64) - 1) for m in witnesses]
+        if witness_mutants:
+            wm = np.concatenate([wm, mutants(d, wm, witness_mutants, seed * 31 + r)])
         # generated triangulations: walks from the triangulations met so far
         per = max(1, n_tris // max(1, len(starts)))
         torch = _torch()
         adj = torch.cat([replicate(d, E, per) for E in starts], 0)
         pw.flip_walk(d, adj, walk_steps, symmetric, seed * 1000 + r)
         m2 = mode2_sweep(d, wm, adj.shape[0], 0, 0, adj=adj, capacity=capacity)
-        info["mode2_pairs"] = adj.shape[0] * len(witnesses)
+        info["mode2_pairs"] = adj.shape[0] * len(wm)
         info["mode2_seconds"] = m2.gpu_seconds
         nxt = {}
         new_regular = 0
@@ -272,7 +298,7 @@ def iterate(d: int, pool, n_tris: int = 4096, walk_steps: int = 64, max_rounds: 
             E = edges_of(d, adj[t])
             if not regular.is_regular(d, E):
                 continue
-            found[code] = Realised(E, witnesses[w], True)
+            found[code] = Realised(E, int(wm[w, 0]) | (int(wm[w, 1]) << 64), True)
             nxt.setdefault(_canon_key(d, E), E)
             new_regular += 1
         info["new_from_mode2"] = new_regular
@@ -288,7 +314,11 @@ def iterate(d: int, pool, n_tris: int = 4096, walk_steps: int = 64, max_rounds: 
             if not explore_chains:
                 break
             t1 = time.perf_counter()
-            nxt, ann = explore(d, found, starts, explore_chains, explore_iters, explore_masks, seed * 7919 + r)
+            for k in range(explore_tries):
+                nxt, ann = explore(d, found, starts, explore_chains, explore_iters, explore_masks,
+                                   seed * 7919 + r * 13 + k, witnesses=wm[:len(witnesses)])
+                if nxt:
+                    break
             info["explore_seconds"] = time.perf_counter() - t1
             info["explore_best"] = float(ann.best_score.max())
             info["explore_selected"] = len(nxt)
