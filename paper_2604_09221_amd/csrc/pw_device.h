@@ -10,16 +10,17 @@
 // parent table of phases 3-4 is one byte row per region.
 //
 // Per mask (thread) the phases are:
-//   1 components  (Alg. 1 "compute connected components of same-sign
-//     vertices"): vertices in program order; each earlier neighbour with
-//     the same sign is unioned.  Entry of v: the index of its union-find
-//     parent (u8 for odd d <= 7; u16 otherwise, with the parity to the
-//     parent and, at a root, the odd-cycle flag for even d).  Signs are
-//     bits of the mask and are not stored.
+//   1 components (Alg. 1, its first union-find over the reflected
+//     diamond: same-sign vertices joined by uncrossed edges): vertices in
+//     program order; each earlier neighbour with the same sign is unioned.
+//     Entry of v: the index of its union-find parent (u8 where 7 bits
+//     index every vertex: odd d <= 7, even d <= 6; u16 otherwise), for
+//     even d with the parity to the parent and, at a root, the odd-cycle
+//     flag.  Signs are bits of the mask and are not stored.
 //     Links always go from the larger root to the smaller one, so every
 //     parent index is smaller than its child's.
-//   2 regions (Alg. 1 "coarsen into regions by identifying antipodal
-//     boundary pairs"): union along the 2d pairs.  For even d the union
+//   2 regions (Alg. 1, the components merged across the identified
+//     antipodal boundary points): union along the 2d pairs.  For even d the union
 //     carries parity 1 (each identification reverses orientation, proof of
 //     Thm. 2) and a same-parity closure marks an odd cycle.
 //   3 region ids and the region tree: vertices in order again; a root gets
@@ -27,8 +28,8 @@
 //     (already relabelled because parents are smaller).  The region tree is
 //     read off a fixed spanning tree of T<> (each vertex's first earlier
 //     neighbour): the first vertex of a region hangs below the region of its
-//     tree parent (Alg. 1 "build region adjacency graph from crossed
-//     edges", restricted to spanning-tree edges, which cross every curve
+//     tree parent (Alg. 1's region adjacency graph from the crossed edges,
+//     restricted to spanning-tree edges, which cross every curve
 //     component).  For odd d a crossed tree edge inside one region marks
 //     the root (the pseudo-line's region).
 //   4 re-root the tree at the root region (Alg. 1 root rule), breadth-first
@@ -99,10 +100,13 @@ struct Cfg {
   // codes of at most RMAX - 1 nodes below the root: 2 (RMAX - 1) bits
   using Code = typename cond<(2 * (RMAX - 1) + 2 <= 64), uint64_t, u128>::type;
   static constexpr int ADJ_W = sizeof(Adj) / 4;
-  // vertex entries: u8 (parent index) where odd d needs no parity flags
-  // and 7 bits index every vertex (d <= 7); u16 otherwise (parent index in
-  // bits 0-8, parity to the parent bit 9, odd-cycle flag bit 10)
-  static constexpr bool NARROW = !EVEN && NV <= 128;
+  // vertex entries: u8 where 7 bits index every vertex and the spare
+  // entry (odd d <= 7, even d <= 6): the parent index in bits 0-6 and, for
+  // even d, bit 7 = the parity to the parent at a non-root and the
+  // odd-cycle flag at a root (a root has no parent, so the bit is free);
+  // u16 otherwise (parent index in bits 0-8, parity to the parent bit 9,
+  // odd-cycle flag bit 10)
+  static constexpr bool NARROW = NV + 1 <= 128;
   using Ent = typename cond<NARROW, uint8_t, uint16_t>::type;
   static constexpr int EB = NARROW ? 1 : 2;
   // a stored region code has 2 * (subtree size) <= 2 * (RMAX - 1) bits
@@ -169,8 +173,6 @@ struct Lane {
   __device__ __forceinline__ uint32_t& eword(int k) const { return reinterpret_cast<uint32_t*>(e)[k]; }
 };
 
-constexpr uint32_t kParity = 0x200u;  // u16 entries only
-constexpr uint32_t kOdd = 0x400u;     // u16 entries only
 
 template <typename T>
 __device__ __forceinline__ int clz_t(T x);
@@ -208,10 +210,14 @@ struct Eval {
   using Code = typename C::Code;
   using Ent = typename C::Ent;
   static constexpr uint32_t kIdx = C::NARROW ? 0x7Fu : 0x1FFu;  // index field of an entry
+  // even d: parity to the parent (non-root) and odd-cycle flag (root); one
+  // bit in u8 entries, whose meaning the root test decides
+  static constexpr uint32_t kParity = C::NARROW ? 0x80u : 0x200u;
+  static constexpr uint32_t kOdd = C::NARROW ? 0x80u : 0x400u;
   __device__ static __forceinline__ Adj one(int x) { return (Adj)1 << x; }
 
-  // parent index in an entry (u8 entries hold nothing else)
-  __device__ static __forceinline__ uint32_t idx(uint32_t e) { return C::NARROW ? e : (e & kIdx); }
+  // parent index in an entry (u8 entries of odd d hold nothing else)
+  __device__ static __forceinline__ uint32_t idx(uint32_t e) { return (C::NARROW && !C::EVEN) ? e : (e & kIdx); }
 
   __device__ static __forceinline__ uint32_t bit(Mask m, int p) { return (uint32_t)(m >> p) & 1u; }
 
