@@ -272,10 +272,16 @@ pw_status patchwork_scheme_sweep_graph(pw_tri_t tri, uint64_t first, uint64_t co
  *             of a code is its smallest global mask index.
  *   d_codes   NULL, or n x 2 uint64 codes written at the masks' positions
  *             (16-byte aligned).
- *   cfg       NULL for the defaults, or the tuned launch shape: masks per
- *             work item, waves per block (lowered until a block's LDS for
- *             the largest degree of its class fits in 160 KiB), blocks per
- *             CU (0 = as many as LDS and registers allow).
+ *   cfg       NULL for the defaults (4096 masks per item, one wave per
+ *             block, blocks per CU as LDS and registers allow), or the tuned
+ *             launch shape: masks per work item, waves per block (lowered
+ *             until a block's LDS for the largest degree of its class fits
+ *             in 160 KiB), blocks per CU (0 = as many as LDS and registers
+ *             allow).  The library reads no tuning cache itself: the tuned
+ *             shapes are kept per degree mix by the Python layer (tune.py,
+ *             in tune_cache_gfx950.json beside it, or the file named by the
+ *             PW_TUNE environment variable); a C caller passes the shape it
+ *             wants here.
  * Degrees are grouped into LDS classes (those whose per-wave areas allow
  * the same number of resident blocks per CU); each class is one persistent
  * launch, sized for its largest degree, and the launches run back to back
