@@ -709,6 +709,7 @@ def bench_search(args):
     res = S.iterate(d, pool, n_tris=args.slots, walk_steps=64, max_rounds=args.rounds, seed=args.seed,
                     target_count=total, max_selected=args.max_selected, explore_masks=2 * n_masks,
                     witness_mutants=args.witness_mutants, explore_tries=args.explore_tries,
+                    target_chains=args.target_chains,
                     log=lambda info: print(json.dumps(info), file=sys.stderr, flush=True))
     total_s = time.perf_counter() - t_all
     assert all(regular.certificate(d, r.edges) is not None for r in res.found.values())
@@ -884,6 +885,8 @@ def main():
     ap.add_argument("--max-selected", type=int, default=32, help="--config search: class sweeps per round")
     ap.add_argument("--witness-mutants", type=int, default=0, help="--config search: mutants per witness")
     ap.add_argument("--explore-tries", type=int, default=1, help="--config search: novelty annealing runs")
+    ap.add_argument("--target-chains", type=int, default=0,
+                    help="--config search: chains of the (p, n)-target annealing runs (0 = none)")
     ap.add_argument("--varied", action="store_true")
     ap.add_argument("--tune", action="store_true")
     ap.add_argument("--budget-log2", type=int, default=26)

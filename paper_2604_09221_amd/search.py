@@ -238,10 +238,65 @@ def explore(d: int, found: dict, starts, n_chains: int, iters: int, n_masks: int
     return out, ann
 
 
+def code_pn(code: int):
+    """(p, n) of a scheme code: ovals at odd depth (outermost = 1) and at
+    even depth, read off the code's bit string ('1' opens a node)."""
+    bits = bin(code & ((1 << 127) - 1))[3:]
+    depth = p = n = 0
+    for ch in bits:
+        if ch == "1":
+            depth += 1
+            if depth % 2:
+                p += 1
+            else:
+                n += 1
+        else:
+            depth -= 1
+    return p, n
+
+
+def explore_targets(d: int, found: dict, starts, n_chains: int, iters: int, seed: int, witnesses, keep: int = 8,
+                    span: int = 2, max_targets: int = 24):
+    """Annealing toward (p, n) pairs no found type has, at the highest oval
+    counts reached (the top `span` + 1 totals): for each pair, chains from
+    `starts` scored by how many masks of a sample reach it; the sample is
+    mutants of the witnesses of the types with the most ovals and of the
+    Harnack distribution, where such types live.  Returns the regular
+    triangulations of the best chains with a positive score (distinct up to
+    S3, at most `keep` per target) and the targets tried."""
+    have = {code_pn(c) for c in found}
+    tot = {c: sum(code_pn(c)) for c in found}
+    top = max(tot.values()) if tot else 0
+    targets = [(p, t - p) for t in range(top + 1, top - span - 1, -1) for p in range(t + 1)
+               if (p, t - p) not in have][:max_targets]
+    rich = [r.mask for c, r in sorted(found.items(), key=lambda kv: -tot[kv[0]])[:32]]
+    base = np.zeros((len(rich) + 1, 2), dtype=np.uint64)
+    for k, m in enumerate(rich + [I.harnack_mask(d)]):
+        base[k, 0] = m & ((1 << 64) - 1)
+        base[k, 1] = m >> 64
+    sample = mutants(d, base, max(1, 2048 // (3 * len(base))), seed)
+    out = {}
+    for k, tg in enumerate(targets):
+        ann = anneal(d, n_chains, iters, n_masks=256, mode=1, target=tg, seed=seed * 101 + k, start=list(starts),
+                     scramble=16, extra_masks=sample)
+        rows = ann.best.cpu().numpy()
+        got = 0
+        for t in np.argsort(-ann.best_score):
+            if ann.best_score[t] <= 0 or got >= keep:
+                break
+            E = edges_of(d, rows[t])
+            key = _canon_key(d, E)
+            if key not in out and regular.is_regular(d, E):
+                out[key] = E
+                got += 1
+    return out, targets
+
+
 def iterate(d: int, pool, n_tris: int = 4096, walk_steps: int = 64, max_rounds: int = 8, seed: int = 0,
             symmetric: bool = True, capacity: int = 1 << 14, max_selected: int = 32, log=None,
             explore_chains: int = 256, explore_iters: int = 200, explore_masks: int = 2048,
-            target_count=None, witness_mutants: int = 0, explore_tries: int = 1) -> IterateResult:
+            target_count=None, witness_mutants: int = 0, explore_tries: int = 1,
+            target_chains: int = 0, target_iters: int = 150) -> IterateResult:
     """The witness <-> triangulation loop of Sec. 3 from an initial pool of
     triangulations.  Each round: (1) every (Z/2)^3 class of each selected
     triangulation is swept (its orbit-canonical member), one witness kept
@@ -253,7 +308,10 @@ def iterate(d: int, pool, n_tris: int = 4096, walk_steps: int = 64, max_rounds: 
     (up to explore_tries runs); the loop stops when that finds nothing
     either, after max_rounds, or once target_count types are known.  With
     witness_mutants > 0 the second mode also judges that many mutants of
-    every witness (1-3 flips each) against the generated triangulations."""
+    every witness (1-3 flips each) against the generated triangulations.
+    With target_chains > 0, a round without news whose novelty runs find
+    nothing anneals toward the (p, n) pairs missing at the highest oval
+    counts (``explore_targets``) before giving up."""
     found: dict = {}
     witnesses: list = []
     rounds = []
@@ -319,8 +377,12 @@ def iterate(d: int, pool, n_tris: int = 4096, walk_steps: int = 64, max_rounds: 
                                    seed * 7919 + r * 13 + k, witnesses=wm[:len(witnesses)])
                 if nxt:
                     break
-            info["explore_seconds"] = time.perf_counter() - t1
             info["explore_best"] = float(ann.best_score.max())
+            if not nxt and target_chains:
+                nxt, tried = explore_targets(d, found, starts, target_chains, target_iters, seed * 7 + r,
+                                             wm[:len(witnesses)])
+                info["targets_tried"] = len(tried)
+            info["explore_seconds"] = time.perf_counter() - t1
             info["explore_selected"] = len(nxt)
             t_all += info["explore_seconds"]
             if not nxt:
