@@ -484,8 +484,8 @@ def gemm_roofline():
     H2 = torch.empty((rows, Lr.HIDDEN), dtype=torch.int16, device="cuda")
     stream = torch.cuda.current_stream()
 
-    def layer2():
-        Lr.gemm(H1, Lr.HIDDEN, 1, net.W16["W2"], Lr.HIDDEN, 1, rows, Lr.HIDDEN, Lr.HIDDEN, C16=H2,
+    def layer2():  # as in the forward pass: the weight's [out][in] copy, contiguous along K
+        Lr.gemm(H1, Lr.HIDDEN, 1, net.W16T["W2"], 1, Lr.HIDDEN, rows, Lr.HIDDEN, Lr.HIDDEN, C16=H2,
                 bias=net.P["b2"], relu=True)
 
     for _ in range(3):
@@ -889,7 +889,8 @@ def main():
                     help="--config search: chains of the (p, n)-target annealing runs (0 = none)")
     ap.add_argument("--varied", action="store_true")
     ap.add_argument("--tune", action="store_true")
-    ap.add_argument("--budget-log2", type=int, default=26)
+    ap.add_argument("--budget-log2", type=int, default=30,
+                    help="--config learned: judged masks per method (2^30: the configured workload)")
     ap.add_argument("--learned-tri", choices=("standard", "bow_tie", "rank016", "rank015"), default="standard",
                     help="--config learned: the d=8 triangulation")
     ap.add_argument("--targets", type=int, nargs="*", help="--config learned: scheme counts to time")

@@ -519,6 +519,12 @@ pw_status pw_mlp_adam(float *w, const float *g, float *m, float *v, int64_t n, f
 /* y[i] = x[i] rounded to bf16 (nearest even). */
 pw_status pw_to_bf16(const float *x, int64_t n, uint16_t *y, hipStream_t stream);
 
+/* out[c * rows + r] = in[r * cols + c]: the transpose of a rows x cols
+ * bf16 matrix (the network keeps each weight matrix also as [out][in], so
+ * that both operands of a forward product are contiguous along K).  in and
+ * out must not overlap. */
+pw_status pw_bf16_transpose(const uint16_t *in, int64_t rows, int64_t cols, uint16_t *out, hipStream_t stream);
+
 /*
  * Novelty score of each row of Y (n x 64 logits): the sum over the six heads
  * of sum_j softmax(Y)_j * rarity[j] (rarity: 64 floats, e.g. -log of the

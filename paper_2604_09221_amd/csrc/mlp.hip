@@ -592,6 +592,20 @@ __global__ void k_to_bf16(const float* __restrict__ x, int64_t n, uint16_t* __re
   if (i < n) y[i] = f32_to_bf16(x[i]);
 }
 
+// out[c][r] = in[r][c] for a rows x cols bf16 matrix, through 32 x 32 LDS
+// tiles (reads and writes along rows of 32 consecutive elements)
+__global__ void k_transpose_bf16(const uint16_t* __restrict__ in, int64_t rows, int64_t cols,
+                                 uint16_t* __restrict__ out) {
+  __shared__ uint16_t t[32][33];
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 8 rows at a time
+  for (int k = ty; k < 32; k += 8)
+    if (r0 + k < rows && c0 + tx < cols) t[k][tx] = in[(r0 + k) * cols + c0 + tx];
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8)
+    if (c0 + k < cols && r0 + tx < rows) out[(c0 + k) * rows + r0 + tx] = t[tx][k];
+}
+
 int grid1d(int64_t n, int threads) { return (int)((n + threads - 1) / threads); }
 
 }  // namespace pw
@@ -769,6 +783,17 @@ pw_status pw_to_bf16(const float* x, int64_t n, uint16_t* y, hipStream_t s) {
   if (n < 0 || !x || !y) return set_err(PW_ERR_ARG, "bad conversion arguments");
   if (n == 0) return PW_OK;
   hipLaunchKernelGGL(k_to_bf16, dim3(grid1d(n, 256)), dim3(256), 0, s, x, n, y);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
+pw_status pw_bf16_transpose(const uint16_t* in, int64_t rows, int64_t cols, uint16_t* out, hipStream_t s) {
+  if (rows < 0 || cols < 0 || rows > 65535ll * 32 || cols > 2147483647ll * 32)
+    return set_err(PW_ERR_ARG, "bad transpose sizes %lld x %lld", (long long)rows, (long long)cols);
+  if (rows == 0 || cols == 0) return PW_OK;
+  if (!in || !out || in == out) return set_err(PW_ERR_ARG, "null or aliased buffers");
+  const dim3 grid((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32));
+  hipLaunchKernelGGL(k_transpose_bf16, grid, dim3(256), 0, s, in, rows, cols, out);
   PW_HIP(hipGetLastError());
   return PW_OK;
 }

@@ -51,10 +51,11 @@ def _bind():
     L.pw_select.argtypes = [vp, vp, i64, f32, vp, i64, vp, vp]
     L.pw_random_masks.argtypes = [u64, u64, i64, i32, vp, vp]
     L.pw_bin_floats.argtypes = [vp, i64, f32, f32, i32, vp, vp]
+    L.pw_bf16_transpose.argtypes = [vp, i64, i64, vp, vp]
     for n in ("pw_mlp_gemm", "pw_mlp_encode", "pw_features", "pw_mlp_softmax_xent", "pw_mlp_colsum",
               "pw_mlp_adam", "pw_mlp_score", "pw_to_bf16", "pw_mutate", "pw_select",
               "pw_random_masks", "pw_bin_floats", "pw_fill_f32", "pw_mlp_score_grad", "pw_flip_cdf", "pw_mutate_cdf",
-              "pw_label_counts"):
+              "pw_label_counts", "pw_bf16_transpose"):
         getattr(L, n).restype = i32
     _bound = True
     return L
@@ -96,6 +97,17 @@ def features(codes):
     return lab
 
 
+def transpose16(x, out=None):
+    """(r, c) bf16 (int16) device matrix -> its (c, r) transpose."""
+    import torch
+
+    r, c = x.shape
+    if out is None:
+        out = torch.empty((c, r), dtype=torch.int16, device=x.device)
+    pw.check(_bind().pw_bf16_transpose(_p(x), r, c, _p(out), _s()))
+    return out
+
+
 def to_bf16(t32):
     """fp32 device tensor -> bfloat16 bit patterns (int16 tensor)."""
     import torch
@@ -123,11 +135,14 @@ def _offsets():
 class MLP:
     """Device parameters in flat buffers: fp32 masters P, gradients G (plus
     one slot for the loss), Adam moments M, V and the bf16 copy W16, each
-    with per-tensor views.  One training step is 12 kernel launches: zero G,
-    three forward products, the loss, three weight-gradient products, one
-    bias-gradient column sum (the hidden layers' bias gradients are summed
-    in the epilogues of the input-gradient products), two input-gradient
-    products and one Adam update over all parameters."""
+    with per-tensor views, and W16T, each weight matrix transposed to
+    [out][in] so that both operands of a forward product are contiguous
+    along K (the products then stage both in 16-byte chunks).  One training
+    step is 15 kernel launches: zero G, three forward products, the loss,
+    three weight-gradient products, one bias-gradient column sum (the hidden
+    layers' bias gradients are summed in the epilogues of the input-gradient
+    products), two input-gradient products, one Adam update over all
+    parameters and three transposes."""
 
     def __init__(self, n_in=45, seed=0, device="cuda"):
         import torch
@@ -155,6 +170,8 @@ class MLP:
         self.M = self._views(self.Mf)
         self.V = self._views(self.Vf)
         self.W16 = self._views(self.W16f)
+        self.W16T = {k: torch.empty((v.shape[1], v.shape[0]), dtype=torch.int16, device=device)
+                     for k, v in self.W16.items() if v.dim() == 2}
         self.loss = self.Gf[self.n_par:self.n_par + 1]
         self.step = 0
         self._buf = {}
@@ -180,6 +197,11 @@ class MLP:
     def sync16(self):
         """Refresh the bf16 copy from the fp32 masters."""
         pw.check(_bind().pw_to_bf16(_p(self.Pf), self.n_par, _p(self.W16f), _s()))
+        self._sync_t()
+
+    def _sync_t(self):
+        for k, t in self.W16T.items():
+            transpose16(self.W16[k], t)
 
     def load(self, host):
         """Set parameters from host float arrays (tests)."""
@@ -203,9 +225,11 @@ class MLP:
         else:
             b = self._buffers(n, dev)
             H1, H2, Y = b["H1"], b["H2"], b["Y"]
-        gemm(X16, WIDTH_IN, 1, self.W16["W1"], HIDDEN, 1, n, HIDDEN, WIDTH_IN, C16=H1, bias=self.P["b1"], relu=True)
-        gemm(H1, HIDDEN, 1, self.W16["W2"], HIDDEN, 1, n, HIDDEN, HIDDEN, C16=H2, bias=self.P["b2"], relu=True)
-        gemm(H2, HIDDEN, 1, self.W16["W3"], OUT, 1, n, OUT, HIDDEN, C32=Y, bias=self.P["b3"])
+        # B(k, n) = W[k][n] = W^T[n][k]: the transposed copies are contiguous along k
+        gemm(X16, WIDTH_IN, 1, self.W16T["W1"], 1, WIDTH_IN, n, HIDDEN, WIDTH_IN, C16=H1, bias=self.P["b1"],
+             relu=True)
+        gemm(H1, HIDDEN, 1, self.W16T["W2"], 1, HIDDEN, n, HIDDEN, HIDDEN, C16=H2, bias=self.P["b2"], relu=True)
+        gemm(H2, HIDDEN, 1, self.W16T["W3"], 1, HIDDEN, n, OUT, HIDDEN, C32=Y, bias=self.P["b3"])
         if keep:
             return Y, H1, H2
         return Y
@@ -235,6 +259,7 @@ class MLP:
         self.step += 1
         pw.check(_bind().pw_mlp_adam(_p(self.Pf), _p(self.Gf), _p(self.Mf), _p(self.Vf), self.n_par, lr, b1, b2, eps,
                                      self.step, _p(self.W16f), _s()))
+        self._sync_t()
 
     def train_step(self, X16, labels, lr=1e-3):
         Y, H1, H2 = self.forward(X16, keep=True, fresh=False)

@@ -393,3 +393,29 @@ def test_random_masks_bins_and_select_exact(L):
         got = {tuple(r) for r in out.view(np.uint64).tolist()}
         want = {tuple(r) for r in kept.tolist()}
         assert got <= want and (len(got) == len(want) or len(got) == cap)
+
+
+@pytest.mark.parametrize("rows,cols", [(64, 512), (512, 512), (512, 64), (33, 70), (1, 5)])
+def test_bf16_transpose_exact(rows, cols):
+    from paper_2604_09221_amd import learn as Lr
+
+    rng = np.random.default_rng(rows * 1000 + cols)
+    x = rng.integers(-32768, 32767, size=(rows, cols), dtype=np.int16)
+    got = Lr.transpose16(torch.from_numpy(x).cuda())
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), x.T)
+
+
+def test_forward_uses_transposed_weights_consistently():
+    """The forward products read the [out][in] copies of the weights; after
+    an Adam step those copies equal the transposes of the updated bf16
+    weights."""
+    from paper_2604_09221_amd import learn as Lr
+
+    net = Lr.MLP(n_in=45, seed=3)
+    X = Lr.encode(torch.from_numpy(I.masks128(I.random_masks(8, 4, 128))).cuda().view(-1, 2), 128, 45)
+    lab = Lr.features(torch.zeros((128, 2), dtype=torch.int64, device="cuda") + 6)
+    net.train_step(X, lab, lr=1e-2)
+    torch.cuda.synchronize()
+    for k, t in net.W16T.items():
+        assert torch.equal(t, net.W16[k].t().contiguous()), k
