@@ -126,6 +126,15 @@ pw_status pw_tri_specialize(pw_tri_t tri);
  * NULL to query it).  Host memory only; PW_ERR_ARG if cap is too small. */
 pw_status pw_tri_program(pw_tri_t tri, uint32_t *words, int32_t cap, int32_t *n_words);
 
+/* Copy the handle's group program for G = 2 or 4 lanes per mask (one block
+ * of the reflected diamond, Sec. 2: the half y >= 0 or the quadrant
+ * x, y >= 0, with its earlier neighbours, then the glues that join the
+ * copies of an axis point in two blocks and the 2d antipodal pairs, in
+ * group indices v * G + q) into a host buffer of cap words, as
+ * pw_tri_program.  Degrees 8..12 only.  Errors: PW_ERR_ARG (other G or
+ * degree, cap too small). */
+pw_status pw_tri_group_program(pw_tri_t tri, int32_t G, uint32_t *words, int32_t cap, int32_t *n_words);
+
 /* ------------------------------------------------------------------------
  * Symmetries of the search space (Sec. 3, Table 1).  Host calls; no device
  * work.
@@ -273,11 +282,17 @@ pw_status patchwork_scheme_sweep_graph(pw_tri_t tri, uint64_t first, uint64_t co
  *   d_codes   NULL, or n x 2 uint64 codes written at the masks' positions
  *             (16-byte aligned).
  *   cfg       NULL for the defaults (4096 masks per item, one wave per
- *             block, blocks per CU as LDS and registers allow), or the tuned
- *             launch shape: masks per work item, waves per block (lowered
- *             until a block's LDS for the largest degree of its class fits
- *             in 160 KiB), blocks per CU (0 = as many as LDS and registers
- *             allow).  The library reads no tuning cache itself: the tuned
+ *             block, blocks per CU as LDS and registers allow, lane groups
+ *             PW_MULTI_DEFAULT_LANE_GROUPS), or the tuned launch shape:
+ *             masks per work item, waves per block (lowered until a block's
+ *             LDS for the largest degree of its class fits in 160 KiB),
+ *             blocks per CU (0 = as many as LDS and registers allow), and
+ *             lanes per mask for each degree: bits 2d..2d+1 of lane_groups
+ *             are 0 (one lane per mask), 1 (two lanes: the halves y >= 0 and
+ *             y <= 0 of the reflected diamond, Sec. 2) or 2 (four lanes: the
+ *             four reflected copies of the triangulation); 1 and 2 are
+ *             allowed for degrees 8..12 only (PW_ERR_ARG otherwise).  The
+ *             codes do not depend on the shape.  The library reads no tuning cache itself: the tuned
  *             shapes are kept per degree mix by the Python layer (tune.py,
  *             in tune_cache_gfx950.json beside it, or the file named by the
  *             PW_TUNE environment variable); a C caller passes the shape it
@@ -294,7 +309,11 @@ typedef struct {
   int32_t chunk;
   int32_t waves_per_block;
   int32_t blocks_per_cu;
+  uint32_t lane_groups;
 } pw_multi_config;
+
+/* Lane groups used when cfg is NULL: four lanes per mask for degrees 10..12. */
+#define PW_MULTI_DEFAULT_LANE_GROUPS ((2u << 20) | (2u << 22) | (2u << 24))
 
 pw_status patchwork_scheme_batch_multi(const pw_tri_t *tris, int32_t n_tris, const void *d_masks,
                                        const int64_t *offsets, const pw_hist_t *hists, uint64_t *d_codes,

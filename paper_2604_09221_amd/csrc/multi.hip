@@ -23,12 +23,14 @@
 
 #include "patchwork.h"
 #include "pw_device.h"
+#include "pw_group.h"
 #include "pw_host.h"
 
 namespace pw {
 
 struct TriDesc {
   const uint32_t* prog;
+  const uint32_t* gprog[2];  // group programs for 2 and 4 lanes per mask (degrees 8..12), else null
   uint32_t* err;
   const HistDev* hist;
   int32_t d;
@@ -127,6 +129,91 @@ __global__ __launch_bounds__(256) void k_multi(const TriDesc* __restrict__ tris,
   }
 }
 
+// The same with G lanes per mask (pw_group.h): the wave takes 64 / G masks
+// per batch; lane q of group g evaluates block q of mask begin + base + g,
+// and lane 0 of the group writes its code and counts it.
+template <int D, int G>
+__device__ __forceinline__ void run_item_g(const TriDesc& t, const Item& w, const uint64_t* __restrict__ masks,
+                                           uint64_t* __restrict__ codes, uint32_t* wave, int lane,
+                                           const Overflow& ov) {
+  constexpr int RC = multi_cap(D);
+  using GE = GroupEval<D, G, RC>;
+  using C = typename GE::C;
+  constexpr int NG = GE::GC::NG;
+  const typename GE::Mem M = GE::memory(wave, lane);
+  const int q = lane % G, g = lane / G;
+  const typename C::Mask fl = GE::flip(q);
+  const uint32_t* prog = t.gprog[G == 4 ? 1 : 0];
+  uint32_t errs = 0;
+  WaveTable tab;
+  tab.clear();
+  for (int64_t base = 0; base < w.count; base += NG) {
+    const int64_t i = w.begin + base + g;
+    bool valid = base + g < w.count;
+    typename C::Mask m = 0;
+    if (valid) {
+      if constexpr (sizeof(typename C::Mask) == 8) {
+        m = masks[2 * i];
+      } else {
+        m = ((u128)masks[2 * i + 1] << 64) | (u128)masks[2 * i];
+      }
+    }
+    uint32_t e = 0;
+    const u128 code = GE::run(prog, m ^ fl, M, lane, q, e);
+    valid = valid && q == 0;
+    if (C::CAPPED && (e & kErrOverflow) && valid) {
+      const unsigned long long slot = atomicAdd(ov.n, 1ull);
+      if (slot < ov.cap) {
+        ov.list[2 * slot] = (uint64_t)w.tri;
+        ov.list[2 * slot + 1] = (uint64_t)i;
+      }
+      valid = false;  // counted and written by k_multi_big
+    }
+    errs |= e & ~kErrOverflow;
+    if (codes && valid) store_code(codes, i, code);
+    // (valid lanes hold increasing indices: the lowest lane of a match has
+    // the smallest witness)
+    if (t.use_hist) tab.add_batch((uint64_t)code, (uint64_t)(code >> 64), valid, (uint64_t)i, lane, t.hist);
+  }
+  if (t.use_hist) tab.flush(t.hist);
+  if (errs) atomicOr(t.err, errs);
+}
+
+// k_multi with G lanes per mask; wave_dw dwords of LDS per wave.  Only
+// degrees 8..12 are given to it.
+template <int G>
+__global__ __launch_bounds__(256) void k_multi_g(const TriDesc* __restrict__ tris, const Item* __restrict__ items,
+                                                 int64_t n_items, unsigned long long* __restrict__ ticket,
+                                                 unsigned long long base, const uint64_t* __restrict__ masks,
+                                                 uint64_t* __restrict__ codes, int wave_dw, Overflow ov) {
+  extern __shared__ uint32_t smem[];
+  const int lane = threadIdx.x & 63;
+  uint32_t* wave = smem + (threadIdx.x >> 6) * wave_dw;
+  while (true) {
+    unsigned long long tk = 0;
+    if (lane == 0) tk = atomicAdd(ticket, 1ull);
+    tk = (unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)tk) |
+         ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(tk >> 32)) << 32);
+    const int64_t it = (int64_t)(tk - base);
+    if (it >= n_items) break;
+    const Item w = items[it];
+    const TriDesc t = tris[w.tri];
+    switch (t.d) {
+      case 8: run_item_g<8, G>(t, w, masks, codes, wave, lane, ov); break;
+      case 9: run_item_g<9, G>(t, w, masks, codes, wave, lane, ov); break;
+      case 10: run_item_g<10, G>(t, w, masks, codes, wave, lane, ov); break;
+      case 11: run_item_g<11, G>(t, w, masks, codes, wave, lane, ov); break;
+      case 12: run_item_g<12, G>(t, w, masks, codes, wave, lane, ov); break;
+      default: break;
+    }
+  }
+}
+
+template __global__ void k_multi_g<2>(const TriDesc*, const Item*, int64_t, unsigned long long*, unsigned long long,
+                                      const uint64_t*, uint64_t*, int, Overflow);
+template __global__ void k_multi_g<4>(const TriDesc*, const Item*, int64_t, unsigned long long*, unsigned long long,
+                                      const uint64_t*, uint64_t*, int, Overflow);
+
 // One overflow entry per lane, full phase-4 tables (Cfg<D>).
 template <int D>
 __device__ __forceinline__ void run_big(const TriDesc& t, int64_t i, const uint64_t* __restrict__ masks,
@@ -160,6 +247,19 @@ __global__ __launch_bounds__(64) void k_multi_big(const TriDesc* __restrict__ tr
       case 12: run_big<12>(t, i, masks, codes, smem); break;
       default: break;
     }
+  }
+}
+
+// LDS dwords per wave of k_multi_g<G> at degree d
+template <int G>
+int group_wave_dw(int d) {
+  switch (d) {
+    case 8: return GCfg<8, G, multi_cap(8)>::WAVE_DW;
+    case 9: return GCfg<9, G, multi_cap(9)>::WAVE_DW;
+    case 10: return GCfg<10, G, multi_cap(10)>::WAVE_DW;
+    case 11: return GCfg<11, G, multi_cap(11)>::WAVE_DW;
+    case 12: return GCfg<12, G, multi_cap(12)>::WAVE_DW;
+    default: return 0;
   }
 }
 
@@ -234,7 +334,7 @@ struct MultiPlan {
   std::vector<TriDesc> desc;
   std::vector<Item> items;  // grouped by class (in launch order), longest first within a class
   struct Shape {
-    int words, wpb, per_cu;
+    int wave_dw, wpb, per_cu, group;  // LDS dwords per wave, waves per block, blocks per CU, lanes per mask
   };
   std::vector<Shape> cls;
   std::vector<int> order;  // classes in launch order
@@ -259,12 +359,17 @@ pw_status plan_multi(const pw_tri_t* tris, int32_t n_tris, const void* d_masks, 
   if (n_tris == 0) return PW_OK;
   if (!hists && !d_codes) return set_err(PW_ERR_ARG, "need histograms, codes or both");
   if ((uintptr_t)d_codes & 15) return set_err(PW_ERR_ARG, "d_codes must be 16-byte aligned");
-  pw_multi_config c = {4096, 1, 0};
+  pw_multi_config c = {4096, 1, 0, PW_MULTI_DEFAULT_LANE_GROUPS};
   if (cfg) c = *cfg;
   if (c.chunk < 64 || c.chunk > (1 << 24) || c.waves_per_block < 1 || c.waves_per_block > 4 ||
       c.blocks_per_cu < 0 || c.blocks_per_cu > 32)
     return set_err(PW_ERR_ARG, "bad multi config (chunk %d, waves %d, blocks/CU %d)", c.chunk, c.waves_per_block,
                    c.blocks_per_cu);
+  for (int d = 0; d <= 15; ++d) {
+    const uint32_t code = (c.lane_groups >> (2 * d)) & 3u;
+    if (code == 3 || (code != 0 && (d < kGroupMinDegree || d > kDMax)))
+      return set_err(PW_ERR_ARG, "bad lane group code %u for degree %d (lane_groups 0x%x)", code, d, c.lane_groups);
+  }
   std::vector<TriDesc>& desc = P.desc;
   std::vector<Item>& items = P.items;
   desc.assign(n_tris, TriDesc{});
@@ -275,6 +380,8 @@ pw_status plan_multi(const pw_tri_t* tris, int32_t n_tris, const void* d_masks, 
     if (hists && !hists[t]) return set_err(PW_ERR_ARG, "null histogram %d", t);
     const int d = tris[t]->prog.d;
     desc[t].prog = tris[t]->d_prog;
+    desc[t].gprog[0] = tris[t]->d_gprog[0];
+    desc[t].gprog[1] = tris[t]->d_gprog[1];
     desc[t].err = tris[t]->d_err;
     desc[t].hist = hists ? hists[t]->d_dev : nullptr;
     desc[t].d = d;
@@ -284,8 +391,14 @@ pw_status plan_multi(const pw_tri_t* tris, int32_t n_tris, const void* d_masks, 
   }
   if (items.empty()) return PW_OK;
   if (!d_masks) return set_err(PW_ERR_ARG, "null mask buffer");
-  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_multi),
-                                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  const void* kern[3] = {reinterpret_cast<const void*>(&k_multi), reinterpret_cast<const void*>(&k_multi_g<2>),
+                         reinterpret_cast<const void*>(&k_multi_g<4>)};
+  static const hipError_t attr = [&] {
+    hipError_t e = hipSuccess;
+    for (const void* k : kern)
+      if (e == hipSuccess) e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    return e;
+  }();
   if (attr != hipSuccess) {
     (void)hipGetLastError();
     return set_err(PW_ERR_HIP, "hipFuncSetAttribute: %s (code %d)", hipGetErrorString(attr), (int)attr);
@@ -295,16 +408,18 @@ pw_status plan_multi(const pw_tri_t* tris, int32_t n_tris, const void* d_masks, 
   // largest degree present (3 waves per CU at d = 12).  Degrees whose own
   // areas allow the same number of resident blocks per CU (LDS, registers
   // and the configured cap) share a launch sized for the largest of them;
-  // the launches follow each other on the stream.
+  // the launches follow each other on the stream.  A degree evaluated
+  // with lane groups (G lanes per mask) uses the kernel for G, so its
+  // class holds only degrees with the same G.
   using Shape = MultiPlan::Shape;
-  auto shape_for = [&](int words) {
-    Shape s{words, c.waves_per_block, 1};
-    while (s.wpb > 1 && (size_t)words * 256 * s.wpb > 160 * 1024) --s.wpb;
-    const size_t lds = (size_t)words * 256 * s.wpb;
+  auto shape_for = [&](int wave_dw, int group) {
+    Shape s{wave_dw, c.waves_per_block, 1, group};
+    while (s.wpb > 1 && (size_t)wave_dw * 4 * s.wpb > 160 * 1024) --s.wpb;
+    const size_t lds = (size_t)wave_dw * 4 * s.wpb;
     int per_cu = (int)((160 * 1024) / lds);
     int by_regs = 0;  // resident blocks allowed by the register budget alone
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&by_regs, reinterpret_cast<const void*>(&k_multi), 64 * s.wpb,
-                                                     0) == hipSuccess) {
+    const void* k = kern[group == 1 ? 0 : (group == 2 ? 1 : 2)];
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&by_regs, k, 64 * s.wpb, 0) == hipSuccess) {
       if (by_regs > 0) per_cu = std::min(per_cu, by_regs);
     } else {
       (void)hipGetLastError();
@@ -319,13 +434,19 @@ pw_status plan_multi(const pw_tri_t* tris, int32_t n_tris, const void* d_masks, 
   for (const TriDesc& t : desc) {
     if (t.d < 1 || t.d > 12) return set_err(PW_ERR_ARG, "degree %d outside 1..12", t.d);
     if (P.cls_of_deg[t.d] >= 0) continue;
-    const Shape s = shape_for(lane_words_for(t.d));
-    if ((size_t)s.words * 256 * s.wpb > 160 * 1024)
-      return set_err(PW_ERR_ARG, "block needs %zu bytes of LDS", (size_t)s.words * 256 * s.wpb);
+    const uint32_t code = (c.lane_groups >> (2 * t.d)) & 3u;
+    const int group = code == 0 ? 1 : (code == 1 ? 2 : 4);
+    if (group > 1 && !t.gprog[group == 2 ? 0 : 1])
+      return set_err(PW_ERR_INTERNAL, "triangulation of degree %d has no group program", t.d);
+    const int wave_dw = group == 1 ? 64 * lane_words_for(t.d)
+                                   : (group == 2 ? group_wave_dw<2>(t.d) : group_wave_dw<4>(t.d));
+    const Shape s = shape_for(wave_dw, group);
+    if ((size_t)s.wave_dw * 4 * s.wpb > 160 * 1024)
+      return set_err(PW_ERR_ARG, "block needs %zu bytes of LDS", (size_t)s.wave_dw * 4 * s.wpb);
     int k = 0;
-    while (k < (int)cls.size() && (cls[k].per_cu != s.per_cu || cls[k].wpb != s.wpb)) ++k;
+    while (k < (int)cls.size() && (cls[k].per_cu != s.per_cu || cls[k].wpb != s.wpb || cls[k].group != s.group)) ++k;
     if (k == (int)cls.size()) cls.push_back(s);
-    cls[k].words = std::max(cls[k].words, s.words);
+    cls[k].wave_dw = std::max(cls[k].wave_dw, s.wave_dw);
     P.cls_of_deg[t.d] = k;
   }
   // longest processing time first within a class: cost ~ chunk length x
@@ -333,7 +454,10 @@ pw_status plan_multi(const pw_tri_t* tris, int32_t n_tris, const void* d_masks, 
   std::vector<int>& order = P.order;
   order.resize(cls.size());
   for (size_t k = 0; k < cls.size(); ++k) order[k] = (int)k;
-  std::sort(order.begin(), order.end(), [&](int a, int b) { return cls[a].words > cls[b].words; });
+  // (per mask: a wave's area times G over 64 masks)
+  std::sort(order.begin(), order.end(), [&](int a, int b) {
+    return (int64_t)cls[a].wave_dw * cls[a].group > (int64_t)cls[b].wave_dw * cls[b].group;
+  });
   std::vector<int> rank(cls.size());
   for (size_t k = 0; k < order.size(); ++k) rank[order[k]] = (int)k;
   std::stable_sort(items.begin(), items.end(), [&](const Item& a, const Item& b) {
@@ -363,13 +487,21 @@ pw_status run_multi(const MultiPlan& P, MultiBuffers& B, const void* d_masks, ui
     const int64_t n = (int64_t)(last - first);
     if (n == 0) continue;  // a class whose triangulations have no masks
     const MultiPlan::Shape& s = P.cls[k];
-    const size_t lds = (size_t)s.words * 256 * s.wpb;
+    const size_t lds = (size_t)s.wave_dw * 4 * s.wpb;
     const int64_t blocks = std::min<int64_t>((int64_t)cu_count() * s.per_cu, (n + s.wpb - 1) / s.wpb);
     const unsigned long long base = *B.issued;
     // every wave takes one ticket past the end of its launch before it stops
     *B.issued += (unsigned long long)n + (unsigned long long)blocks * s.wpb;
-    hipLaunchKernelGGL(k_multi, dim3((unsigned)blocks), dim3(64 * s.wpb), lds, stream, B.tris, B.items + first, n,
-                       B.ticket, base, static_cast<const uint64_t*>(d_masks), d_codes, s.words, ov);
+    const uint64_t* masks = static_cast<const uint64_t*>(d_masks);
+    if (s.group == 1)
+      hipLaunchKernelGGL(k_multi, dim3((unsigned)blocks), dim3(64 * s.wpb), lds, stream, B.tris, B.items + first, n,
+                         B.ticket, base, masks, d_codes, s.wave_dw / 64, ov);
+    else if (s.group == 2)
+      hipLaunchKernelGGL(k_multi_g<2>, dim3((unsigned)blocks), dim3(64 * s.wpb), lds, stream, B.tris,
+                         B.items + first, n, B.ticket, base, masks, d_codes, s.wave_dw, ov);
+    else
+      hipLaunchKernelGGL(k_multi_g<4>, dim3((unsigned)blocks), dim3(64 * s.wpb), lds, stream, B.tris,
+                         B.items + first, n, B.ticket, base, masks, d_codes, s.wave_dw, ov);
     const hipError_t le = hipGetLastError();
     if (le != hipSuccess) {
       *B.issued = base;  // a launch that failed took no tickets

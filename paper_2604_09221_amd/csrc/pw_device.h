@@ -171,6 +171,8 @@ struct Lane {
   __device__ __forceinline__ uint32_t& word(int k) const { return w[k * 64]; }
   // word k of the lane's entry row (entries 4 k / EB .. 4 (k + 1) / EB - 1)
   __device__ __forceinline__ uint32_t& eword(int k) const { return reinterpret_cast<uint32_t*>(e)[k]; }
+  // byte row x of the parent table
+  __device__ __forceinline__ uint8_t& prow(int x) const { return *reinterpret_cast<uint8_t*>(b + x * 64); }
 };
 
 
@@ -228,20 +230,26 @@ struct Eval {
   // end of phase 1 for v: its root so far
   __device__ static __forceinline__ void close(const Lane& L, int v, uint32_t rv) { ent(L, v) = (Ent)rv; }
 
-  // ---- region data (phases 3-4)
-  __device__ static __forceinline__ uint8_t& par_ref(const Lane& L, int x) {
-    return *reinterpret_cast<uint8_t*>(L.b + x * 64);
+  // ---- region data (phases 3-4), through a view of the region tables:
+  // Lane (one mask per lane) or the view of a lane group (pw_group.h)
+  template <class LV>
+  __device__ static __forceinline__ int par(const LV& L, int x) {
+    return L.prow(x);
   }
-  __device__ static __forceinline__ int par(const Lane& L, int x) { return par_ref(L, x); }
-  __device__ static __forceinline__ void set_par(const Lane& L, int x, int p) { par_ref(L, x) = (uint8_t)p; }
-  __device__ static __forceinline__ Adj load_adj(const Lane& L, int x) {
+  template <class LV>
+  __device__ static __forceinline__ void set_par(const LV& L, int x, int p) {
+    L.prow(x) = (uint8_t)p;
+  }
+  template <class LV>
+  __device__ static __forceinline__ Adj load_adj(const LV& L, int x) {
     if constexpr (C::ADJ_W == 1) {
       return L.word(C::CHILD_BASE + x);
     } else {
       return (uint64_t)L.word(C::CHILD_BASE + 2 * x) | ((uint64_t)L.word(C::CHILD_BASE + 2 * x + 1) << 32);
     }
   }
-  __device__ static __forceinline__ void store_adj(const Lane& L, int x, Adj a) {
+  template <class LV>
+  __device__ static __forceinline__ void store_adj(const LV& L, int x, Adj a) {
     if constexpr (C::ADJ_W == 1) {
       L.word(C::CHILD_BASE + x) = a;
     } else {
@@ -249,13 +257,15 @@ struct Eval {
       L.word(C::CHILD_BASE + 2 * x + 1) = (uint32_t)(a >> 32);
     }
   }
-  __device__ static __forceinline__ Code load_code(const Lane& L, int x) {
+  template <class LV>
+  __device__ static __forceinline__ Code load_code(const LV& L, int x) {
     constexpr int W = C::CODE_W;
     Code r = 0;
     for (int k = W - 1; k >= 0; --k) r = (Code)(r << 32) | (Code)L.word(C::CODE_BASE + W * x + k);
     return r;
   }
-  __device__ static __forceinline__ void store_code(const Lane& L, int x, Code c) {
+  template <class LV>
+  __device__ static __forceinline__ void store_code(const LV& L, int x, Code c) {
     constexpr int W = C::CODE_W;
     for (int k = 0; k < W; ++k) L.word(C::CODE_BASE + W * x + k) = (uint32_t)(c >> (32 * k));
   }
@@ -488,7 +498,8 @@ struct Eval {
 
   // Phase 4: re-root the region tree at `root` and build the canonical
   // code (AHU) from the leaves up.
-  __device__ __forceinline__ static u128 finish(const Lane& L, int nR, Adj roots, uint32_t& errs) {
+  template <class LV>
+  __device__ __forceinline__ static u128 finish(const LV& L, int nR, Adj roots, uint32_t& errs) {
     uint32_t err = 0;
     if (roots == 0 || (roots & (roots - 1))) err |= kErrRoot;  // exactly one root region
     if (nR > C::RMAX) err |= C::CAPPED ? kErrOverflow : kErrRegions;

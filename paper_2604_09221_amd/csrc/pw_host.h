@@ -13,6 +13,10 @@ struct pw_tri {
   pw::HostProgram prog;
   uint32_t* d_prog = nullptr;
   uint32_t* d_err = nullptr;
+  // group programs for 2 and 4 lanes per mask (degrees 8..12, else empty)
+  uint32_t gprog[2][pw::kGroupWordsMax];
+  int n_gprog[2] = {0, 0};
+  uint32_t* d_gprog[2] = {nullptr, nullptr};
   int device = 0;
   // kernels specialised to this triangulation (pw_tri_specialize), or null
   hipModule_t jit_mod = nullptr;

@@ -226,15 +226,33 @@ pw_status pw_tri_create(int32_t d, const int16_t* edges_ij, int32_t n_edges, pw_
     delete t;
     return set_err(rc, "%s", msg);
   }
+  if (d >= kGroupMinDegree) {
+    for (int k = 0; k < 2; ++k) {
+      rc = build_group_program(t->prog, k == 0 ? 2 : 4, t->gprog[k], msg, sizeof msg);
+      if (rc != 0) {
+        delete t;
+        return set_err(rc, "%s", msg);
+      }
+      t->n_gprog[k] = group_program_words(d, k == 0 ? 2 : 4);
+    }
+  }
   hipError_t e = hipGetDevice(&t->device);
   if (e == hipSuccess) e = hipMalloc(&t->d_prog, sizeof(uint32_t) * t->prog.n_words);
   if (e == hipSuccess) e = hipMalloc(&t->d_err, sizeof(uint32_t));
   if (e == hipSuccess)
     e = hipMemcpy(t->d_prog, t->prog.words, sizeof(uint32_t) * t->prog.n_words, hipMemcpyHostToDevice);
+  for (int k = 0; k < 2; ++k) {
+    if (t->n_gprog[k] == 0) continue;
+    if (e == hipSuccess) e = hipMalloc(&t->d_gprog[k], sizeof(uint32_t) * t->n_gprog[k]);
+    if (e == hipSuccess)
+      e = hipMemcpy(t->d_gprog[k], t->gprog[k], sizeof(uint32_t) * t->n_gprog[k], hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess) e = hipMemset(t->d_err, 0, sizeof(uint32_t));
   if (e != hipSuccess) {
     if (t->d_prog) (void)hipFree(t->d_prog);
     if (t->d_err) (void)hipFree(t->d_err);
+    for (uint32_t* g : t->d_gprog)
+      if (g) (void)hipFree(g);
     delete t;
     return set_err(PW_ERR_HIP, "%s (code %d)", hipGetErrorString(e), (int)e);
   }
@@ -249,6 +267,8 @@ pw_status pw_tri_destroy(pw_tri_t t) {
   if (t->jit_mod) (void)hipModuleUnload(t->jit_mod);
   (void)hipFree(t->d_prog);
   (void)hipFree(t->d_err);
+  for (uint32_t* g : t->d_gprog)
+    if (g) (void)hipFree(g);
   delete t;
   return PW_OK;
 }
@@ -270,6 +290,19 @@ pw_status pw_tri_program(pw_tri_t t, uint32_t* words, int32_t cap, int32_t* n_wo
   if (words) {
     if (cap < t->prog.n_words) return set_err(PW_ERR_ARG, "program has %d words, buffer %d", t->prog.n_words, cap);
     std::memcpy(words, t->prog.words, sizeof(uint32_t) * t->prog.n_words);
+  }
+  return PW_OK;
+}
+
+pw_status pw_tri_group_program(pw_tri_t t, int32_t G, uint32_t* words, int32_t cap, int32_t* n_words) {
+  if (!t) return set_err(PW_ERR_ARG, "null handle");
+  if (G != 2 && G != 4) return set_err(PW_ERR_ARG, "lane group size must be 2 or 4, got %d", G);
+  const int k = G == 2 ? 0 : 1;
+  if (t->n_gprog[k] == 0) return set_err(PW_ERR_ARG, "group programs exist for degrees 8..12, not %d", t->prog.d);
+  if (n_words) *n_words = t->n_gprog[k];
+  if (words) {
+    if (cap < t->n_gprog[k]) return set_err(PW_ERR_ARG, "group program has %d words, buffer %d", t->n_gprog[k], cap);
+    std::memcpy(words, t->gprog[k], sizeof(uint32_t) * t->n_gprog[k]);
   }
   return PW_OK;
 }

@@ -167,4 +167,88 @@ int build_program(int d, const int16_t* edges_ij, int n_edges, HostProgram* prog
   return 0;
 }
 
+int build_group_program(const HostProgram& full, int G, std::uint32_t* words, char* err, int errlen) {
+  const int kArg = -1, kInternal = -5;
+  const int d = full.d;
+  if (G != 2 && G != 4) return fail(err, errlen, kArg, "lane group size must be 2 or 4");
+  if (d < 2 || d > kDMax || !words) return fail(err, errlen, kArg, "bad degree or null pointer");
+  // diamond vertices in program order (rows y = -d..d, x ascending)
+  std::vector<Pt> vert;
+  for (int y = -d; y <= d; ++y)
+    for (int x = -d; x <= d; ++x)
+      if (std::abs(x) + std::abs(y) <= d) vert.push_back({x, y});
+  if ((int)vert.size() != full.nV) return fail(err, errlen, kInternal, "diamond size mismatch");
+  // block 0: y >= 0 (and x >= 0 for G = 4), numbered in diamond order
+  auto in_block0 = [&](Pt p) { return p.second >= 0 && (G == 2 || p.first >= 0); };
+  std::vector<int> local(full.nV, -1);
+  std::vector<int> of_local;
+  for (int v = 0; v < full.nV; ++v)
+    if (in_block0(vert[v])) {
+      local[v] = (int)of_local.size();
+      of_local.push_back(v);
+    }
+  const int NB = (int)of_local.size();
+  if (NB != group_block_vertices(d, G)) return fail(err, errlen, kInternal, "block size mismatch");
+  // records and earlier-neighbour lists (the diamond's, restricted to the block)
+  int off = 0;
+  std::vector<std::uint32_t> nbrs;
+  for (int b = 0; b < NB; ++b) {
+    const int v = of_local[b];
+    const int x = vert[v].first, y = vert[v].second;
+    const std::uint32_t rec = full.words[v];
+    const std::uint32_t n_all = (rec >> 8) & 0xFF, off_all = rec >> 16;
+    std::uint32_t n = 0;
+    for (std::uint32_t k = 0; k < n_all; ++k) {
+      const int u = (int)full.words[full.nV + off_all + k];
+      if (local[u] >= 0) {
+        nbrs.push_back((std::uint32_t)local[u]);
+        ++n;
+      }
+    }
+    // the kernels take the first earlier neighbour as the spanning-tree parent
+    if (b > 0 && n == 0) return fail(err, errlen, kInternal, "a block vertex has no earlier neighbour");
+    if (off >= (1 << 12)) return fail(err, errlen, kInternal, "neighbour list too long");
+    words[b] = (rec & 0xFF) | (n << 8) | ((std::uint32_t)off << 16) | ((std::uint32_t)(x == 0) << 28) |
+               ((std::uint32_t)(y == 0) << 29);
+    off += (int)n;
+  }
+  if (off != group_block_edges(d, G)) return fail(err, errlen, kInternal, "block edge count mismatch");
+  for (int k = 0; k < off; ++k) words[NB + k] = nbrs[k];
+  int at = NB + off;
+  // glues, in the order the device derives its tree parents
+  const int dx = 1, dy = G == 4 ? 2 : 1;
+  int n_glue = 0;
+  for (int q = 1; q < G; ++q) {
+    const int sx = G == 4 ? (q & 1) : 0, sy = G == 4 ? (q >> 1) : q;
+    for (int b = 0; b < NB; ++b) {
+      const Pt p = vert[of_local[b]];
+      const bool gx = sx && p.first == 0, gy = sy && p.second == 0;
+      if (!gx && !gy) continue;
+      const int partner = q - (gx ? dx : dy);
+      words[at++] = (std::uint32_t)(b * G + partner) | ((std::uint32_t)(b * G + q) << 16);
+      ++n_glue;
+    }
+  }
+  if (n_glue != group_glues(d, G)) return fail(err, errlen, kInternal, "glue count mismatch");
+  // antipodal pairs: each diamond point through the lowest block that holds it
+  auto gidx = [&](int v) {
+    const int x = vert[v].first, y = vert[v].second;
+    const int sx = G == 4 && x < 0 ? 1 : 0, sy = y < 0 ? 1 : 0;
+    const int q = G == 4 ? sx + 2 * sy : sy;
+    const Pt p0{G == 4 ? std::abs(x) : x, std::abs(y)};
+    int b = -1;
+    for (int k = 0; k < NB; ++k)
+      if (vert[of_local[k]] == p0) b = k;
+    return b * G + q;
+  };
+  for (int t = 0; t < full.nP; ++t) {
+    const std::uint32_t w = full.words[full.nV + full.nE + t];
+    int a = gidx((int)(w & 0xFFFF)), b = gidx((int)(w >> 16));
+    if (a > b) std::swap(a, b);
+    words[at++] = (std::uint32_t)a | ((std::uint32_t)b << 16);
+  }
+  if (at != group_program_words(d, G)) return fail(err, errlen, kInternal, "group program size mismatch");
+  return 0;
+}
+
 }  // namespace pw

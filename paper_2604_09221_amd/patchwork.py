@@ -30,7 +30,26 @@ _lib = None
 
 class MultiConfig(ctypes.Structure):
     """Launch shape of patchwork_scheme_batch_multi (pw_multi_config)."""
-    _fields_ = [("chunk", ctypes.c_int32), ("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
+    _fields_ = [("chunk", ctypes.c_int32), ("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("lane_groups", ctypes.c_uint32)]
+
+
+def lane_groups_code(groups: dict) -> int:
+    """pw_multi_config.lane_groups from {degree: lanes per mask (1, 2 or 4)}."""
+    code = 0
+    for d, g in groups.items():
+        code |= {1: 0, 2: 1, 4: 2}[int(g)] << (2 * int(d))
+    return code
+
+
+def lane_groups_of(code: int) -> dict:
+    """{degree: lanes per mask} for the degrees with more than one lane."""
+    return {d: {1: 2, 2: 4}[(code >> (2 * d)) & 3] for d in range(16) if (code >> (2 * d)) & 3}
+
+
+# the library's lane groups when no configuration is passed
+# (PW_MULTI_DEFAULT_LANE_GROUPS: four lanes per mask for degrees 10..12)
+DEFAULT_LANE_GROUPS = lane_groups_code({10: 4, 11: 4, 12: 4})
 
 
 class PatchworkError(RuntimeError):
@@ -76,6 +95,7 @@ def lib():
                                                ctypes.POINTER(vp), vp, ctypes.POINTER(MultiConfig), vp]
     L.patchwork_scheme_batch_multi_noalloc.argtypes = L.patchwork_scheme_batch_multi.argtypes
     L.pw_tri_program.argtypes = [vp, u32p, i32, i32p]
+    L.pw_tri_group_program.argtypes = [vp, i32, u32p, i32, i32p]
     L.pw_tri_canonical.argtypes = [i32, i16p, i32, i16p, i32p, i32p]
     L.pw_point_map.argtypes = [i32, i32, i32p]
     L.pw_class_fixed_bits.argtypes = [i32, u64p]
@@ -87,7 +107,7 @@ def lib():
     L.patchwork_scheme_programs.argtypes = [i32, vp, i64, vp, i64, vp, vp, vp, vp]
     L.pw_tri_objective.argtypes = [i32, vp, i64, i32, i32, i32, i32, vp, i32, vp, vp]
     L.pw_anneal_accept.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp, i32, u64, u64, vp, vp]
-    for name in ("pw_tri_program", "pw_tri_canonical", "pw_point_map", "pw_class_fixed_bits", "pw_program_words",
+    for name in ("pw_tri_program", "pw_tri_group_program", "pw_tri_canonical", "pw_point_map", "pw_class_fixed_bits", "pw_program_words",
                  "pw_adjacency_from_edges", "pw_edges_from_adjacency", "pw_flip_walk", "pw_build_programs",
                  "patchwork_scheme_programs", "pw_tri_objective", "pw_anneal_accept"):
         getattr(L, name).restype = i32
@@ -180,6 +200,15 @@ class Triangulation:
         """Build and load kernels specialised to this triangulation."""
         check(lib().pw_tri_specialize(self.handle))
         return self
+
+    def group_program(self, G: int) -> np.ndarray:
+        """The handle's group program for G = 2 or 4 lanes per mask (host copy)."""
+        n = ctypes.c_int32()
+        check(lib().pw_tri_group_program(self.handle, int(G), None, 0, ctypes.byref(n)))
+        w = np.zeros(n.value, dtype=np.uint32)
+        check(lib().pw_tri_group_program(self.handle, int(G), w.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                         n.value, ctypes.byref(n)))
+        return w
 
     def program(self) -> np.ndarray:
         """The handle's program words (host copy)."""
@@ -329,7 +358,8 @@ def batch_multi(tris, masks128, offsets, hists=None, codes=None, config=None, st
     masks128: device int64 tensor holding two words per mask; triangulation
     t owns masks [offsets[t], offsets[t+1]).  hists: list of Histogram (one
     per triangulation) or None; codes: (n,2) int64 device tensor or None.
-    config: (chunk, waves_per_block, blocks_per_cu), or None for the tuned
+    config: (chunk, waves_per_block, blocks_per_cu[, lane_groups]) -- a
+    missing lane_groups is DEFAULT_LANE_GROUPS -- or None for the tuned
     shape from the tuning cache (defaults if there is none).  noalloc: use
     patchwork_scheme_batch_multi_noalloc (the library's fixed device array
     instead of buffers it allocates)."""
@@ -343,6 +373,8 @@ def batch_multi(tris, masks128, offsets, hists=None, codes=None, config=None, st
         from . import tune
 
         config = tune.lookup_multi([t.d for t in tris])
+    if config is not None and len(config) == 3:
+        config = (*config, DEFAULT_LANE_GROUPS)
     cfg = MultiConfig(*config) if config is not None else None
     fn = lib().patchwork_scheme_batch_multi_noalloc if noalloc else lib().patchwork_scheme_batch_multi
     check(fn(

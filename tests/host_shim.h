@@ -1,7 +1,8 @@
-// Host shim for tests/test_host_emulation.py: lets g++ compile the device
-// header (pw_device.h) and a generated per-triangulation evaluator, so one
-// lane's evaluation runs on the CPU.  Wave-level intrinsics (ballots,
-// atomics, lane reads) are not emulated and abort if reached.
+// Host shim for tests/test_host_emulation.py and tests/test_group_emulation.py:
+// lets g++ compile the device headers (pw_device.h, pw_group.h) and a
+// generated per-triangulation evaluator, so the evaluation runs on the CPU.
+// Wave-level intrinsics (ballots, shuffles, atomics, lane reads) are not
+// emulated and abort if reached.
 #pragma once
 #define __HIPCC_RTC__ 1
 #include <cstdint>
@@ -27,11 +28,13 @@ static inline int __clzll(long long x) { return x ? __builtin_clzll((unsigned lo
 static inline int __clz(int x) { return x ? __builtin_clz((unsigned)x) : 32; }
 static inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
 static inline int __ffsll(unsigned long long x) { return __builtin_ffsll((long long)x); }
+static inline int __popc(unsigned x) { return __builtin_popcount(x); }
 [[noreturn]] static inline void emu_unsupported() { std::fprintf(stderr, "unsupported in emulation\n"); std::abort(); }
 template <class T> static inline T atomicAdd(T*, T) { emu_unsupported(); }
 template <class T> static inline T atomicMin(T*, T) { emu_unsupported(); }
 template <class T> static inline T atomicOr(T*, T) { emu_unsupported(); }
 static inline uint64_t __ballot(int) { emu_unsupported(); }
+static inline int __shfl_xor(int, int, int) { emu_unsupported(); }
 static inline uint64_t __builtin_amdgcn_ballot_w64(bool) { emu_unsupported(); }
 static inline int emu_readlane(int, int) { emu_unsupported(); }
 #define __builtin_amdgcn_readlane(a, b) emu_readlane(a, b)

@@ -1,7 +1,9 @@
 """GPU parity of the batched multi-triangulation call
 (patchwork_scheme_batch_multi): uneven degrees 4..12 in one call, codes
 bit-exact against the oracle, per-triangulation histograms equal to the
-codes' histograms, and identical tables under different launch shapes."""
+codes' histograms, and identical tables under different launch shapes,
+including every lane-group size (1, 2 or 4 lanes per mask) for degrees
+8..12."""
 from __future__ import annotations
 
 import os
@@ -58,17 +60,19 @@ def test_multi_codes_and_histograms(pw):
         assert np.array_equal(got[a:b], want), (t, int(d))
         assert hists[t].read() == hist_of(want, a), (t, int(d))
         assert tris[t].errors() == 0
-    # another launch shape: the same tables
+    # another launch shape, one lane per mask everywhere: the same tables
     hists2 = [pw.Histogram(1024) for _ in tris]
-    pw.batch_multi(tris, mt, offsets, hists=hists2, config=(4096, 2, 2))
+    pw.batch_multi(tris, mt, offsets, hists=hists2, config=(4096, 2, 2, 0))
     for h1, h2 in zip(hists, hists2):
         assert h1.read() == h2.read()
     # four waves per block: each LDS class lowers it until its block fits
     # (3 at d = 12, 4 at d = 11 and below)
     assert {10, 11, 12} <= {int(d) for d in degs}
+    # (and two lanes per mask for degrees 8..12)
     hists3 = [pw.Histogram(1024) for _ in tris]
     codes3 = torch.zeros_like(codes)
-    pw.batch_multi(tris, mt, offsets, hists=hists3, codes=codes3, config=(512, 4, 0))
+    g2 = pw.lane_groups_code({d: 2 for d in range(8, 13)})
+    pw.batch_multi(tris, mt, offsets, hists=hists3, codes=codes3, config=(512, 4, 0, g2))
     assert torch.equal(codes3, codes)
     for h1, h3 in zip(hists, hists3):
         assert h1.read() == h3.read()
@@ -121,11 +125,13 @@ def test_multi_literal_lift_slots_and_edge_cases(pw):
     pw.batch_multi(tris, mt, empty, codes=codes)                 # nothing to do
 
 
-def test_multi_many_regions_take_the_overflow_path(pw):
+@pytest.mark.parametrize("groups", [{}, {10: 4, 11: 4, 12: 4, 9: 2}, {10: 2, 11: 2, 12: 2}])
+def test_multi_many_regions_take_the_overflow_path(pw, groups):
     """Degrees 10..12 run with phase-4 tables for at most 32 regions; masks
     with more (Harnack: 38, 46, 57 regions, and near-Harnack masks) are
     evaluated again with the full tables.  Codes, histograms (counts and
-    witnesses) and error flags must be as for any other mask."""
+    witnesses) and error flags must be as for any other mask, with one lane
+    per mask and with lane groups."""
     rng = np.random.default_rng(9)
     degs = [10, 11, 12, 9, 12]
     edges = [I.standard_triangulation(d) if k % 2 == 0 else I.lift_triangulation(d, 40 + k, noise=1.0)
@@ -147,7 +153,7 @@ def test_multi_many_regions_take_the_overflow_path(pw):
     mt = torch.from_numpy(I.masks128(allm)).cuda()
     codes = torch.empty((len(allm), 2), dtype=torch.int64, device="cuda")
     hists = [pw.Histogram(4096) for _ in tris]
-    pw.batch_multi(tris, mt, offsets, hists=hists, codes=codes, config=(256, 1, 0))
+    pw.batch_multi(tris, mt, offsets, hists=hists, codes=codes, config=(256, 1, 0, pw.lane_groups_code(groups)))
     got = codes.cpu().numpy().view(np.uint64)
     many = 0
     for t, (d, E) in enumerate(zip(degs, edges)):
@@ -159,6 +165,60 @@ def test_multi_many_regions_take_the_overflow_path(pw):
         if d >= 10:
             many += sum(oracle.n_ovals(int(lo) | (int(hi) << 64)) + 1 > 32 for lo, hi in want)
     assert many > 100   # the overflow path did run
+
+
+@pytest.mark.parametrize("G,wpb,chunk", [(2, 1, 256), (4, 1, 256), (4, 4, 1000), (2, 2, 333)])
+def test_multi_lane_groups_every_degree(pw, G, wpb, chunk):
+    """G lanes per mask for every degree 8..12: codes equal the oracle's for
+    every mask (standard and lifted triangulations, the Harnack mask and its
+    single flips, all '+', random masks; per-triangulation counts that are
+    not multiples of the 64 / G masks a wave holds), histograms equal the
+    codes' histograms and those of the one-lane call, and no error flags."""
+    degs = [8, 9, 10, 11, 12, 8, 10, 12]
+    edges = [I.standard_triangulation(d) if k < 5 and k % 2 == 0 else I.lift_triangulation(d, 60 + k, noise=1.0)
+             for k, d in enumerate(degs)]
+    masks = []
+    for k, d in enumerate(degs):
+        nA = I.n_points(d)
+        h = I.harnack_mask(d)
+        rows = [h, 0] + [h ^ (1 << b) for b in range(1, nA, 2)]
+        m = np.zeros((len(rows) + 700 + 13 * k, 2), dtype=np.uint64)
+        m[:len(rows), 0] = [x & ((1 << 64) - 1) for x in rows]
+        m[:len(rows), 1] = [x >> 64 for x in rows]
+        m[len(rows):] = I.random_masks(d, 300 + k, len(m) - len(rows))
+        masks.append(m)
+    offsets = np.concatenate([[0], np.cumsum([len(m) for m in masks])]).astype(np.int64)
+    tris = [pw.Triangulation(int(d), E) for d, E in zip(degs, edges)]
+    allm = np.vstack(masks)
+    mt = torch.from_numpy(I.masks128(allm)).cuda()
+    code = pw.lane_groups_code({d: G for d in range(8, 13)})
+    codes = torch.zeros((len(allm), 2), dtype=torch.int64, device="cuda")
+    hists = [pw.Histogram(4096) for _ in tris]
+    pw.batch_multi(tris, mt, offsets, hists=hists, codes=codes, config=(chunk, wpb, 0, code))
+    got = codes.cpu().numpy().view(np.uint64)
+    for t, (d, E) in enumerate(zip(degs, edges)):
+        a, b = offsets[t], offsets[t + 1]
+        want = oracle.scheme_many(int(d), E, masks[t], threads=THREADS)
+        assert np.array_equal(got[a:b], want), (t, int(d))
+        assert hists[t].read() == hist_of(want, a), (t, int(d))
+        assert tris[t].errors() == 0
+    # mixed: one, two and four lanes per mask in one call
+    mixed = pw.lane_groups_code({8: 1, 9: 4, 10: 2, 11: 1, 12: G})
+    hists1 = [pw.Histogram(4096) for _ in tris]
+    pw.batch_multi(tris, mt, offsets, hists=hists1, config=(chunk, wpb, 0, mixed))
+    for h, h1 in zip(hists, hists1):
+        assert h.read() == h1.read()
+
+
+def test_multi_lane_groups_refused_below_degree_8(pw):
+    tris = [pw.Triangulation(7, I.standard_triangulation(7))]
+    mt = torch.zeros((64, 2), dtype=torch.int64, device="cuda")
+    codes = torch.zeros((64, 2), dtype=torch.int64, device="cuda")
+    for groups in ({7: 2}, {7: 4}):
+        with pytest.raises(pw.PatchworkError):
+            pw.batch_multi(tris, mt.view(-1), [0, 64], codes=codes, config=(256, 1, 0, pw.lane_groups_code(groups)))
+    with pytest.raises(pw.PatchworkError):
+        pw.batch_multi(tris, mt.view(-1), [0, 64], codes=codes, config=(256, 1, 0, 3 << 20))
 
 
 def test_multi_full_size_sampled(pw):
