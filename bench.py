@@ -49,8 +49,8 @@ TRAFFIC_PROFILE = "profiles/pw_jit_enum_snap_d7_sweep_counters.md"
 # the same for the batched call (its kernel, the program builder and the
 # tuned launch shape, which sets the number of histogram flushes)
 MULTI_SOURCES = ("paper_2604_09221_amd/csrc/pw_device.h", "paper_2604_09221_amd/csrc/pw_internal.h",
-                 "paper_2604_09221_amd/csrc/multi.hip", "paper_2604_09221_amd/csrc/tri.cpp",
-                 "paper_2604_09221_amd/tune_cache_gfx950.json")
+                 "paper_2604_09221_amd/csrc/pw_group.h", "paper_2604_09221_amd/csrc/multi.hip",
+                 "paper_2604_09221_amd/csrc/tri.cpp", "paper_2604_09221_amd/tune_cache_gfx950.json")
 MULTI_TRAFFIC_PROFILE = "profiles/k_multi_batched_uneven_4096x2p16_counters.md"
 # the d=6 codes + histogram launches (the generated kernel's sources)
 D6_SOURCES = KERNEL_SOURCES
@@ -204,7 +204,8 @@ def bench_multi(args):
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_INT_OPS / 1e12, "unit": "TOP/s",
                      "frac": achieved * 1e12 / PEAK_INT_OPS,
                      "traffic": profiled_traffic(MULTI_TRAFFIC_PROFILE, MULTI_SOURCES)
-                     if n_slots == 4096 and not args.varied else None, "kernel": "pw::k_multi",
+                     if n_slots == 4096 and not args.varied else None,
+                     "kernel": "pw::k_multi, pw::k_multi_g<2>, pw::k_multi_g<4>",
                      "per": "call (the class launches back to back)",
                      "avg_call_ms": sum(times) / len(times) * 1e3},
     }

@@ -41,6 +41,21 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
 
 
+def test_multi_config_layout_and_default_lane_groups():
+    """The ctypes mirror of pw_multi_config and the Python copy of
+    PW_MULTI_DEFAULT_LANE_GROUPS agree with the header; the lane-group
+    code round-trips."""
+    text = open(os.path.join(ROOT, "include", "patchwork.h")).read()
+    body = re.search(r"typedef struct \{([^}]*)\} pw_multi_config;", text).group(1)
+    fields = re.findall(r"(u?int32_t)\s+([a-z_]+);", body)
+    assert [f for _, f in fields] == [f for f, _ in pw.MultiConfig._fields_]
+    expr = re.search(r"#define PW_MULTI_DEFAULT_LANE_GROUPS (.*)", text).group(1)
+    assert eval(expr.replace("u", "")) == pw.DEFAULT_LANE_GROUPS
+    g = {8: 2, 9: 4, 11: 4, 12: 2}
+    assert pw.lane_groups_of(pw.lane_groups_code(g)) == g
+    assert pw.lane_groups_code({7: 1}) == 0
+
+
 def test_mask_bytes():
     assert [pw.mask_bytes(d) for d in range(1, 13)] == [4] * 6 + [8] * 3 + [16] * 3
     with pytest.raises(pw.PatchworkError):
