@@ -151,8 +151,9 @@ struct GroupEval {
       const uint32_t self = (uint32_t)(v * G + q);
       uint32_t rv = self;
       for (int k = 0; k < nn; ++k) {
-        const int u = (int)nbr[o + k];
-        const uint32_t su = sign(prog, m, u);
+        const uint32_t nw = nbr[o + k];
+        const int u = (int)(nw & 0xFFFF);
+        const uint32_t su = bit(m, (nw >> 16) & 0x7F) ^ ((nw >> 23) & 1u);
         const uint32_t r = root(M, M.own[u * G]);
         M.own[u * G] = (uint16_t)r;
         const bool same = su == sv;
@@ -250,7 +251,8 @@ struct GroupEval {
     const bool gx = sx && ((rec >> 28) & 1u), gy = sy && ((rec >> 29) & 1u);
     const bool glued = gx || gy;
     const bool has_t = v > 0 || q > 0;
-    const int t_loc = v > 0 ? (int)prog[GC::NB + ((rec >> 16) & 0xFFF)] : 0;
+    const uint32_t tw = v > 0 ? prog[GC::NB + ((rec >> 16) & 0xFFF)] : 0u;
+    const int t_loc = (int)(tw & 0xFFFF);
     const uint32_t t_idx = glued ? (uint32_t)(v * G + q - (gx ? 1 : (G == 4 ? 2 : 1))) : (uint32_t)(t_loc * G + q);
     const uint32_t rt = region(M, has_t ? t_idx : 0u);
     const uint32_t rid = is_root ? (uint32_t)cid : (M.grp[ev & kIdx] & 0xFFu);
@@ -261,7 +263,7 @@ struct GroupEval {
     if constexpr (C::EVEN) {
       hit = is_root && (ev & kOdd);
     } else {
-      const bool crossed = has_t && !glued && sign(prog, m, v) != sign(prog, m, t_loc);
+      const bool crossed = has_t && !glued && sign(prog, m, v) != (bit(m, (tw >> 16) & 0x7F) ^ ((tw >> 23) & 1u));
       hit = crossed && rid == rt;
     }
     roots |= hit ? E::one((int)rid & (AB - 1)) : (Adj)0;

@@ -47,7 +47,7 @@ constexpr uint32_t kErrOverflow = 16u;  // more regions than capped tables hold 
 //   words [0, NB)         vertex records: p | g << 7 | n << 8 | off << 16,
 //                         with off in bits 16..27, bit 28 = (x == 0),
 //                         bit 29 = (y == 0) (block coordinates)
-//   words [NB, NB+NEB)    earlier-neighbour block ids
+//   words [NB, NB+NEB)    earlier neighbours: block id | (p | g << 7) << 16
 //   words [.., +NGL)      glues a | b << 16 (group indices, a < b): the
 //                         copies of an axis point in two blocks
 //   words [.., +2d)       antipodal pairs a | b << 16 (group indices)

@@ -201,7 +201,9 @@ int build_group_program(const HostProgram& full, int G, std::uint32_t* words, ch
     for (std::uint32_t k = 0; k < n_all; ++k) {
       const int u = (int)full.words[full.nV + off_all + k];
       if (local[u] >= 0) {
-        nbrs.push_back((std::uint32_t)local[u]);
+        // the neighbour's block id, with its lattice point and reflection
+        // parity (bits 0..7 of its record) in bits 16..23
+        nbrs.push_back((std::uint32_t)local[u] | ((full.words[u] & 0xFF) << 16));
         ++n;
       }
     }
