@@ -117,12 +117,14 @@ struct Cfg {
   //                           the lanes' entry rows start in distinct banks
   //   [PAR_BASE, +PAR_WORDS)  parent region of every region, one byte row
   //                           of the wave per region (phases 3-4)
-  // after phase 3 the entry words hold, per region: child mask (ADJ_W
-  // words) and code (CODE_W words).
+  // after phase 3 the entry words hold one slot of SLOT_W words per
+  // region: its child mask (ADJ_W words), replaced by its code (CODE_W
+  // words) once phase 4 has coded the region -- the mask is read only
+  // just before that, and a region's slot is read as a code only by its
+  // parent, which is coded later.
   static constexpr int E_WORDS = (((NV + 1) * EB + 3) / 4) | 1;
-  static constexpr int CHILD_BASE = 0;
-  static constexpr int CODE_BASE = RMAX * ADJ_W;
-  static constexpr int TAIL_WORDS = CODE_BASE + RMAX * CODE_W;
+  static constexpr int SLOT_W = ADJ_W > CODE_W ? ADJ_W : CODE_W;
+  static constexpr int TAIL_WORDS = RMAX * SLOT_W;
   static constexpr int LOW_WORDS = E_WORDS > TAIL_WORDS ? E_WORDS : TAIL_WORDS;
   static constexpr int PAR_BASE = LOW_WORDS;
   static constexpr int PAR_WORDS = (RMAX + 4) / 4;  // RMAX byte rows + a spare row
@@ -138,9 +140,10 @@ struct Cfg {
   static constexpr int SNAP_BYTES = (SNAP_WORDS * 4 + 15) / 16 * 16;
   static constexpr int WAVE_BYTES = LANE_WORDS * 4 * 64;
   // waves per block: as many waves per CU as the 160 KiB of LDS allows,
-  // in blocks of at most 4 waves
+  // in blocks of 4 waves, or of 2 where that keeps more of them resident
   static constexpr int WAVES_PER_CU = (160 * 1024) / WAVE_BYTES;
-  static constexpr int WAVES = WAVES_PER_CU >= 16 ? 4 : (WAVES_PER_CU >= 4 ? 2 : 1);
+  static constexpr int WAVES = WAVES_PER_CU >= 16 ? ((WAVES_PER_CU / 2) * 2 > (WAVES_PER_CU / 4) * 4 ? 2 : 4)
+                                                  : (WAVES_PER_CU >= 4 ? 2 : 1);
   // resident waves per SIMD when the LDS is full: the register budget the
   // kernels are compiled for (more registers would lower the occupancy
   // below what the LDS allows)
@@ -243,31 +246,31 @@ struct Eval {
   template <class LV>
   __device__ static __forceinline__ Adj load_adj(const LV& L, int x) {
     if constexpr (C::ADJ_W == 1) {
-      return L.word(C::CHILD_BASE + x);
+      return L.word(C::SLOT_W * x);
     } else {
-      return (uint64_t)L.word(C::CHILD_BASE + 2 * x) | ((uint64_t)L.word(C::CHILD_BASE + 2 * x + 1) << 32);
+      return (uint64_t)L.word(C::SLOT_W * x) | ((uint64_t)L.word(C::SLOT_W * x + 1) << 32);
     }
   }
   template <class LV>
   __device__ static __forceinline__ void store_adj(const LV& L, int x, Adj a) {
     if constexpr (C::ADJ_W == 1) {
-      L.word(C::CHILD_BASE + x) = a;
+      L.word(C::SLOT_W * x) = a;
     } else {
-      L.word(C::CHILD_BASE + 2 * x) = (uint32_t)a;
-      L.word(C::CHILD_BASE + 2 * x + 1) = (uint32_t)(a >> 32);
+      L.word(C::SLOT_W * x) = (uint32_t)a;
+      L.word(C::SLOT_W * x + 1) = (uint32_t)(a >> 32);
     }
   }
   template <class LV>
   __device__ static __forceinline__ Code load_code(const LV& L, int x) {
     constexpr int W = C::CODE_W;
     Code r = 0;
-    for (int k = W - 1; k >= 0; --k) r = (Code)(r << 32) | (Code)L.word(C::CODE_BASE + W * x + k);
+    for (int k = W - 1; k >= 0; --k) r = (Code)(r << 32) | (Code)L.word(C::SLOT_W * x + k);
     return r;
   }
   template <class LV>
   __device__ static __forceinline__ void store_code(const LV& L, int x, Code c) {
     constexpr int W = C::CODE_W;
-    for (int k = 0; k < W; ++k) L.word(C::CODE_BASE + W * x + k) = (uint32_t)(c >> (32 * k));
+    for (int k = 0; k < W; ++k) L.word(C::SLOT_W * x + k) = (uint32_t)(c >> (32 * k));
   }
 
   // root of u and u's parity relative to it (parity: even d only)
