@@ -148,6 +148,7 @@ std::string jit_source(const HostProgram& P) {
   o << "  __device__ __forceinline__ u128 operator()(Cfg<" << d
     << ">::Mask m, const Lane& L, uint32_t& errs) const {\n";
   o << "    using E = Eval<" << d << ">;\n";
+  o << "    E::clear_side(L);\n";
   o << "    // phase 1: components of same-sign vertices; r<u> = a root u had\n";
   for (int v = 0; v < nV; ++v) {
     const uint32_t rec = P.words[v];
@@ -323,6 +324,7 @@ std::string jit_source(const HostProgram& P) {
     o << "    {\n      const uint32_t* s = reinterpret_cast<const uint32_t*>(__builtin_assume_aligned(snap, 16));\n"
          "#pragma unroll\n      for (int k = 0; k < Cfg<"
       << d << ">::SNAP_WORDS; ++k) {\n        L.eword(k) = s[k];\n        if (k % 8 == 7) PW_FENCE();\n      }\n    }\n";
+    o << "    E::clear_side(L);\n";
     o << "    const E::Ent* srow = reinterpret_cast<const E::Ent*>(snap);\n";
     o << "    // phase 1 for the varying vertices (in index order; each with all\n"
          "    // its fixed-sign neighbours and its earlier varying ones; duplicate\n"

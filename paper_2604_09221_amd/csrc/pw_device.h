@@ -100,15 +100,19 @@ struct Cfg {
   // codes of at most RMAX - 1 nodes below the root: 2 (RMAX - 1) bits
   using Code = typename cond<(2 * (RMAX - 1) + 2 <= 64), uint64_t, u128>::type;
   static constexpr int ADJ_W = sizeof(Adj) / 4;
-  // vertex entries: u8 where 7 bits index every vertex and the spare
-  // entry (odd d <= 7, even d <= 6): the parent index in bits 0-6 and, for
-  // even d, bit 7 = the parity to the parent at a non-root and the
-  // odd-cycle flag at a root (a root has no parent, so the bit is free);
-  // u16 otherwise (parent index in bits 0-8, parity to the parent bit 9,
-  // odd-cycle flag bit 10)
+  // vertex entries: u8 where 8 bits index every vertex and the spare
+  // entry (d <= 10: BYTE), u16 otherwise (parent index in bits 0-8, for
+  // even d the parity to the parent in bit 9 and the odd-cycle flag in
+  // bit 10).  Odd d keeps nothing but the index.  Even d with 7-bit
+  // indices (d <= 6: NARROW) keeps in bit 7 the parity to the parent at a
+  // non-root and the odd-cycle flag at a root (a root has no parent, so
+  // the bit is free); even d = 8, 10 (SIDE) keeps that bit in a side
+  // bitset of the lane instead (bit v of word SIDE_BASE + v / 32).
+  static constexpr bool BYTE = NV + 1 <= 256;
   static constexpr bool NARROW = NV + 1 <= 128;
-  using Ent = typename cond<NARROW, uint8_t, uint16_t>::type;
-  static constexpr int EB = NARROW ? 1 : 2;
+  static constexpr bool SIDE = EVEN && BYTE && !NARROW;
+  using Ent = typename cond<BYTE, uint8_t, uint16_t>::type;
+  static constexpr int EB = BYTE ? 1 : 2;
   // a stored region code has 2 * (subtree size) <= 2 * (RMAX - 1) bits
   static constexpr int CODE_W = 2 * (RMAX - 1) <= 32 ? 1 : (int)(sizeof(Code) / 4);
   // per-lane LDS words:
@@ -123,9 +127,11 @@ struct Cfg {
   // just before that, and a region's slot is read as a code only by its
   // parent, which is coded later.
   static constexpr int E_WORDS = (((NV + 1) * EB + 3) / 4) | 1;
+  static constexpr int SIDE_BASE = E_WORDS;
+  static constexpr int SIDE_WORDS = SIDE ? (NV + 1 + 31) / 32 : 0;
   static constexpr int SLOT_W = ADJ_W > CODE_W ? ADJ_W : CODE_W;
   static constexpr int TAIL_WORDS = RMAX * SLOT_W;
-  static constexpr int LOW_WORDS = E_WORDS > TAIL_WORDS ? E_WORDS : TAIL_WORDS;
+  static constexpr int LOW_WORDS = E_WORDS + SIDE_WORDS > TAIL_WORDS ? E_WORDS + SIDE_WORDS : TAIL_WORDS;
   static constexpr int PAR_BASE = LOW_WORDS;
   static constexpr int PAR_WORDS = (RMAX + 4) / 4;  // RMAX byte rows + a spare row
   static constexpr int LANE_WORDS = LOW_WORDS + PAR_WORDS;
@@ -141,6 +147,8 @@ struct Cfg {
   static constexpr int WAVE_BYTES = LANE_WORDS * 4 * 64;
   // waves per block: as many waves per CU as the 160 KiB of LDS allows,
   // in blocks of 4 waves, or of 2 where that keeps more of them resident
+  // (blocks of one wave measured slower: d = 6, 23 instead of 22 resident
+  // waves, 15% slower)
   static constexpr int WAVES_PER_CU = (160 * 1024) / WAVE_BYTES;
   static constexpr int WAVES = WAVES_PER_CU >= 16 ? ((WAVES_PER_CU / 2) * 2 > (WAVES_PER_CU / 4) * 4 ? 2 : 4)
                                                   : (WAVES_PER_CU >= 4 ? 2 : 1);
@@ -214,7 +222,7 @@ struct Eval {
   using Adj = typename C::Adj;
   using Code = typename C::Code;
   using Ent = typename C::Ent;
-  static constexpr uint32_t kIdx = C::NARROW ? 0x7Fu : 0x1FFu;  // index field of an entry
+  static constexpr uint32_t kIdx = C::NARROW ? 0x7Fu : (C::BYTE ? 0xFFu : 0x1FFu);  // index field of an entry
   // even d: parity to the parent (non-root) and odd-cycle flag (root); one
   // bit in u8 entries, whose meaning the root test decides
   static constexpr uint32_t kParity = C::NARROW ? 0x80u : 0x200u;
@@ -222,7 +230,32 @@ struct Eval {
   __device__ static __forceinline__ Adj one(int x) { return (Adj)1 << x; }
 
   // parent index in an entry (u8 entries of odd d hold nothing else)
-  __device__ static __forceinline__ uint32_t idx(uint32_t e) { return (C::NARROW && !C::EVEN) ? e : (e & kIdx); }
+  __device__ static __forceinline__ uint32_t idx(uint32_t e) {
+    return (C::BYTE && !(C::EVEN && C::NARROW)) ? e : (e & kIdx);
+  }
+
+  // ---- the side bitset (SIDE): parity to the parent at a non-root,
+  // odd-cycle flag at a root
+  __device__ static __forceinline__ uint32_t side_bit(const Lane& L, uint32_t v) {
+    return (L.word(C::SIDE_BASE + (int)(v >> 5)) >> (v & 31u)) & 1u;
+  }
+  __device__ static __forceinline__ void set_side(const Lane& L, uint32_t v, uint32_t b) {
+    uint32_t& w = L.word(C::SIDE_BASE + (int)(v >> 5));
+    w = (w & ~(1u << (v & 31u))) | (b << (v & 31u));
+  }
+  // start of an evaluation: no parity or odd-cycle bit set
+  __device__ static __forceinline__ void clear_side(const Lane& L) {
+    if constexpr (C::SIDE)
+      for (int k = 0; k < C::SIDE_WORDS; ++k) L.word(C::SIDE_BASE + k) = 0;
+  }
+  // odd-cycle flag of root r whose entry is er
+  __device__ static __forceinline__ bool odd_flag(const Lane& L, uint32_t r, uint32_t er) {
+    if constexpr (C::SIDE) {
+      return side_bit(L, r) != 0;
+    } else {
+      return (er & kOdd) != 0;
+    }
+  }
 
   __device__ static __forceinline__ uint32_t bit(Mask m, int p) { return (uint32_t)(m >> p) & 1u; }
 
@@ -279,7 +312,11 @@ struct Eval {
     er = ent(L, u);
     par = 0;
     while (idx(er) != r) {
-      if (C::EVEN) par ^= (er & kParity) ? 1u : 0u;
+      if constexpr (C::SIDE) {
+        par ^= side_bit(L, r);
+      } else if constexpr (C::EVEN) {
+        par ^= (er & kParity) ? 1u : 0u;
+      }
       r = idx(er);
       er = ent(L, (int)r);
     }
@@ -372,7 +409,17 @@ struct Eval {
     uint32_t ea, eb, pa, pb;
     const uint32_t ra = find_parity(L, a, ea, pa);
     const uint32_t rb = find_parity(L, b, eb, pb);
-    if (ra == rb) {
+    if constexpr (C::SIDE) {
+      if (ra == rb) {
+        if (pa == pb) set_side(L, ra, 1u);
+      } else {
+        const uint32_t lo = ra < rb ? ra : rb, hi = ra < rb ? rb : ra;
+        const uint32_t odd_hi = side_bit(L, hi);  // hi's bit: its odd-cycle flag, then its parity
+        ent(L, (int)hi) = (Ent)lo;
+        set_side(L, hi, pa ^ pb ^ 1u);
+        if (odd_hi) set_side(L, lo, 1u);
+      }
+    } else if (ra == rb) {
       if (C::EVEN && pa == pb) ent(L, (int)ra) = (Ent)(ea | kOdd);
     } else {
       const bool a_lo = ra < rb;
@@ -420,7 +467,7 @@ struct Eval {
     // keep the running count a plain running count (re-associating the
     // chain of increments would hold every vertex's flag in a register)
     PW_OPAQUE(nR);
-    const bool hit = C::EVEN ? (is_root && (ev & kOdd)) : (t >= 0 && st != sv && (int)et == cid);
+    const bool hit = C::EVEN ? (is_root && odd_flag(L, (uint32_t)v, ev)) : (t >= 0 && st != sv && (int)et == cid);
     roots |= hit ? one(cid & (8 * (int)sizeof(Adj) - 1)) : (Adj)0;
     const uint32_t pc = t >= 0 ? et : 0xFFu;
     int slot = is_root ? cid : C::RMAX;
@@ -444,7 +491,7 @@ struct Eval {
     // keep the running count a plain running count (re-associating the
     // chain of increments would hold every vertex's flag in a register)
     PW_OPAQUE(nR);
-    const bool hit = C::EVEN ? (is_root && (ev & kOdd)) : (crossed && (int)et == cid);
+    const bool hit = C::EVEN ? (is_root && odd_flag(L, (uint32_t)v, ev)) : (crossed && (int)et == cid);
     roots |= hit ? one(cid & (8 * (int)sizeof(Adj) - 1)) : (Adj)0;
     // (a plain running value: between branches the compiler would
     // otherwise keep every vertex's term until the end)
@@ -473,6 +520,7 @@ struct Eval {
   __device__ static u128 run(const uint32_t* __restrict__ prog, Mask m, const Lane& L, uint32_t& errs) {
     const uint32_t* nbr = prog + C::NV;
     const uint32_t* pairs = prog + C::NV + C::NE;
+    clear_side(L);
     // phase 1: components of same-sign vertices
     for (int v = 0; v < C::NV; ++v) {
       const uint32_t rec = prog[v];
