@@ -46,28 +46,39 @@ def lookup_multi(degrees):
     return tuple(entry["config"])
 
 
-def tune_multi(tris, masks128, offsets, hists=None, repeats=2, save=True, log=print):
-    """Time candidate shapes on this workload; cache and return the fastest
-    (chunk, waves_per_block, blocks_per_cu, lane_groups)."""
+def call_timer(tris, masks128, offsets, hists=None):
+    """ms of one patchwork_scheme_batch_multi call with a given shape (HIP
+    events around the call on the current stream)."""
     import torch
 
     from . import patchwork as pw
 
+    def run(cfg):
+        if hists is not None:
+            for h in hists:
+                h.reset()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        pw.batch_multi(tris, masks128, offsets, hists=hists, config=cfg)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)
+
+    return run
+
+
+def tune_multi(tris, masks128, offsets, hists=None, repeats=2, save=True, log=print, timer=None):
+    """Time candidate shapes on this workload; cache and return the fastest
+    (chunk, waves_per_block, blocks_per_cu, lane_groups).  timer(cfg) -> ms
+    (default: call_timer on this workload)."""
+    from . import patchwork as pw
+
+    run = timer or call_timer(tris, masks128, offsets, hists)
+
     def timed(cfg):
-        best = None
-        for _ in range(repeats):
-            if hists is not None:
-                for h in hists:
-                    h.reset()
-            torch.cuda.synchronize()
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record()
-            pw.batch_multi(tris, masks128, offsets, hists=hists, config=cfg)
-            b.record()
-            torch.cuda.synchronize()
-            ms = a.elapsed_time(b)
-            best = ms if best is None else min(best, ms)
+        best = min(run(cfg) for _ in range(repeats))
         if log:
             log(f"tune multi {cfg}: {best:.3f} ms")
         return best
@@ -84,9 +95,7 @@ def tune_multi(tris, masks128, offsets, hists=None, repeats=2, save=True, log=pr
     groups = {d: pw.lane_groups_of(best_cfg[3]).get(d, 1) for d in LANE_GROUP_DEGREES}
     present = sorted({int(t.d) for t in tris} & set(LANE_GROUP_DEGREES))
     for d in present:
-        for g in LANE_GROUPS:
-            if g == groups[d]:
-                continue
+        for g in [x for x in LANE_GROUPS if x != groups[d]]:
             trial = {**groups, d: g}
             cfg = (*best_cfg[:3], pw.lane_groups_code(trial))
             ms = timed(cfg)

@@ -66,3 +66,33 @@ def test_fig2_check_whole_sweep(tmp_path):
     gap = bench.fig2_check([_part(tmp_path, "c.json", 0, (1 << 41) - 512, h),
                             _part(tmp_path, "d.json", 1 << 41, 1 << 41, h)])
     assert not gap["whole_sweep"]
+
+
+def test_tuner_descends_over_lanes_per_mask(tmp_path, monkeypatch):
+    """The autotuner's search, with a synthetic cost model in place of the
+    GPU timer: it times every (chunk, waves, blocks) shape, then changes the
+    lanes per mask of one degree at a time, keeps what is faster and caches
+    the result per degree mix."""
+    from paper_2604_09221_amd import patchwork as pw
+    from paper_2604_09221_amd import tune
+
+    monkeypatch.setattr(tune, "CACHE", str(tmp_path / "tune.json"))
+    best_groups = {8: 2, 9: 4, 10: 4, 11: 4, 12: 1}
+
+    def cost(cfg):
+        chunk, waves, bpc, code = cfg
+        g = pw.lane_groups_of(code)
+        ms = 100.0 + (0 if chunk == 2048 else 5) + (0 if waves == 2 else 3) + (0 if bpc == 0 else 2)
+        return ms + sum(10.0 for d in range(8, 13) if g.get(d, 1) != best_groups[d])
+
+    class T:
+        def __init__(self, d):
+            self.d = d
+
+    tris = [T(d) for d in (4, 7, 8, 9, 10, 11, 12)]
+    calls = []
+    cfg = tune.tune_multi(tris, None, None, repeats=1, log=None, timer=lambda c: calls.append(c) or cost(c))
+    assert cfg[:3] == (2048, 2, 0)
+    assert pw.lane_groups_of(cfg[3]) == {d: g for d, g in best_groups.items() if g > 1}
+    assert len(calls) == len(tune.CHUNKS) * len(tune.WAVES) * len(tune.BLOCKS_PER_CU) + 5 * 2
+    assert tune.lookup_multi([t.d for t in tris]) == tuple(cfg)
