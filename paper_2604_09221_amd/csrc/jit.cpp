@@ -335,12 +335,16 @@ std::string jit_source(const HostProgram& P) {
       o << "    uint32_t r" << v << " = " << v << "u; { const uint32_t sv = " << sign_expr(P, v) << ";";
       std::vector<int> nb = adj[v];
       std::sort(nb.begin(), nb.end());
+      // the fixed-sign neighbours' snapshot roots (wave-uniform), all read
+      // before the first union so that their loads overlap
+      for (int u : nb)
+        if (!vary[u]) o << " const uint32_t s" << u << " = srow[" << u << "];";
       for (int u : nb) {
         if (vary[u] && u > v) continue;
         if (vary[u]) {
           o << " E::edge_v(L, sv, " << sign_expr(P, u) << ", " << v << ", r" << v << ", r" << u << ");";
         } else {
-          const std::string step = "{ uint32_t t = srow[" + std::to_string(u) + "]; E::edge_v(L, sv, " +
+          const std::string step = "{ uint32_t t = s" + std::to_string(u) + "; E::edge_v(L, sv, " +
                                    sign_expr(P, u) + ", " + std::to_string(v) + ", r" + std::to_string(v) + ", t); }";
           if (earlier_fixed[fe].empty())
             o << " " << step;
