@@ -78,7 +78,7 @@ __device__ __forceinline__ void run_item(const TriDesc& t, const Item& w, const 
       }
     }
     uint32_t e = 0;
-    const u128 code = Eval<D, RC>::run(t.prog, m, L, e);
+    const u128 code = Eval<D, RC>::run(const_prog(t.prog), m, L, e);
     if (C::CAPPED && (e & kErrOverflow) && valid) {
       const unsigned long long slot = atomicAdd(ov.n, 1ull);
       if (slot < ov.cap) {
@@ -143,7 +143,7 @@ __device__ __forceinline__ void run_item_g(const TriDesc& t, const Item& w, cons
   const typename GE::Mem M = GE::memory(wave, lane);
   const int q = lane % G, g = lane / G;
   const typename C::Mask fl = GE::flip(q);
-  const uint32_t* prog = t.gprog[G == 4 ? 1 : 0];
+  const prog_ptr prog = const_prog(t.gprog[G == 4 ? 1 : 0]);
   uint32_t errs = 0;
   WaveTable tab;
   tab.clear();
@@ -227,7 +227,7 @@ __device__ __forceinline__ void run_big(const TriDesc& t, int64_t i, const uint6
     m = ((u128)masks[2 * i + 1] << 64) | (u128)masks[2 * i];
   }
   uint32_t e = 0;
-  const u128 code = Eval<D>::run(t.prog, m, L, e);
+  const u128 code = Eval<D>::run(const_prog(t.prog), m, L, e);
   if (e) atomicOr(t.err, e);
   if (codes) store_code(codes, i, code);
   // (the descriptor differs between lanes here: a plain vector load)

@@ -71,6 +71,18 @@ namespace pw {
 
 typedef unsigned __int128 u128;
 
+// A triangulation's program as the kernels read it.  The batched kernels
+// take its address from a descriptor in memory, so the compiler cannot
+// tell its address space and would read it with vector loads; in the
+// constant address space (read-only during a kernel) its wave-uniform
+// words are read through the scalar cache.
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef const __attribute__((address_space(4))) uint32_t* prog_ptr;
+#else
+typedef const uint32_t* prog_ptr;
+#endif
+__device__ __forceinline__ prog_ptr const_prog(const uint32_t* p) { return (prog_ptr)p; }
+
 template <bool B, class X, class Y>
 struct cond {
   using type = X;
@@ -512,14 +524,16 @@ struct Eval {
     PW_OPAQUE(roots);
   }
 
-  __device__ static __forceinline__ uint32_t sign_of(const uint32_t* __restrict__ prog, Mask m, int v) {
+  template <class P>
+  __device__ static __forceinline__ uint32_t sign_of(P prog, Mask m, int v) {
     const uint32_t rec = prog[v];
     return bit(m, rec & 0x7F) ^ ((rec >> 7) & 1u);
   }
 
-  __device__ static u128 run(const uint32_t* __restrict__ prog, Mask m, const Lane& L, uint32_t& errs) {
-    const uint32_t* nbr = prog + C::NV;
-    const uint32_t* pairs = prog + C::NV + C::NE;
+  template <class P>
+  __device__ static u128 run(P prog, Mask m, const Lane& L, uint32_t& errs) {
+    const P nbr = prog + C::NV;
+    const P pairs = prog + C::NV + C::NE;
     clear_side(L);
     // phase 1: components of same-sign vertices
     for (int v = 0; v < C::NV; ++v) {

@@ -123,7 +123,8 @@ struct GroupEval {
   }
 
   __device__ __forceinline__ static uint32_t bit(Mask m, int p) { return (uint32_t)(m >> p) & 1u; }
-  __device__ __forceinline__ static uint32_t sign(const uint32_t* __restrict__ prog, Mask m, int v) {
+  template <class P>
+  __device__ __forceinline__ static uint32_t sign(P prog, Mask m, int v) {
     const uint32_t rec = prog[v];
     return bit(m, rec & 0x7F) ^ ((rec >> 7) & 1u);
   }
@@ -142,8 +143,9 @@ struct GroupEval {
   // Phase 1 on the lane's own block; m is the lane's flipped mask.  As the
   // one-lane evaluator: a lane whose signs differ stores into v's own
   // entry, which is scratch until v is closed.
-  __device__ static void phase1(const uint32_t* __restrict__ prog, Mask m, const Mem& M, int q) {
-    const uint32_t* nbr = prog + GC::NB;
+  template <class P>
+  __device__ static void phase1(P prog, Mask m, const Mem& M, int q) {
+    const P nbr = prog + GC::NB;
     for (int v = 0; v < GC::NB; ++v) {
       const uint32_t rec = prog[v];
       const uint32_t sv = bit(m, rec & 0x7F) ^ ((rec >> 7) & 1u);
@@ -181,9 +183,10 @@ struct GroupEval {
 
   // Phase 2: glues, then the antipodal pairs (the same steps in every lane
   // of the group).
-  __device__ static void phase2(const uint32_t* __restrict__ prog, const Mem& M) {
-    const uint32_t* glue = prog + GC::NB + GC::NEB;
-    const uint32_t* pairs = glue + GC::NGL;
+  template <class P>
+  __device__ static void phase2(P prog, const Mem& M) {
+    const P glue = prog + GC::NB + GC::NEB;
+    const P pairs = glue + GC::NGL;
     for (int k = 0; k < GC::NGL; ++k) {
       const uint32_t ra = root(M, glue[k] & 0xFFFF), rb = root(M, glue[k] >> 16);
       const uint32_t lo = ra < rb ? ra : rb, hi = ra < rb ? rb : ra;
@@ -244,7 +247,8 @@ struct GroupEval {
   }
   // ... second half: the region tree edge of a root, the root region
   // marks.  cid: v's id if v is a root (capped at RMAX).
-  __device__ __forceinline__ static void p3_link(const uint32_t* __restrict__ prog, Mask m, const Mem& M, int v, int q,
+  template <class P>
+  __device__ __forceinline__ static void p3_link(P prog, Mask m, const Mem& M, int v, int q,
                                                  bool is_root, uint32_t ev, int cid, Adj& roots) {
     const uint32_t rec = prog[v];
     const int sx = G == 4 ? (q & 1) : 0, sy = G == 4 ? (q >> 1) : q;
@@ -281,7 +285,8 @@ struct GroupEval {
 
   // The whole evaluation; m is the lane's flipped mask.  Every lane of the
   // group returns the same code and error flags.
-  __device__ static u128 run(const uint32_t* __restrict__ prog, Mask m, const Mem& M, int lane, int q,
+  template <class P>
+  __device__ static u128 run(P prog, Mask m, const Mem& M, int lane, int q,
                              uint32_t& errs) {
     phase1(prog, m, M, q);
     PW_FENCE();
