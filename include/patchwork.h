@@ -312,8 +312,8 @@ typedef struct {
   uint32_t lane_groups;
 } pw_multi_config;
 
-/* Lane groups used when cfg is NULL: four lanes per mask for degrees 9..12. */
-#define PW_MULTI_DEFAULT_LANE_GROUPS ((2u << 18) | (2u << 20) | (2u << 22) | (2u << 24))
+/* Lane groups used when cfg is NULL: four lanes per mask for degrees 11 and 12. */
+#define PW_MULTI_DEFAULT_LANE_GROUPS ((2u << 22) | (2u << 24))
 
 pw_status patchwork_scheme_batch_multi(const pw_tri_t *tris, int32_t n_tris, const void *d_masks,
                                        const int64_t *offsets, const pw_hist_t *hists, uint64_t *d_codes,

@@ -48,8 +48,8 @@ def lane_groups_of(code: int) -> dict:
 
 
 # the library's lane groups when no configuration is passed
-# (PW_MULTI_DEFAULT_LANE_GROUPS: four lanes per mask for degrees 9..12)
-DEFAULT_LANE_GROUPS = lane_groups_code({9: 4, 10: 4, 11: 4, 12: 4})
+# (PW_MULTI_DEFAULT_LANE_GROUPS: four lanes per mask for degrees 11 and 12)
+DEFAULT_LANE_GROUPS = lane_groups_code({11: 4, 12: 4})
 
 
 class PatchworkError(RuntimeError):
