@@ -1,7 +1,8 @@
 // scheme.hip -- single-triangulation kernels and their C-ABI entry points:
 // codes of a mask batch, histogram of a mask batch, histogram of an
-// enumerated index range.  One sign mask per lane; the evaluation itself is
-// Eval<D>::run in pw_device.h.
+// enumerated index range.  One sign mask per lane (the evaluation itself is
+// Eval<D>::run in pw_device.h), or for degrees 10..12 a group of four lanes
+// per mask (GroupEval in pw_group.h).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -15,6 +16,7 @@
 
 #include "patchwork.h"
 #include "pw_device.h"
+#include "pw_group.h"
 #include "pw_host.h"
 
 namespace pw {
@@ -44,6 +46,100 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Cfg<D>::WAV
                                               Runs runs, const HistDev* __restrict__ h, uint32_t* __restrict__ errflag) {
   extern __shared__ uint32_t smem[];
   enum_body<D>(RtEval<D>{prog}, first, count, runs, h, errflag, smem);
+}
+
+// Degrees 10..12 have no kernels specialised to one triangulation, and one
+// lane per mask holds a u16 entry row of up to 313 vertices plus the full
+// phase-4 tables: 2-3 waves per CU.  There the kernels for one
+// triangulation take a group of four lanes per mask (pw_group.h, one
+// reflected quadrant per lane, full tables): 10-15 waves per CU.
+constexpr int kSingleGroup = 4;
+constexpr int kSingleGroupWaves = 2;  // waves per block
+
+template <int D>
+__global__ __launch_bounds__(64 * kSingleGroupWaves) void k_codes_g(const uint32_t* __restrict__ gprog,
+                                                                    const void* __restrict__ masks, int64_t n,
+                                                                    uint64_t* __restrict__ codes,
+                                                                    uint32_t* __restrict__ errflag) {
+  extern __shared__ uint32_t smem[];
+  using GE = GroupEval<D, kSingleGroup>;
+  using Mask = typename GE::Mask;
+  constexpr int NG = GE::GC::NG;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const typename GE::Mem M = GE::memory(smem + wave * GE::GC::WAVE_DW, lane);
+  const int q = lane % kSingleGroup, g = lane / kSingleGroup;
+  const Mask fl = GE::flip(q);
+  uint32_t errs = 0;
+  const int64_t waves_total = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t base = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * NG; base < n; base += waves_total * NG) {
+    const int64_t i = base + g;
+    const bool valid = i < n;
+    const Mask m = valid ? load_mask<D>(masks, i) : (Mask)0;
+    const u128 code = GE::run(const_prog(gprog), m ^ fl, M, lane, q, errs);
+    if (valid && q == 0) store_code(codes, i, code);
+  }
+  if (errs) atomicOr(errflag, errs);
+}
+
+template <int D>
+__global__ __launch_bounds__(64 * kSingleGroupWaves) void k_hist_g(const uint32_t* __restrict__ gprog,
+                                                                   const void* __restrict__ masks, int64_t n,
+                                                                   uint64_t index_base, const HistDev* __restrict__ h,
+                                                                   uint64_t* __restrict__ codes,
+                                                                   uint32_t* __restrict__ errflag) {
+  extern __shared__ uint32_t smem[];
+  using GE = GroupEval<D, kSingleGroup>;
+  using Mask = typename GE::Mask;
+  constexpr int NG = GE::GC::NG;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const typename GE::Mem M = GE::memory(smem + wave * GE::GC::WAVE_DW, lane);
+  const int q = lane % kSingleGroup, g = lane / kSingleGroup;
+  const Mask fl = GE::flip(q);
+  WaveTable tab;
+  tab.clear();
+  uint32_t errs = 0;
+  const int64_t waves_total = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t base = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * NG; base < n; base += waves_total * NG) {
+    const int64_t i = base + g;
+    const bool valid = i < n && q == 0;
+    const Mask m = i < n ? load_mask<D>(masks, i) : (Mask)0;
+    const u128 code = GE::run(const_prog(gprog), m ^ fl, M, lane, q, errs);
+    if (codes && valid) store_code(codes, i, code);
+    // (the counted lanes hold increasing indices: the lowest lane of a
+    // match has the smallest witness)
+    tab.add_batch((uint64_t)code, (uint64_t)(code >> 64), valid, index_base + (uint64_t)i, lane, h);
+  }
+  tab.flush(h);
+  if (errs) atomicOr(errflag, errs);
+}
+
+template <int D>
+__global__ __launch_bounds__(64 * kSingleGroupWaves) void k_enum_g(const uint32_t* __restrict__ gprog, uint64_t first,
+                                                                   uint64_t count, Runs runs,
+                                                                   const HistDev* __restrict__ h,
+                                                                   uint32_t* __restrict__ errflag) {
+  extern __shared__ uint32_t smem[];
+  using GE = GroupEval<D, kSingleGroup>;
+  using Mask = typename GE::Mask;
+  constexpr int NG = GE::GC::NG;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const typename GE::Mem M = GE::memory(smem + wave * GE::GC::WAVE_DW, lane);
+  const int q = lane % kSingleGroup, g = lane / kSingleGroup;
+  const Mask fl = GE::flip(q);
+  WaveTable tab;
+  tab.clear();
+  uint32_t errs = 0;
+  const uint64_t waves_total = (uint64_t)gridDim.x * (blockDim.x >> 6);
+  for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + wave) * NG; base < count;
+       base += waves_total * NG) {
+    const uint64_t k = base + (uint64_t)g;
+    const bool valid = k < count && q == 0;
+    const uint64_t idx = first + k;
+    const u128 code = GE::run(const_prog(gprog), deposit<Mask>(idx, runs) ^ fl, M, lane, q, errs);
+    tab.add_batch((uint64_t)code, (uint64_t)(code >> 64), valid, idx, lane, h);
+  }
+  tab.flush(h);
+  if (errs) atomicOr(errflag, errs);
 }
 
 }  // namespace pw
@@ -101,8 +197,34 @@ hipError_t allow_lds(const void* kernel) {
   return e;
 }
 
+// the group kernels of degrees 10..12: LDS per block, blocks for n units
+template <int D>
+size_t group_lds() {
+  return (size_t)GCfg<D, kSingleGroup>::WAVE_DW * 4 * kSingleGroupWaves;
+}
+template <int D>
+int group_blocks(int64_t units_per_block, int64_t n) {
+  const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(8, (160 * 1024) / (int64_t)group_lds<D>()));
+  const int64_t need = (n + units_per_block - 1) / units_per_block;
+  return (int)std::max<int64_t>(1, std::min(need, (int64_t)cu_count() * per_cu));
+}
+inline hipError_t allow_group_lds(const void* kernel) {
+  const hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (e != hipSuccess) (void)hipGetLastError();
+  return e;
+}
+constexpr int kGroupMasksPerBlock = 64 / kSingleGroup * kSingleGroupWaves;
+
 template <int D>
 pw_status launch_codes(const pw_tri* t, const void* masks, int64_t n, uint64_t* codes, hipStream_t s) {
+  if constexpr (D >= 10) {
+    static const hipError_t attr = allow_group_lds(reinterpret_cast<const void*>(&k_codes_g<D>));
+    if (attr != hipSuccess) return set_err(PW_ERR_HIP, "hipFuncSetAttribute: %s (code %d)", hipGetErrorString(attr), (int)attr);
+    hipLaunchKernelGGL(k_codes_g<D>, dim3(group_blocks<D>(kGroupMasksPerBlock, n)), dim3(64 * kSingleGroupWaves),
+                       group_lds<D>(), s, t->d_gprog[1], masks, n, codes, t->d_err);
+    PW_HIP(hipGetLastError());
+    return PW_OK;
+  }
   using C = Cfg<D>;
   const int threads = 64 * C::WAVES;
   const size_t lds = (size_t)C::DYN_WORDS * 4 * 64 * C::WAVES;  // + the static parent table
@@ -126,6 +248,14 @@ pw_status launch_codes(const pw_tri* t, const void* masks, int64_t n, uint64_t* 
 template <int D>
 pw_status launch_hist(const pw_tri* t, const void* masks, int64_t n, uint64_t base, const pw_hist* h,
                       uint64_t* codes, hipStream_t s) {
+  if constexpr (D >= 10) {
+    static const hipError_t attr = allow_group_lds(reinterpret_cast<const void*>(&k_hist_g<D>));
+    if (attr != hipSuccess) return set_err(PW_ERR_HIP, "hipFuncSetAttribute: %s (code %d)", hipGetErrorString(attr), (int)attr);
+    hipLaunchKernelGGL(k_hist_g<D>, dim3(group_blocks<D>(kGroupMasksPerBlock, n)), dim3(64 * kSingleGroupWaves),
+                       group_lds<D>(), s, t->d_gprog[1], masks, n, base, h->d_dev, codes, t->d_err);
+    PW_HIP(hipGetLastError());
+    return PW_OK;
+  }
   using C = Cfg<D>;
   const int threads = 64 * C::WAVES;
   const size_t lds = (size_t)C::DYN_WORDS * 4 * 64 * C::WAVES;  // + the static parent table
@@ -150,6 +280,15 @@ pw_status launch_hist(const pw_tri* t, const void* masks, int64_t n, uint64_t ba
 template <int D>
 pw_status launch_enum(const pw_tri* t, uint64_t first, uint64_t count, const Runs& runs, const pw_hist* h,
                       hipStream_t s) {
+  if constexpr (D >= 10) {
+    static const hipError_t attr = allow_group_lds(reinterpret_cast<const void*>(&k_enum_g<D>));
+    if (attr != hipSuccess) return set_err(PW_ERR_HIP, "hipFuncSetAttribute: %s (code %d)", hipGetErrorString(attr), (int)attr);
+    const int64_t n = count > (uint64_t)INT64_MAX ? INT64_MAX : (int64_t)count;
+    hipLaunchKernelGGL(k_enum_g<D>, dim3(group_blocks<D>(kGroupMasksPerBlock, n)), dim3(64 * kSingleGroupWaves),
+                       group_lds<D>(), s, t->d_gprog[1], first, count, runs, h->d_dev, t->d_err);
+    PW_HIP(hipGetLastError());
+    return PW_OK;
+  }
   using C = Cfg<D>;
   const int threads = 64 * C::WAVES;
   const size_t lds = (size_t)C::DYN_WORDS * 4 * 64 * C::WAVES;  // + the static parent table

@@ -209,6 +209,38 @@ def test_wide_masks_and_large_degrees(pw, d):
     assert np.array_equal(gpu_codes(pw, d, E, masks), oracle.scheme_many(d, E, masks))
 
 
+@pytest.mark.parametrize("d", [10, 11, 12])
+def test_large_degrees_histogram_and_enumeration(pw, d):
+    """Degrees 10..12 evaluate one mask with a group of four lanes (one
+    reflected quadrant each): histograms with an index base, the fused
+    codes + histogram call and enumerated index ranges, bit-exact (codes,
+    counts and witnesses) against the oracle."""
+    E = I.lift_triangulation(d, 3, noise=1.0)
+    tri = pw.Triangulation(d, E)
+    nA = I.n_points(d)
+    masks = I.random_masks(d, 70 + d, 5003)
+    h = I.harnack_mask(d)
+    flips = [h] + [h ^ (1 << b) for b in range(1, nA, 5)]       # many regions (the full phase-4 tables)
+    for k, x in enumerate(flips):
+        masks[k, 0], masks[k, 1] = x & (2**64 - 1), x >> 64
+    want = oracle.scheme_many(d, E, masks, threads=THREADS)
+    mt = pw.mask_tensor(masks, d)
+    hist = pw.Histogram(8192)
+    tri.histogram(mt, hist, index_base=1000)
+    assert hist.read() == oracle_hist(want, index_of=np.arange(1000, 1000 + len(masks), dtype=np.uint64))
+    hist2 = pw.Histogram(8192)
+    codes = torch.zeros((len(masks), 2), dtype=torch.int64, device="cuda")
+    tri.codes_histogram(mt, hist2, codes)
+    assert np.array_equal(codes.cpu().numpy().view(np.uint64), want)
+    assert hist2.read() == oracle_hist(want)
+    for first, n in [(0, 4099), ((1 << 40) + 12345, 3001), ((1 << 64) - 2000, 1999)]:
+        he = pw.Histogram(8192)
+        tri.enumerate_range(first, n, he)
+        wm = oracle.scheme_many(d, E, enum_masks(first, n, fixed=1, nA=nA), threads=THREADS)
+        assert he.read() == oracle_hist(wm, index_of=np.arange(first, first + n, dtype=np.uint64))
+    assert tri.errors() == 0
+
+
 # -------------------------------------------------------------- edge cases
 
 def test_edge_cases(pw):
