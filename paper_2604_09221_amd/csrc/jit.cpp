@@ -55,16 +55,16 @@ int lattice_bit(const HostProgram& P, int v) { return (int)(P.words[v] & 0x7F); 
 constexpr int kAhead = 4;  // phase 3 reads entries this many vertices ahead
 
 // phases 2 and 3 and the call of phase 4, common to both evaluators
-// skip_pair(t): the pair is already merged (the sweep kernel's snapshot);
-// vary: the sweep kernel's varying vertices (null for the plain evaluator).
-template <class Skip>
-void emit_tail(std::ostringstream& o, const HostProgram& P, Skip skip_pair, const std::vector<char>* vary) {
-  const int nV = P.nV, nE = P.nE, nP = P.nP;
+// pair_stmt(t): the statement of antipodal pair t (empty: the pair is
+// already merged in the sweep kernel's snapshot); vary: the sweep kernel's
+// varying vertices (null for the plain evaluator).
+template <class PairStmt>
+void emit_tail(std::ostringstream& o, const HostProgram& P, PairStmt pair_stmt, const std::vector<char>* vary) {
+  const int nV = P.nV, nP = P.nP;
   o << "    // phase 2: antipodal pairs\n";
   for (int t = 0; t < nP; ++t) {
-    if (skip_pair(t)) continue;
-    const uint32_t pr = P.words[nV + nE + t];
-    o << "    E::pair(L, " << (pr & 0xFFFF) << ", " << (pr >> 16) << ");\n";
+    const std::string st = pair_stmt(t);
+    if (!st.empty()) o << "    " << st << "\n";
   }
   o << "    // phase 3: region ids and the region tree (each vertex's entry read\n"
        "    // " << kAhead << " vertices ahead)\n";
@@ -138,7 +138,9 @@ void emit_tail(std::ostringstream& o, const HostProgram& P, Skip skip_pair, cons
 // kSnapBits when only sigma(0,0) is fixed.
 constexpr int kSnapVaryingBits = 6 + 3;
 
-bool snapshot_applies(const HostProgram& P) { return P.nA - 1 >= kSnapVaryingBits + 8; }
+// (d <= 9: the reduction of even d's antipodal pairs needs the varying
+// bits to cover the horizontal axis)
+bool snapshot_applies(const HostProgram& P) { return P.nA - 1 >= kSnapVaryingBits + 8 && P.d <= kSnapVaryingBits; }
 
 std::string jit_source(const HostProgram& P) {
   std::ostringstream o;
@@ -160,7 +162,13 @@ std::string jit_source(const HostProgram& P) {
     }
     o << " E::close(L, " << v << ", r" << v << "); }\n";
   }
-  emit_tail(o, P, [](int) { return false; }, nullptr);
+  emit_tail(
+      o, P,
+      [&](int t) {
+        const uint32_t pr = P.words[nV + P.nE + t];
+        return "E::pair(L, " + std::to_string(pr & 0xFFFF) + ", " + std::to_string(pr >> 16) + ");";
+      },
+      nullptr);
   o << "  }\n};\n\n";
   if (snapshot_applies(P)) {
     // vertices whose sign varies inside a chunk, and the full adjacency
@@ -188,10 +196,12 @@ std::string jit_source(const HostProgram& P) {
     // varying vertex (and the padding after vertex NV-1) keeps its own
     // index, its entry before its edges are added.
     const int nE = P.nE;
-    auto fixed_pair = [&](int t) {
+    const bool even = d % 2 == 0;
+    auto both_fixed = [&](int t) {
       const uint32_t pr = P.words[nV + nE + t];
-      return (d % 2 == 1) && !vary[pr & 0xFFFF] && !vary[pr >> 16];
+      return !vary[pr & 0xFFFF] && !vary[pr >> 16];
     };
+    auto fixed_pair = [&](int t) { return !even && both_fixed(t); };
     const int nw = (nV + 63) / 64;
     // links of each fixed-sign vertex: same-sign neighbours (packed: u,
     // lattice bits of u and v, flip difference) and antipodal partners
@@ -252,12 +262,100 @@ std::string jit_source(const HostProgram& P) {
          "      mn = z < mn ? z : mn;\n"
          "      if (mn < cur) {\n        row[v] = (E::Ent)mn;\n        changed = true;\n      }\n    }\n"
          "    return changed;\n  }\n";
+    if (even) {
+      // Even d: the antipodal pairs of fixed-sign vertices carry a parity
+      // (they join opposite sides), which the plain label propagation
+      // cannot merge.  They are reduced per chunk instead.  Stage 1: each
+      // lane applies them, in order, to its own copy of the snapshot row; a
+      // pair that joins two sets belongs to a spanning forest of the pairs
+      // over the snapshot's sets, one that first closes an odd cycle of a
+      // set marks it, and any other changes nothing in any batch (the
+      // cycle it closes has the parity of the forest path, or the set is
+      // marked already).  Stages 2 and 3: the sets of the pair graph that
+      // no varying vertex reaches -- none of their vertices has a varying
+      // neighbour or partner, so no phase-1 edge or pair of a batch touches
+      // them -- are merged into the snapshot row, each vertex pointing at
+      // the set's smallest vertex (the root the union-find would give).
+      // Such a set has no odd cycle: the varying bits 1 .. 9 include the
+      // lattice points (i, 0), i = 1 .. d (bits 1 .. d in the bit order;
+      // the sweep kernel exists for d <= 9), so the varying vertices cover
+      // the horizontal axis line of the reflected diamond but its centre,
+      // a one-sided loop that every other one crosses; a cycle of
+      // fixed-sign vertices closed by an odd number of pairs is one-sided,
+      // so it passes through the centre, whose neighbours (1, 0) and
+      // (0, 1) vary.  Only the forest pairs and marks of the reached sets
+      // are left to each batch.
+      std::vector<uint64_t> touch(nw, 0), fixedv(nw, 0);
+      for (int v = 0; v < nV; ++v) {
+        if (vary[v]) continue;
+        fixedv[v / 64] |= 1ull << (v % 64);
+        for (int u : adj[v])
+          if (vary[u]) touch[v / 64] |= 1ull << (v % 64);
+      }
+      for (int t = 0; t < P.nP; ++t) {
+        const uint32_t pr = P.words[nV + nE + t];
+        const int a = (int)(pr & 0xFFFF), b = (int)(pr >> 16);
+        if (vary[a] && !vary[b]) touch[b / 64] |= 1ull << (b % 64);
+        if (vary[b] && !vary[a]) touch[a / 64] |= 1ull << (a % 64);
+      }
+      // (bit lane of word k: vertex lane + 64 k, the one the lane owns)
+      auto lit = [](uint64_t x) {
+        std::ostringstream h;
+        h << "0x" << std::hex << x << "ull";
+        return h.str();
+      };
+      const std::string C = "Cfg<" + std::to_string(d) + ">::";
+      o << "  __device__ __forceinline__ static uint64_t pairs_1(const Lane& L, uint8_t* snap, int lane) {\n"
+           "    uint32_t* w = reinterpret_cast<uint32_t*>(snap);\n"
+           "    for (int k = 0; k < " << C << "SNAP_WORDS; ++k) L.eword(k) = w[k];\n"
+           "    E::clear_side(L);\n    uint32_t kf = 0, ko = 0;\n";
+      for (int t = 0; t < P.nP; ++t) {
+        if (!both_fixed(t)) continue;
+        const uint32_t pr = P.words[nV + nE + t];
+        o << "    { const uint32_t k = E::pair_kind(L, " << (pr & 0xFFFF) << ", " << (pr >> 16)
+          << "); kf |= (uint32_t)(k == 1u) << " << t << "; ko |= (uint32_t)(k == 2u) << " << t << "; }\n";
+      }
+      o << "    if (lane < " << C << "TOUCH_WORDS) w[" << C << "SNAP_TOUCH + lane] = 0;\n"
+           "    return (uint64_t)kf | (uint64_t)ko << 32;\n  }\n";
+      o << "  __device__ __forceinline__ static void pairs_2(const Lane& L, uint8_t* snap, int lane) {\n"
+           "    // the sets that vertices with a varying neighbour or partner are in\n"
+           "    uint32_t* w = reinterpret_cast<uint32_t*>(snap);\n";
+      for (int k = 0; k < nw; ++k)
+        o << "    if ((" << lit(touch[k]) << " >> lane) & 1u) {\n"
+             "      const uint32_t r = E::root_of(L, (uint32_t)(lane + " << 64 * k << "));\n"
+             "      atomicOr(&w[" << C << "SNAP_TOUCH + (r >> 5)], 1u << (r & 31u));\n    }\n";
+      o << "  }\n";
+      o << "  __device__ __forceinline__ static void pairs_3(const Lane& L, uint8_t* snap, int lane, uint64_t kinds) {\n"
+           "    uint32_t* w = reinterpret_cast<uint32_t*>(snap);\n"
+           "    E::Ent* row = reinterpret_cast<E::Ent*>(snap);\n"
+           "    auto reached = [&](uint32_t r) { return (w[" << C << "SNAP_TOUCH + (r >> 5)] >> (r & 31u)) & 1u; };\n"
+           "    // the lane's fixed-sign vertices in sets no varying vertex reaches\n";
+      for (int k = 0; k < nw; ++k)
+        o << "    if ((" << lit(fixedv[k]) << " >> lane) & 1u) {\n"
+             "      const uint32_t v = (uint32_t)(lane + " << 64 * k << "), r = E::root_of(L, v);\n"
+             "      if (!reached(r) && row[v] != r) row[v] = (E::Ent)r;\n    }\n";
+      o << "    // the pairs of the other sets\n    uint32_t keep = 0;\n";
+      for (int t = 0; t < P.nP; ++t) {
+        if (!both_fixed(t)) continue;
+        const uint32_t pr = P.words[nV + nE + t];
+        o << "    keep |= reached(E::root_of(L, " << (pr & 0xFFFF) << "u)) << " << t << ";\n";
+      }
+      o << "    w[" << C << "SNAP_KIND] = (uint32_t)kinds & keep;\n"
+           "    w[" << C << "SNAP_KIND + 1] = (uint32_t)(kinds >> 32) & keep;\n  }\n";
+    }
     o << "  __device__ __forceinline__ void snapshot(Cfg<" << d
       << ">::Mask m, const Lane& L, uint8_t* snap, int lane) const {\n"
          "    (void)L;\n    snap_init(snap, lane);\n    const Links ln = snap_links(uniform_mask(m), lane);\n"
          "    // labels only go down: at most NV rounds (the bound is never reached)\n"
          "    for (int round = 0; round <= Cfg<"
-      << d << ">::NV; ++round)\n      if (__builtin_amdgcn_ballot_w64(snap_step(ln, snap, lane)) == 0) break;\n  }\n";
+      << d << ">::NV; ++round)\n      if (__builtin_amdgcn_ballot_w64(snap_step(ln, snap, lane)) == 0) break;\n";
+    if (even)
+      o << "    // the stages read what other lanes wrote in the one before\n"
+           "    PW_FENCE();\n    __builtin_amdgcn_wave_barrier();\n    const uint64_t kinds = pairs_1(L, snap, lane);\n"
+           "    PW_FENCE();\n    __builtin_amdgcn_wave_barrier();\n    pairs_2(L, snap, lane);\n"
+           "    PW_FENCE();\n    __builtin_amdgcn_wave_barrier();\n    pairs_3(L, snap, lane, kinds);\n"
+           "    PW_FENCE();\n";
+    o << "  }\n";
     // The edges of phase 1 between a varying vertex and a fixed-sign
     // neighbour, in the order the batch adds them; such an edge is a
     // duplicate when an earlier fixed-sign neighbour of the same vertex has
@@ -284,7 +382,9 @@ std::string jit_source(const HostProgram& P) {
     // is v: v is a root of the fixed-sign part) and from m0
     o << "  struct Flags {\n    uint64_t fr[" << nw << "];  // fixed-sign vertices that are snapshot roots\n"
       << "    uint64_t cr[" << nw << "];  // fixed-sign vertices whose tree edge (both ends fixed) is crossed\n"
-      << "    uint64_t dp[" << nd << "];  // duplicate phase-1 edges to fixed-sign neighbours\n  };\n";
+      << "    uint64_t dp[" << nd << "];  // duplicate phase-1 edges to fixed-sign neighbours\n";
+    if (even) o << "    uint32_t fp, op;  // fixed-sign pairs left to each batch: joining two sets, marking one\n";
+    o << "  };\n";
     o << "  __device__ __forceinline__ Flags flags(Cfg<" << d << ">::Mask m0, const uint8_t* snap) const {\n";
     o << "    Flags fl{};\n    const E::Ent* row = reinterpret_cast<const E::Ent*>(snap);\n";
     for (int v = 0; v < nV; ++v)
@@ -305,6 +405,10 @@ std::string jit_source(const HostProgram& P) {
         o << "    fl.cr[" << v / 64 << "] |= (uint64_t)(" << sign_expr(P, v, "m0") << " ^ " << sign_expr(P, t, "m0")
           << ") << " << v % 64 << ";\n";
     }
+    if (even)
+      o << "    fl.fp = (uint32_t)__builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t*>(snap)[Cfg<" << d
+        << ">::SNAP_KIND]);\n    fl.op = (uint32_t)__builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t*>(snap)[Cfg<"
+        << d << ">::SNAP_KIND + 1]);\n";
     o << "    return fl;\n  }\n";
     o << "  // one batch: restore, the edges of the varying vertices, then as usual\n";
     o << "  __device__ __forceinline__ u128 batch(Cfg<" << d
@@ -318,13 +422,16 @@ std::string jit_source(const HostProgram& P) {
         << "] = uniform_mask(b); }\n";
     for (int k = 0; k < nd; ++k)
       o << "    { uint64_t a = fl_chunk.dp[" << k << "]; PW_OPAQUE(a); fl.dp[" << k << "] = uniform_mask(a); }\n";
+    if (even)
+      o << "    { uint32_t a = fl_chunk.fp, b = fl_chunk.op; PW_OPAQUE(a); PW_OPAQUE(b); "
+           "fl.fp = (uint32_t)__builtin_amdgcn_readfirstlane(a); fl.op = (uint32_t)__builtin_amdgcn_readfirstlane(b); }\n";
     // the restore: the row, a word at a time (a compiler barrier every 8
     // words keeps the loads from all being hoisted at once, which would
     // need a register each)
     o << "    {\n      const uint32_t* s = reinterpret_cast<const uint32_t*>(__builtin_assume_aligned(snap, 16));\n"
          "#pragma unroll\n      for (int k = 0; k < Cfg<"
-      << d << ">::SNAP_WORDS; ++k) {\n        L.eword(k) = s[k];\n        if (k % 8 == 7) PW_FENCE();\n      }\n    }\n";
-    o << "    E::clear_side(L);\n";
+      << d << ">::SNAP_WORDS; ++k) {\n        L.eword(k) = s[k];\n        if (k % 8 == 7) PW_FENCE();\n      }\n";
+    o << "    }\n    E::clear_side(L);\n";
     o << "    const E::Ent* srow = reinterpret_cast<const E::Ent*>(snap);\n";
     o << "    // phase 1 for the varying vertices (in index order; each with all\n"
          "    // its fixed-sign neighbours and its earlier varying ones; duplicate\n"
@@ -355,7 +462,18 @@ std::string jit_source(const HostProgram& P) {
       }
       o << " }\n";
     }
-    emit_tail(o, P, fixed_pair, &vary);
+    emit_tail(
+        o, P,
+        [&](int t) -> std::string {
+          const uint32_t pr = P.words[nV + nE + t];
+          const std::string a = std::to_string(pr & 0xFFFF), b = std::to_string(pr >> 16), ts = std::to_string(t);
+          if (fixed_pair(t)) return "";
+          if (even && both_fixed(t))
+            return "if ((fl.fp >> " + ts + ") & 1u) E::pair(L, (int)srow[" + a + "], (int)srow[" + b +
+                   "]); else if ((fl.op >> " + ts + ") & 1u) E::odd_mark(L, (int)srow[" + a + "]);";
+          return "E::pair(L, " + a + ", " + b + ");";
+        },
+        &vary);
     o << "  }\n};\n\n";
   }
   o << "}  // namespace pw\n\n";

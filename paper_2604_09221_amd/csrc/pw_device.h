@@ -152,10 +152,16 @@ struct Cfg {
   // dynamic area (DYN_WORDS per lane)
   static constexpr int PAR_ROWS = RMAX + 1;
   static constexpr int DYN_WORDS = LOW_WORDS;
-  // snapshot row of the sweep kernel: the entries of vertices 0 .. NV-1
-  // (SNAP_WORDS words, copied word by word), padded to 16 bytes
+  // snapshot area of the sweep kernel: the entries of vertices 0 .. NV-1
+  // (SNAP_WORDS words, copied word by word); for even d then the chunk's
+  // bitset of the sets that varying vertices reach (TOUCH_WORDS words)
+  // and the antipodal pairs left to each batch (2 words); padded to 16
+  // bytes
   static constexpr int SNAP_WORDS = (NV * EB + 3) / 4;
-  static constexpr int SNAP_BYTES = (SNAP_WORDS * 4 + 15) / 16 * 16;
+  static constexpr int TOUCH_WORDS = EVEN ? (NV + 31) / 32 : 0;
+  static constexpr int SNAP_TOUCH = SNAP_WORDS;
+  static constexpr int SNAP_KIND = SNAP_TOUCH + TOUCH_WORDS;
+  static constexpr int SNAP_BYTES = ((EVEN ? SNAP_KIND + 2 : SNAP_WORDS) * 4 + 15) / 16 * 16;
   static constexpr int WAVE_BYTES = LANE_WORDS * 4 * 64;
   // waves per block: as many waves per CU as the 160 KiB of LDS allows,
   // in blocks of 4 waves, or of 2 where that keeps more of them resident
@@ -421,6 +427,49 @@ struct Eval {
     uint32_t ea, eb, pa, pb;
     const uint32_t ra = find_parity(L, a, ea, pa);
     const uint32_t rb = find_parity(L, b, eb, pb);
+    join(L, ra, rb, ea, eb, pa, pb);
+  }
+
+  // The same, telling what the pair did: 1 if it joined two sets, 2 if it
+  // set the odd-cycle flag of a set that had none (even d), 0 if it
+  // changed nothing.  (The sweep kernel's per-chunk reduction of the pairs
+  // whose vertices are all of fixed sign.)
+  __device__ static __forceinline__ uint32_t pair_kind(const Lane& L, int a, int b) {
+    uint32_t ea, eb, pa, pb;
+    const uint32_t ra = find_parity(L, a, ea, pa);
+    const uint32_t rb = find_parity(L, b, eb, pb);
+    const uint32_t kind = ra != rb ? 1u : ((C::EVEN && pa == pb && !odd_flag(L, ra, ea)) ? 2u : 0u);
+    join(L, ra, rb, ea, eb, pa, pb);
+    return kind;
+  }
+
+  // root of the set of r (an entry's parity and flag bits ignored)
+  __device__ static __forceinline__ uint32_t root_of(const Lane& L, uint32_t r) {
+    uint32_t er = ent(L, (int)r);
+    while (idx(er) != r) {
+      r = idx(er);
+      er = ent(L, (int)r);
+    }
+    return r;
+  }
+
+  // sets the odd-cycle flag of the set of u (even d): what a pair inside
+  // one set closing an odd cycle does
+  __device__ static __forceinline__ void odd_mark(const Lane& L, int u) {
+    const uint32_t r = root_of(L, (uint32_t)u);
+    if constexpr (C::SIDE) {
+      set_side(L, r, 1u);
+    } else {
+      ent(L, (int)r) = (Ent)(ent(L, (int)r) | kOdd);
+    }
+  }
+
+  // the pair's effect once the roots ra, rb of its vertices and their
+  // parities pa, pb (even d) are known: an odd cycle flags the root, else
+  // the larger root is linked below the smaller one with the parity that
+  // makes the two vertices opposite, passing on its odd-cycle flag
+  __device__ static __forceinline__ void join(const Lane& L, uint32_t ra, uint32_t rb, uint32_t ea, uint32_t eb,
+                                              uint32_t pa, uint32_t pb) {
     if constexpr (C::SIDE) {
       if (ra == rb) {
         if (pa == pb) set_side(L, ra, 1u);

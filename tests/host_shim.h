@@ -1,8 +1,10 @@
 // Host shim for tests/test_host_emulation.py and tests/test_group_emulation.py:
 // lets g++ compile the device headers (pw_device.h, pw_group.h) and a
 // generated per-triangulation evaluator, so the evaluation runs on the CPU.
-// Wave-level intrinsics (ballots, shuffles, atomics, lane reads) are not
-// emulated and abort if reached.
+// Wave-level intrinsics (ballots, shuffles, lane reads) and global atomics
+// are not emulated and abort if reached.  atomicOr is a plain OR: the
+// emulation runs one lane at a time, so nothing can interleave with it
+// (the sweep kernel's per-chunk stages use it on the wave's own LDS words).
 #pragma once
 #define __HIPCC_RTC__ 1
 #include <cstdint>
@@ -32,7 +34,11 @@ static inline int __popc(unsigned x) { return __builtin_popcount(x); }
 [[noreturn]] static inline void emu_unsupported() { std::fprintf(stderr, "unsupported in emulation\n"); std::abort(); }
 template <class T> static inline T atomicAdd(T*, T) { emu_unsupported(); }
 template <class T> static inline T atomicMin(T*, T) { emu_unsupported(); }
-template <class T> static inline T atomicOr(T*, T) { emu_unsupported(); }
+template <class T> static inline T atomicOr(T* p, T x) {
+  const T old = *p;
+  *p = old | x;
+  return old;
+}
 static inline uint64_t __ballot(int) { emu_unsupported(); }
 static inline int __shfl_xor(int, int, int) { emu_unsupported(); }
 static inline uint64_t __builtin_amdgcn_ballot_w64(bool) { emu_unsupported(); }

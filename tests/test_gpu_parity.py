@@ -382,17 +382,21 @@ def _chunks_across_range(rng, n_free, n_aligned, n_ragged, chunk=512):
     return out
 
 
-def test_d7_sweep_kernel_mid_range(pw):
-    """The specialised d = 7 sweep kernel (shared snapshot per 512 masks)
-    on 256 whole chunks spread over the 2^35 indices and 64 ragged ranges:
-    histogram counts and witnesses of every range against the oracle."""
-    d = 7
-    E = I.standard_triangulation(d)
+@pytest.mark.parametrize("d", [7, 6])
+def test_d7_sweep_kernel_mid_range(pw, d):
+    """The specialised sweep kernel (shared snapshot per 512 masks) on 256
+    whole chunks spread over the 2^(nA - 1) indices and 64 ragged ranges:
+    histogram counts and witnesses of every range against the oracle.  d = 7
+    is the timed sweep; d = 6 (a varied triangulation) covers the even-degree
+    reduction of the fixed-sign antipodal pairs with u8 entries that hold
+    the parity bit."""
+    E = I.standard_triangulation(d) if d == 7 else I.lift_triangulation(d, 5, noise=1.0)
     tri = pw.Triangulation(d, E).specialize()
-    rng = np.random.default_rng(735)
-    ranges = _chunks_across_range(rng, 35, 256, 64)
+    rng = np.random.default_rng(735 + d)
+    nA = I.n_points(d)
+    ranges = _chunks_across_range(rng, nA - 1, 256, 64)
     hist = pw.Histogram(512)
-    allm = np.concatenate([enum_masks(a, n, nA=36) for a, n in ranges])
+    allm = np.concatenate([enum_masks(a, n, nA=nA) for a, n in ranges])
     want = oracle.scheme_many(d, E, allm, threads=THREADS)
     pos = 0
     for a, n in ranges:
@@ -412,7 +416,7 @@ def test_d8_class_sweep_kernel_mid_range(pw):
 
     fz = bench.fig2_fixed_bits(8)
     rng = np.random.default_rng(842)
-    for name in ("rank015", "bow_tie"):
+    for name in ("rank015", "bow_tie", "rank016"):
         E = fig2_edges(name)
         tri = pw.Triangulation(8, E).specialize()
         ranges = _chunks_across_range(rng, 42, 128, 32)

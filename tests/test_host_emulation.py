@@ -79,7 +79,25 @@ int main(int argc, char** argv) {
       any = false;
       for (int j = 0; j < 64; ++j) any = S::snap_step(links[j], srow, j) || any;
     }
-    if (memcmp(before_snap.data(), smem, kBytes) != 0) ++foreign;  // the snapshot uses its own row only
+    if (memcmp(before_snap.data(), smem, kBytes) != 0) ++foreign;  // the label propagation uses its own row only
+#ifdef SNAP_PAIRS
+    // even d: the per-chunk reduction of the fixed-sign antipodal pairs,
+    // one stage after the other, each stage one lane after the other (on
+    // the device the stages are separated by wave barriers); a lane may
+    // write its own bytes of the area (and the shared snapshot words)
+    uint64_t kinds[64];
+    for (int stage = 1; stage <= 3; ++stage)
+      for (int j = 0; j < 64; ++j) {
+        threadIdx.x = j;
+        const pw::Lane Lj = pw::lane_memory<DEG>(smem, C::LANE_WORDS);
+        own_bytes(j, own);
+        memcpy(before.data(), smem, kBytes);
+        if (stage == 1) kinds[j] = S::pairs_1(Lj, srow, j);
+        if (stage == 2) S::pairs_2(Lj, srow, j);
+        if (stage == 3) S::pairs_3(Lj, srow, j, kinds[j]);
+        if (foreign_write(own, before, smem)) ++foreign;
+      }
+#endif
 #endif
     threadIdx.x = lane;
     const pw::Lane L = pw::lane_memory<DEG>(smem, C::LANE_WORDS);
@@ -106,7 +124,8 @@ def _compile(tmp_path, d, edges, snap):
     src = pw.jit_source(d, edges)
     src = src[:src.index('extern "C"')]          # the evaluators; the kernels need a GPU
     path = tmp_path / f"emu_d{d}.cpp"
-    path.write_text(("#define SNAP 1\n" if snap else "") + '#include "host_shim.h"\n' + src + MAIN.replace("DEG", str(d)))
+    defs = ("#define SNAP 1\n" if snap else "") + ("#define SNAP_PAIRS 1\n" if snap and d % 2 == 0 else "")
+    path.write_text(defs + '#include "host_shim.h"\n' + src + MAIN.replace("DEG", str(d)))
     exe = tmp_path / f"emu_d{d}"
     subprocess.check_call(["g++", "-O1", "-std=c++17", "-w", "-fsanitize=address,undefined",
                            "-fno-sanitize-recover=undefined", "-I", HERE, "-I", CSRC, "-o", str(exe), str(path)])
@@ -122,6 +141,21 @@ def _compile(tmp_path, d, edges, snap):
                                                  (9, None, 0, 600, True)])
 def test_evaluator_on_host_matches_oracle(tmp_path, d, noise, seed, n, snap):
     edges = I.standard_triangulation(d) if noise is None else I.lift_triangulation(d, seed, noise=noise)
+    _check(tmp_path, d, edges, seed, n, snap)
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+@pytest.mark.parametrize("name", ["bow_tie", "rank016"])
+def test_sweep_evaluator_on_fig2_triangulations(tmp_path, name):
+    """The sweep kernel's evaluator on two of the degree-8 triangulations
+    of Fig. 2.  On bow_tie the fixed-sign pairs close an odd cycle in every
+    chunk (a mark left to each batch); on rank016 more of the pair sets are
+    out of the varying vertices' reach (merged into the snapshot)."""
+    edges = np.loadtxt(os.path.join(HERE, "golden", f"fig2_{name}.edges"), dtype=np.int32)
+    _check(tmp_path, 8, edges, 9, 400, True)
+
+
+def _check(tmp_path, d, edges, seed, n, snap):
     exe = _compile(tmp_path, d, edges, snap)
     masks = np.ascontiguousarray(I.random_masks(d, seed + 11, n).astype(np.uint64))
     # first rows: the Harnack distribution (the most regions), all '+', all
