@@ -104,19 +104,47 @@ void emit_tail(std::ostringstream& o, const HostProgram& P, PairStmt pair_stmt, 
   auto region_of = [&](int x) -> std::string {  // a vertex whose region id is already assigned
     return (*vary)[x] ? std::to_string(x) : "(int)srow[" + std::to_string(x) + "]";
   };
-  for (int v = 0; v < nV; ++v) {
-    const int t = tree_parent(P, v);
+  // Runs of up to 4 consecutive fixed-sign vertices (in one flag word)
+  // share one uniform test first: most of them are not snapshot roots.
+  // (Entries read ahead for the varying vertices are read before a run.
+  // Runs of 4 measured faster than runs of 8 at d = 7.)
+  auto run_end = [&](int v0) {
+    int v1 = v0;
+    while (v1 < nV && !(*vary)[v1] && v1 - v0 < 4 && v1 / 64 == v0 / 64) ++v1;
+    return v1;
+  };
+  auto run_mask = [](int v0, int v1) {
+    std::ostringstream h;
+    h << "0x" << std::hex << ((1ull << (v1 - v0)) - 1) << "ull";
+    return h.str();
+  };
+  auto read_ahead = [&](int v) {
     if (v + kAhead < nV && (*vary)[v + kAhead])
       o << "    const uint32_t e" << v + kAhead << " = E::ent(L, " << v + kAhead << ");\n";
+  };
+  auto step3 = [&](int v) {
+    const int t = tree_parent(P, v);
     const std::string ev = (*vary)[v] ? "e" + std::to_string(v) : "E::ent(L, " + std::to_string(v) + ")";
-    const std::string step = "E::vertex3c(L, " + std::to_string(v) + ", " + (t >= 0 ? region_of(t) : "-1") + ", " +
-                             crossed(v, t) + ", " + ev + ", nR, roots);";
-    if ((*vary)[v])
-      o << "    " << step << "\n";
-    else
-      o << "    if (" << bitflag("fr", v) << ") " << step << "\n";
+    return "E::vertex3c(L, " + std::to_string(v) + ", " + (t >= 0 ? region_of(t) : "-1") + ", " + crossed(v, t) +
+           ", " + ev + ", nR, roots);";
+  };
+  for (int v = 0; v < nV;) {
+    if ((*vary)[v]) {
+      read_ahead(v);
+      o << "    " << step3(v) << "\n";
+      ++v;
+      continue;
+    }
+    const int v1 = run_end(v);
+    for (int x = v; x < v1; ++x) read_ahead(x);
+    if (v1 - v > 1)
+      o << "    if ((fl.fr[" << v / 64 << "] >> " << v % 64 << ") & " << run_mask(v, v1) << ") {\n";
+    for (int x = v; x < v1; ++x) o << "    if (" << bitflag("fr", x) << ") " << step3(x) << "\n";
+    if (v1 - v > 1) o << "    }\n";
+    v = v1;
   }
   if (odd) {
+    // (about half of these flags are set: grouping them measured slower)
     o << "    // crossed tree edges of the fixed-sign non-roots\n";
     for (int v = 0; v < nV; ++v) {
       const int t = tree_parent(P, v);
