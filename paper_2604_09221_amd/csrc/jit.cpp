@@ -55,6 +55,17 @@ int lattice_bit(const HostProgram& P, int v) { return (int)(P.words[v] & 0x7F); 
 
 constexpr int kAhead = 4;  // phase 3 reads entries this many vertices ahead
 
+// The sweep kernel's tree edges (v, t(v)) with both ends of fixed sign, in
+// vertex order (odd d: a chunk reduces their crossing tests).
+std::vector<int> fixed_tree_edges(const HostProgram& P, const std::vector<char>& vary) {
+  std::vector<int> h;
+  for (int v = 0; v < P.nV; ++v) {
+    const int t = tree_parent(P, v);
+    if (!vary[v] && t >= 0 && !vary[t]) h.push_back(v);
+  }
+  return h;
+}
+
 // phases 2 and 3 and the call of phase 4, common to both evaluators
 // pair_stmt(t): the statement of antipodal pair t (empty: the pair is
 // already merged in the sweep kernel's snapshot); vary: the sweep kernel's
@@ -144,17 +155,26 @@ void emit_tail(std::ostringstream& o, const HostProgram& P, PairStmt pair_stmt, 
     v = v1;
   }
   if (odd) {
-    // (about half of these flags are set: grouping them measured slower)
-    o << "    // crossed tree edges of the fixed-sign non-roots\n";
+    o << "    // crossed tree edges of the fixed-sign non-roots: to a varying\n"
+         "    // parent, then between fixed-sign vertices (only the first edge of\n"
+         "    // each pair of snapshot roots, runs of 4 edges tested together)\n";
     for (int v = 0; v < nV; ++v) {
       const int t = tree_parent(P, v);
-      if ((*vary)[v] || t < 0) continue;
-      if (!(*vary)[t])
-        o << "    if (((fl.cr[" << v / 64 << "] & ~fl.fr[" << v / 64 << "]) >> " << v % 64 << ") & 1u) E::hit(L, srow["
-          << v << "], srow[" << t << "], true, roots);\n";
-      else
-        o << "    if (!" << bitflag("fr", v) << ") E::hit(L, srow[" << v << "], " << t << ", " << crossed(v, t)
-          << ", roots);\n";
+      if ((*vary)[v] || t < 0 || !(*vary)[t]) continue;
+      o << "    if (!" << bitflag("fr", v) << ") E::hit(L, srow[" << v << "], " << t << ", " << crossed(v, t)
+        << ", roots);\n";
+    }
+    const std::vector<int> h = fixed_tree_edges(P, *vary);
+    const int nh = (int)h.size();
+    for (int e = 0; e < nh;) {
+      int e1 = e;
+      while (e1 < nh && e1 - e < 4 && e1 / 64 == e / 64) ++e1;
+      if (e1 - e > 1) o << "    if ((fl.hx[" << e / 64 << "] >> " << e % 64 << ") & " << run_mask(e, e1) << ") {\n";
+      for (int x = e; x < e1; ++x)
+        o << "    if ((fl.hx[" << x / 64 << "] >> " << x % 64 << ") & 1u) E::hit(L, srow[" << h[x] << "], srow["
+          << tree_parent(P, h[x]) << "], true, roots);\n";
+      if (e1 - e > 1) o << "    }\n";
+      e = e1;
     }
   }
   o << "    return E::finish(L, nR, roots, errs);\n";
@@ -262,6 +282,21 @@ std::string jit_source(const HostProgram& P) {
         o << (v || j ? "," : "") << (j == 0 ? "\n  " : " ") << "0x" << std::hex << x << std::dec << "u";
       }
     o << "};\n";
+    if (d % 2 == 1) {
+      const std::vector<int> he = fixed_tree_edges(P, vary);
+      o << "// per tree edge between fixed-sign vertices: bits 0-7 v, 8-15 t(v), 16-22\n"
+           "// v's lattice bit, 23-29 t's, 30 the flip difference\n";
+      o << "__device__ const uint32_t kHitEdges[" << std::max<size_t>(1, he.size()) << "] = {";
+      for (size_t e = 0; e < std::max<size_t>(1, he.size()); ++e) {
+        uint32_t x = 0;
+        if (e < he.size()) {
+          const int v = he[e], t = tree_parent(P, v);
+          x = (uint32_t)v | (uint32_t)t << 8 | bit_of(v) << 16 | bit_of(t) << 23 | (flip_of(v) ^ flip_of(t)) << 30;
+        }
+        o << (e ? "," : "") << (e % 8 == 0 ? "\n  " : " ") << "0x" << std::hex << x << std::dec << "u";
+      }
+      o << "};\n";
+    }
     o << "struct JitSnap {\n  using E = Eval<" << d << ">;\n";
     o << "  static constexpr int kNW = " << nw << ", kSlots = " << slots << ";\n";
     o << "  static constexpr int kRow = Cfg<" << d << ">::SNAP_WORDS * 4 / Cfg<" << d << ">::EB;\n";
@@ -372,6 +407,43 @@ std::string jit_source(const HostProgram& P) {
       o << "    w[" << C << "SNAP_KIND] = (uint32_t)kinds & keep;\n"
            "    w[" << C << "SNAP_KIND + 1] = (uint32_t)(kinds >> 32) & keep;\n  }\n";
     }
+    const std::vector<int> hedges = fixed_tree_edges(P, vary);
+    const int nh = (int)hedges.size(), nhk = (nh + 63) / 64, nh32 = (nh + 31) / 32;
+    if (!even) {
+      // Odd d: a crossed tree edge between two fixed-sign non-root and
+      // parent vertices marks the root region when its two snapshot roots
+      // end up in one region; every edge with the same pair of snapshot
+      // roots tests the same thing (about 34 such edges per batch over 6
+      // pairs at d = 7).  Per chunk, stage 1 writes each edge's pair (a key;
+      // none if the edge is not crossed or v is a snapshot root) and stage 2
+      // keeps the first edge of each key; a batch tests only those.
+      o << "  static constexpr int kNH = " << nh << ", kHK = " << nhk << ";\n";
+      o << "  __device__ __forceinline__ static void hits_1(uint8_t* snap, int lane, uint64_t m0) {\n"
+           "    uint32_t* w = reinterpret_cast<uint32_t*>(snap);\n"
+           "    const E::Ent* row = reinterpret_cast<const E::Ent*>(snap);\n"
+           "    uint16_t* key = reinterpret_cast<uint16_t*>(w + Cfg<" << d << ">::SNAP_HKEY);\n"
+           "    if (lane < Cfg<" << d << ">::HIT_WORDS) w[Cfg<" << d << ">::SNAP_HX + lane] = 0;\n"
+           "    for (int k = 0; k < kHK; ++k) {\n"
+           "      const int e = lane + 64 * k;\n"
+           "      if (e >= kNH) continue;\n"
+           "      const uint32_t x = kHitEdges[e], v = x & 0xFFu, t = (x >> 8) & 0xFFu;\n"
+           "      const uint32_t a = row[v], b = row[t];\n"
+           "      const bool crossed = ((uint32_t)((m0 >> ((x >> 16) & 0x7Fu)) ^ (m0 >> ((x >> 23) & 0x7Fu))) ^ (x >> 30)) & 1u;\n"
+           "      const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;\n"
+           "      key[e] = (uint16_t)((a != v && crossed) ? (lo | hi << 8) : 0xFFFFu);\n"
+           "    }\n  }\n";
+      o << "  __device__ __forceinline__ static void hits_2(uint8_t* snap, int lane) {\n"
+           "    uint32_t* w = reinterpret_cast<uint32_t*>(snap);\n"
+           "    const uint16_t* key = reinterpret_cast<const uint16_t*>(w + Cfg<" << d << ">::SNAP_HKEY);\n"
+           "    for (int k = 0; k < kHK; ++k) {\n"
+           "      const int e = lane + 64 * k;\n"
+           "      const uint32_t my = e < kNH ? (uint32_t)key[e] : 0xFFFFu;\n"
+           "      bool first = my != 0xFFFFu;\n"
+           "      const int jn = kNH < 64 * (k + 1) ? kNH : 64 * (k + 1);\n"
+           "      for (int j = 0; j < jn; ++j) first = first && !(j < e && (uint32_t)key[j] == my);\n"
+           "      if (first) atomicOr(&w[Cfg<" << d << ">::SNAP_HX + (e >> 5)], 1u << (e & 31));\n"
+           "    }\n  }\n";
+    }
     o << "  __device__ __forceinline__ void snapshot(Cfg<" << d
       << ">::Mask m, const Lane& L, uint8_t* snap, int lane) const {\n"
          "    (void)L;\n    snap_init(snap, lane);\n    const Links ln = snap_links(uniform_mask(m), lane);\n"
@@ -383,6 +455,11 @@ std::string jit_source(const HostProgram& P) {
            "    PW_FENCE();\n    __builtin_amdgcn_wave_barrier();\n    const uint64_t kinds = pairs_1(L, snap, lane);\n"
            "    PW_FENCE();\n    __builtin_amdgcn_wave_barrier();\n    pairs_2(L, snap, lane);\n"
            "    PW_FENCE();\n    __builtin_amdgcn_wave_barrier();\n    pairs_3(L, snap, lane, kinds);\n"
+           "    PW_FENCE();\n";
+    else
+      o << "    // the stages read what other lanes wrote in the one before\n"
+           "    PW_FENCE();\n    __builtin_amdgcn_wave_barrier();\n    hits_1(snap, lane, uniform_mask(m));\n"
+           "    PW_FENCE();\n    __builtin_amdgcn_wave_barrier();\n    hits_2(snap, lane);\n"
            "    PW_FENCE();\n";
     o << "  }\n";
     // The edges of phase 1 between a varying vertex and a fixed-sign
@@ -413,6 +490,7 @@ std::string jit_source(const HostProgram& P) {
       << "    uint64_t cr[" << nw << "];  // fixed-sign vertices whose tree edge (both ends fixed) is crossed\n"
       << "    uint64_t dp[" << nd << "];  // duplicate phase-1 edges to fixed-sign neighbours\n";
     if (even) o << "    uint32_t fp, op;  // fixed-sign pairs left to each batch: joining two sets, marking one\n";
+    else o << "    uint64_t hx[" << std::max(1, nhk) << "];  // fixed-sign tree edges whose crossing a batch tests\n";
     o << "  };\n";
     o << "  __device__ __forceinline__ Flags flags(Cfg<" << d << ">::Mask m0, const uint8_t* snap) const {\n";
     o << "    Flags fl{};\n    const E::Ent* row = reinterpret_cast<const E::Ent*>(snap);\n";
@@ -434,6 +512,10 @@ std::string jit_source(const HostProgram& P) {
         o << "    fl.cr[" << v / 64 << "] |= (uint64_t)(" << sign_expr(P, v, "m0") << " ^ " << sign_expr(P, t, "m0")
           << ") << " << v % 64 << ";\n";
     }
+    if (!even)
+      for (int k = 0; k < nh32; ++k)
+        o << "    fl.hx[" << k / 2 << "] |= (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(reinterpret_cast<const "
+             "uint32_t*>(snap)[Cfg<" << d << ">::SNAP_HX + " << k << "]) << " << 32 * (k % 2) << ";\n";
     if (even)
       o << "    fl.fp = (uint32_t)__builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t*>(snap)[Cfg<" << d
         << ">::SNAP_KIND]);\n    fl.op = (uint32_t)__builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t*>(snap)[Cfg<"
@@ -451,6 +533,9 @@ std::string jit_source(const HostProgram& P) {
         << "] = uniform_mask(b); }\n";
     for (int k = 0; k < nd; ++k)
       o << "    { uint64_t a = fl_chunk.dp[" << k << "]; PW_OPAQUE(a); fl.dp[" << k << "] = uniform_mask(a); }\n";
+    if (!even)
+      for (int k = 0; k < std::max(1, nhk); ++k)
+        o << "    { uint64_t a = fl_chunk.hx[" << k << "]; PW_OPAQUE(a); fl.hx[" << k << "] = uniform_mask(a); }\n";
     if (even)
       o << "    { uint32_t a = fl_chunk.fp, b = fl_chunk.op; PW_OPAQUE(a); PW_OPAQUE(b); "
            "fl.fp = (uint32_t)__builtin_amdgcn_readfirstlane(a); fl.op = (uint32_t)__builtin_amdgcn_readfirstlane(b); }\n";

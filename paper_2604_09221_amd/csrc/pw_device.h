@@ -155,13 +155,19 @@ struct Cfg {
   // snapshot area of the sweep kernel: the entries of vertices 0 .. NV-1
   // (SNAP_WORDS words, copied word by word); for even d then the chunk's
   // bitset of the sets that varying vertices reach (TOUCH_WORDS words)
-  // and the antipodal pairs left to each batch (2 words); padded to 16
-  // bytes
+  // and the antipodal pairs left to each batch (2 words), for odd d the
+  // words below; padded to 16 bytes
   static constexpr int SNAP_WORDS = (NV * EB + 3) / 4;
   static constexpr int TOUCH_WORDS = EVEN ? (NV + 31) / 32 : 0;
   static constexpr int SNAP_TOUCH = SNAP_WORDS;
   static constexpr int SNAP_KIND = SNAP_TOUCH + TOUCH_WORDS;
-  static constexpr int SNAP_BYTES = ((EVEN ? SNAP_KIND + 2 : SNAP_WORDS) * 4 + 15) / 16 * 16;
+  // for odd d instead: the snapshot-root pair of each crossed tree edge
+  // between fixed-sign vertices (u16 keys, at most NV edges) and the bitset
+  // of the edges whose pair no earlier edge has (HIT_WORDS words)
+  static constexpr int HIT_WORDS = EVEN ? 0 : (NV + 31) / 32;
+  static constexpr int SNAP_HKEY = SNAP_WORDS;
+  static constexpr int SNAP_HX = SNAP_HKEY + (EVEN ? 0 : (2 * NV + 3) / 4);
+  static constexpr int SNAP_BYTES = ((EVEN ? SNAP_KIND + 2 : SNAP_HX + HIT_WORDS) * 4 + 15) / 16 * 16;
   static constexpr int WAVE_BYTES = LANE_WORDS * 4 * 64;
   // waves per block: as many waves per CU as the 160 KiB of LDS allows,
   // in blocks of 4 waves, or of 2 where that keeps more of them resident

@@ -382,14 +382,15 @@ def _chunks_across_range(rng, n_free, n_aligned, n_ragged, chunk=512):
     return out
 
 
-@pytest.mark.parametrize("d", [7, 6])
+@pytest.mark.parametrize("d", [7, 6, 9, 5])
 def test_d7_sweep_kernel_mid_range(pw, d):
     """The specialised sweep kernel (shared snapshot per 512 masks) on 256
     whole chunks spread over the 2^(nA - 1) indices and 64 ragged ranges:
     histogram counts and witnesses of every range against the oracle.  d = 7
     is the timed sweep; d = 6 (a varied triangulation) covers the even-degree
     reduction of the fixed-sign antipodal pairs with u8 entries that hold
-    the parity bit."""
+    the parity bit; d = 9 and 5 (varied) the other odd degrees with the
+    per-chunk reduction of the crossing tests."""
     E = I.standard_triangulation(d) if d == 7 else I.lift_triangulation(d, 5, noise=1.0)
     tri = pw.Triangulation(d, E).specialize()
     rng = np.random.default_rng(735 + d)

@@ -26,6 +26,7 @@ CSRC = os.path.join(os.path.dirname(HERE), "paper_2604_09221_amd", "csrc")
 
 MAIN = r'''
 Dim3E threadIdx{0, 0, 0}, blockIdx{0, 0, 0}, blockDim{64, 1, 1}, gridDim{1, 1, 1};
+#include <algorithm>
 #include <cstring>
 #include <vector>
 using C = pw::Cfg<DEG>;
@@ -98,6 +99,35 @@ int main(int argc, char** argv) {
         if (foreign_write(own, before, smem)) ++foreign;
       }
 #endif
+#ifdef SNAP_HITS
+    // odd d: the per-chunk reduction of the crossing tests of tree edges
+    // between fixed-sign vertices, stage by stage, lane by lane (shared
+    // snapshot words only)
+    for (int j = 0; j < 64; ++j) S::hits_1(srow, j, (uint64_t)m1);
+    for (int j = 0; j < 64; ++j) S::hits_2(srow, j);
+    if (memcmp(before_snap.data(), smem, kBytes) != 0) ++foreign;
+    {
+      // the kept edges, recomputed here: among the crossed tree edges
+      // (v, t) between fixed-sign vertices with v not a snapshot root, the
+      // first of each unordered pair of snapshot roots
+      const uint8_t* row = srow;
+      const uint32_t* hx = reinterpret_cast<const uint32_t*>(srow) + C::SNAP_HX;
+      std::vector<std::pair<int, int>> seen;
+      for (int e = 0; e < S::kNH; ++e) {
+        const uint32_t x = pw::kHitEdges[e];
+        const int v = (int)(x & 0xFF), t = (int)((x >> 8) & 0xFF);
+        const int sv = (int)(((uint64_t)m1 >> ((x >> 16) & 0x7F)) & 1), st = (int)(((uint64_t)m1 >> ((x >> 23) & 0x7F)) & 1);
+        const bool crossed = (sv ^ st ^ (int)(x >> 30)) != 0;
+        bool keep = false;
+        if (row[v] != v && crossed) {
+          const std::pair<int, int> key(std::min(row[v], row[t]), std::max(row[v], row[t]));
+          keep = std::find(seen.begin(), seen.end(), key) == seen.end();
+          if (keep) seen.push_back(key);
+        }
+        if (keep != (((hx[e / 32] >> (e % 32)) & 1u) != 0)) return 6;
+      }
+    }
+#endif
 #endif
     threadIdx.x = lane;
     const pw::Lane L = pw::lane_memory<DEG>(smem, C::LANE_WORDS);
@@ -124,7 +154,8 @@ def _compile(tmp_path, d, edges, snap):
     src = pw.jit_source(d, edges)
     src = src[:src.index('extern "C"')]          # the evaluators; the kernels need a GPU
     path = tmp_path / f"emu_d{d}.cpp"
-    defs = ("#define SNAP 1\n" if snap else "") + ("#define SNAP_PAIRS 1\n" if snap and d % 2 == 0 else "")
+    defs = ("#define SNAP 1\n" if snap else "") + ("#define SNAP_PAIRS 1\n" if snap and d % 2 == 0 else "") + \
+        ("#define SNAP_HITS 1\n" if snap and d % 2 == 1 else "")
     path.write_text(defs + '#include "host_shim.h"\n' + src + MAIN.replace("DEG", str(d)))
     exe = tmp_path / f"emu_d{d}"
     subprocess.check_call(["g++", "-O1", "-std=c++17", "-w", "-fsanitize=address,undefined",
@@ -168,6 +199,7 @@ def _check(tmp_path, d, edges, seed, n, snap):
         masks[i, 1] = x >> 64
     run = subprocess.run([str(exe), str(n)], input=masks.tobytes(), capture_output=True)
     assert run.returncode != 4, "a lane wrote outside its own LDS bytes"
+    assert run.returncode != 6, "the sweep kernel kept the wrong crossing tests of a chunk"
     assert run.returncode == 0, run.stderr.decode()[-2000:]
     got = np.frombuffer(run.stdout, dtype=np.uint64).reshape(n, 2)
     want = oracle.scheme_many(d, edges, masks, threads=4)
