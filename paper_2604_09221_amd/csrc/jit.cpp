@@ -12,8 +12,9 @@
 // left.  For sweeps with only sigma(0,0) fixed it also writes the sweep
 // evaluator JitSnap: a snapshot of the fixed-sign part shared by the wave
 // per chunk of 512 masks (built by label propagation over a per-triangulation
-// link table), wave-uniform flags derived from it, for even d the per-chunk
-// reduction of the antipodal pairs of fixed-sign vertices, and the
+// link table), wave-uniform flags derived from it, a per-chunk reduction of
+// what the fixed-sign part leaves to each batch (for even d its antipodal
+// pairs, for odd d the crossing tests of its tree edges), and the
 // per-batch work on the 9 varying lattice bits.
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
