@@ -903,8 +903,8 @@ def main():
                     help="skip the checks of whole passes (the generic kernel's reference sweep)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(sharding is one histogram merge; see the design notes).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(sharding the sweeps needs only a merge of the per-GPU histograms).", file=sys.stderr)
         sys.exit(2)
     if args.config == "gemm":
         import torch
