@@ -183,6 +183,34 @@ def test_d7_large_range_properties(pw):
     assert tri.errors() == 0
 
 
+@pytest.mark.parametrize("d", [5, 6])
+def test_whole_sweeps_specialised_equal_generic(pw, d):
+    """All 2^(nA - 1) masks of a varied triangulation (sigma(0,0) = +): the
+    specialised sweep kernel (shared snapshot, per-chunk reduction of the
+    crossing tests at odd d and of the antipodal pairs at even d) gives the
+    histogram of the generic kernel, counts and witnesses; the counts sum to
+    the sweep and are divisible by 4 (sigma -> sigma + b i + c j, (b, c) !=
+    (0, 0), keeps sigma(0,0) and the scheme and has no fixed point: a free
+    (Z/2)^2 action on a whole sweep); every witness's code is the oracle's."""
+    E = I.lift_triangulation(d, 4, noise=1.0)
+    total = 1 << (I.n_points(d) - 1)
+    spec = pw.Triangulation(d, E).specialize()
+    gen = pw.Triangulation(d, E)
+    h1, h2 = pw.Histogram(512), pw.Histogram(512)
+    spec.enumerate_range(0, total, h1)
+    gen.enumerate_range(0, total, h2)
+    a, b = h1.read(), h2.read()
+    assert a == b
+    assert sum(c for c, _ in a.values()) == total
+    assert all(c % 4 == 0 for c, _ in a.values())
+    wit = np.array([w for _, w in a.values()], dtype=np.uint64)
+    masks = np.zeros((len(wit), 2), dtype=np.uint64)
+    masks[:, 0] = wit << np.uint64(1)
+    want = oracle.scheme_many(d, E, masks)
+    assert [int(lo) | (int(hi) << 64) for lo, hi in want] == list(a.keys())
+    assert spec.errors() == 0 and gen.errors() == 0
+
+
 # ------------------------------------------------------------------ d = 8
 
 @pytest.mark.parametrize("name", ["bow_tie", "rank016", "rank015"])
